@@ -1,0 +1,145 @@
+/*
+ * fastbcc -- biconnected components on one MI355X (gfx950), C ABI.
+ *
+ * The problem (paper: Introduction and Preliminaries): given an undirected
+ * graph G = (V, E), partition E into biconnected components (BCCs) -- the
+ * classes of "e1 ~ e2 iff e1 = e2 or both lie on a common simple cycle" --
+ * and report the articulation points (vertices whose removal increases the
+ * number of connected components).
+ *
+ * The method is FAST-BCC (paper: Section "The FAST-BCC Algorithm",
+ * Algorithm 1): First-CC builds a spanning forest, Rooting roots it by an
+ * Euler tour and list ranking, Tagging computes first/last/low/high per
+ * vertex (low/high by range-min/max queries over preorder), Last-CC runs
+ * connectivity on the implicit skeleton (plain tree edges and cross edges;
+ * fence and back edges skipped), and every label gets its component head.
+ * All of it runs as hand-written HIP kernels; this header is the only way in.
+ *
+ * Graph format: symmetric CSR.  offsets[n+1] (int32 or int64), adj[num_arcs]
+ * (int32 vertex ids).  Every undirected edge u-w is stored as two arcs,
+ * u->w in row u and w->u in row w.  Parallel edges are allowed (they always
+ * share a BCC); self-loop arcs are allowed and get label -1.  Rows need not
+ * be sorted for the solve (FASTBCC_FLAG_VALIDATE requires sorted rows).
+ *
+ * Output conventions:
+ *   out_edge_label[a]  smallest arc index of the BCC that arc a belongs to
+ *                      (the "edge id" of an edge is the smaller of its two
+ *                      arc indices, so both arcs of an edge get the same
+ *                      value); -1 for a self-loop arc.
+ *   out_is_ap[v]       1 if v is an articulation point, else 0.
+ *   out_num_bcc[g]     number of BCCs (isolated vertices and self-loops form
+ *                      none).
+ *
+ * Memory: every pointer argument is DEVICE memory unless marked (host).
+ * All buffers -- inputs, outputs and the workspace -- are owned by the
+ * caller.  The solve allocates nothing, keeps no state between calls, and
+ * issues no host synchronisation (unless FASTBCC_FLAG_VALIDATE is set): it
+ * only enqueues kernels on `stream`, so it may be captured into a HIP graph.
+ * Calls on distinct workspaces may run concurrently on distinct streams.
+ *
+ * Limits: n < 2^30 vertices, num_arcs < 2^31 (labels are int32 arc ids).
+ */
+#ifndef FASTBCC_H
+#define FASTBCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define FASTBCC_API __attribute__((visibility("default")))
+#else
+#define FASTBCC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fastbcc_status {
+  FASTBCC_OK = 0,
+  FASTBCC_ERR_INVALID_ARGUMENT = 1,    /* null pointer, negative size, bad flag bits */
+  FASTBCC_ERR_TOO_LARGE = 2,           /* n >= 2^30 or num_arcs >= 2^31 */
+  FASTBCC_ERR_WORKSPACE_TOO_SMALL = 3, /* workspace_bytes < fastbcc_workspace_size() */
+  FASTBCC_ERR_HIP = 4,                 /* a HIP launch or API call failed */
+  FASTBCC_ERR_INVALID_GRAPH = 5        /* FASTBCC_FLAG_VALIDATE found a malformed CSR */
+} fastbcc_status;
+
+/* flags */
+#define FASTBCC_FLAG_VALIDATE 0x1u /* check the CSR on the device first, then
+                                      synchronise `stream` and return
+                                      FASTBCC_ERR_INVALID_GRAPH if it is not a
+                                      symmetric CSR with sorted rows and ids in
+                                      range; nothing else is launched then */
+/* Tuning fields (0 = built-in default).  They change speed, never results.
+ *   bits 8-11  log2 of the list-ranking ruler spacing, 3..10
+ *   bits 12-13 union-find sampling rounds before the full sweep, 0..3 (value 3 = none)
+ *   bits 14-16 log2 of 64-arc windows per wave tile, 2..6 */
+#define FASTBCC_TUNE_RULER_SHIFT 8
+#define FASTBCC_TUNE_SAMPLE_SHIFT 12
+#define FASTBCC_TUNE_TILE_SHIFT 14
+
+/*
+ * Workspace bytes needed for a graph with n vertices and num_arcs arcs split
+ * into num_graphs graphs (1 for a single graph).  O(n + num_arcs/256 +
+ * num_graphs); independent of flags.  `bytes` is host memory.
+ * The paper's space bound (Theorem on cost bounds: O(n) auxiliary space) is
+ * kept: nothing in the workspace grows with the number of arcs except one
+ * int32 per 256 arcs of tile bookkeeping.
+ */
+FASTBCC_API fastbcc_status fastbcc_workspace_size(int64_t n, int64_t num_arcs, int32_t num_graphs, size_t* bytes);
+
+/*
+ * Solve one graph (Algorithm 1 of the paper plus the edge-label and
+ * articulation-point read-out).  offsets: int32[n+1]; adj: int32[num_arcs];
+ * out_edge_label: int32[num_arcs]; out_is_ap: uint8[n] (may be null);
+ * out_num_bcc: int64[1] (may be null); workspace: >= fastbcc_workspace_size
+ * bytes, 256-byte aligned; stream: a hipStream_t (null = default stream).
+ * Asynchronous: returns after enqueueing.  Inputs must stay valid and
+ * unmodified until the work on `stream` completes.
+ */
+FASTBCC_API fastbcc_status fastbcc_solve(int64_t n, int64_t num_arcs, const int32_t* offsets, const int32_t* adj,
+                             int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
+                             void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
+
+/* As fastbcc_solve, with int64 offsets (graphs whose arc count needs them
+ * in memory layout; num_arcs must still be < 2^31). */
+FASTBCC_API fastbcc_status fastbcc_solve_off64(int64_t n, int64_t num_arcs, const int64_t* offsets, const int32_t* adj,
+                                   int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
+                                   void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
+
+/*
+ * Solve many independent graphs in one launch sequence.  The graphs are
+ * concatenated into one CSR: graph g owns vertices [graph_vbegin[g],
+ * graph_vbegin[g+1]) and arcs [offsets[graph_vbegin[g]], offsets[graph_vbegin[g+1]]),
+ * and its arcs hold GLOBAL vertex ids that stay inside its own range.
+ * graph_vbegin: int32[num_graphs+1] on the device, graph_vbegin[0] = 0,
+ * graph_vbegin[num_graphs] = n_total, nondecreasing.
+ * Results are graph-local: out_edge_label[a] is the label graph g would get
+ * if solved alone (its arc indices counted from offsets[graph_vbegin[g]]);
+ * out_num_bcc: int64[num_graphs].  A BCC never spans two graphs (the paper
+ * processes the connected components of a disconnected input in parallel),
+ * so the union is solved as one graph and only the read-out is per graph.
+ */
+FASTBCC_API fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32_t* graph_vbegin, int64_t n_total,
+                                     int64_t num_arcs, const int32_t* offsets, const int32_t* adj,
+                                     int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
+                                     void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
+
+/*
+ * Synchronise `stream` and copy the device status word kept in `workspace`
+ * (0 = fine; otherwise a fastbcc_status written by a device-side check) to
+ * *out_status (host).
+ */
+FASTBCC_API fastbcc_status fastbcc_read_device_status(const void* workspace, void* stream, int32_t* out_status);
+
+/* Static string for a status code. */
+FASTBCC_API const char* fastbcc_status_string(fastbcc_status status);
+
+/* Library version as "major.minor.patch" (static string). */
+FASTBCC_API const char* fastbcc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTBCC_H */

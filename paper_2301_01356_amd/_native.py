@@ -1,0 +1,100 @@
+"""ctypes binding of ``libfastbcc.so`` (the C ABI in ``include/fastbcc.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+the library.  If the library is missing the import fails loudly; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfastbcc.so")
+
+# status codes (fastbcc_status)
+OK = 0
+ERR_INVALID_ARGUMENT = 1
+ERR_TOO_LARGE = 2
+ERR_WORKSPACE_TOO_SMALL = 3
+ERR_HIP = 4
+ERR_INVALID_GRAPH = 5
+
+FLAG_VALIDATE = 0x1
+TUNE_RULER_SHIFT = 8
+TUNE_SAMPLE_SHIFT = 12
+TUNE_TILE_SHIFT = 14
+
+EXPORTED = (
+    "fastbcc_workspace_size",
+    "fastbcc_solve",
+    "fastbcc_solve_off64",
+    "fastbcc_solve_batched",
+    "fastbcc_read_device_status",
+    "fastbcc_status_string",
+    "fastbcc_version",
+)
+
+
+class FastBccError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().fastbcc_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2301_01356_amd.build` "
+            "(there is no non-HIP fallback)"
+        )
+    h = ctypes.CDLL(LIB_PATH)
+    i64, i32, u32, vp, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
+    st = ctypes.c_int
+    h.fastbcc_workspace_size.restype = st
+    h.fastbcc_workspace_size.argtypes = [i64, i64, i32, ctypes.POINTER(sz)]
+    solve_args = [i64, i64, vp, vp, vp, vp, vp, vp, sz, u32, vp]
+    h.fastbcc_solve.restype = st
+    h.fastbcc_solve.argtypes = solve_args
+    h.fastbcc_solve_off64.restype = st
+    h.fastbcc_solve_off64.argtypes = solve_args
+    h.fastbcc_solve_batched.restype = st
+    h.fastbcc_solve_batched.argtypes = [i32, vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, u32, vp]
+    h.fastbcc_read_device_status.restype = st
+    h.fastbcc_read_device_status.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    h.fastbcc_status_string.restype = ctypes.c_char_p
+    h.fastbcc_status_string.argtypes = [st]
+    h.fastbcc_version.restype = ctypes.c_char_p
+    h.fastbcc_version.argtypes = []
+    _lib = h
+    return h
+
+
+def check(status: int, what: str = "") -> None:
+    if status != OK:
+        raise FastBccError(status, what)
+
+
+def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib().fastbcc_workspace_size(int(n), int(num_arcs), int(num_graphs), ctypes.byref(out)), "workspace_size")
+    return int(out.value)
+
+
+def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0) -> int:
+    """Encode tuning fields (0/None = library default)."""
+    f = 0
+    if ruler_shift:
+        f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT
+    if sample_rounds is not None:
+        f |= (3 if sample_rounds == 0 else sample_rounds) << TUNE_SAMPLE_SHIFT
+    if tile_shift:
+        f |= (tile_shift & 0x7) << TUNE_TILE_SHIFT
+    return f

@@ -1,0 +1,167 @@
+"""Torch-facing wrappers over the C ABI (marshalling only).
+
+PyTorch provides device memory and streams; every step of the solve runs in
+the HIP kernels of ``libfastbcc.so``.  Names follow the C ABI:
+
+* ``workspace_size(n, num_arcs, num_graphs=1)``
+* ``solve(offsets, adj, ...)``          -- one graph, int32 or int64 offsets
+* ``solve_batched(vbegin, offsets, adj, ...)`` -- many graphs, one launch sequence
+* ``read_device_status(workspace)``
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _native as N
+
+
+@dataclass
+class BccResult:
+    edge_label: torch.Tensor  # int32 [num_arcs]: smallest arc id of the arc's BCC, -1 for self-loops
+    is_ap: torch.Tensor  # uint8 [n]: articulation-point flags
+    num_bcc: torch.Tensor  # int64 [num_graphs]
+
+
+def _dev_ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _check_tensor(t: torch.Tensor, name: str, dtypes, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a GPU (got {t.device})")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
+    return N.workspace_size(n, num_arcs, num_graphs)
+
+
+def alloc_workspace(n: int, num_arcs: int, num_graphs: int = 1, device=None) -> torch.Tensor:
+    """Caller-owned workspace (torch allocation, 256-byte aligned)."""
+    nbytes = workspace_size(n, num_arcs, num_graphs)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def solve(
+    offsets: torch.Tensor,
+    adj: torch.Tensor,
+    *,
+    out: Optional[BccResult] = None,
+    workspace: Optional[torch.Tensor] = None,
+    flags: int = 0,
+    stream=None,
+) -> BccResult:
+    """BCCs of one graph given as symmetric CSR on the GPU (asynchronous on ``stream``)."""
+    _check_tensor(offsets, "offsets", (torch.int32, torch.int64))
+    n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets needs n + 1 >= 1 entries")
+    _check_tensor(adj, "adj", (torch.int32,))
+    A = adj.numel()
+    dev = offsets.device
+    if adj.device != dev:
+        raise ValueError("offsets and adj must be on the same device")
+    if out is None:
+        out = BccResult(
+            torch.empty(A, dtype=torch.int32, device=dev),
+            torch.empty(n, dtype=torch.uint8, device=dev),
+            torch.empty(1, dtype=torch.int64, device=dev),
+        )
+    _check_tensor(out.edge_label, "edge_label", (torch.int32,), A)
+    _check_tensor(out.is_ap, "is_ap", (torch.uint8,), n)
+    _check_tensor(out.num_bcc, "num_bcc", (torch.int64,), 1)
+    if workspace is None:
+        workspace = alloc_workspace(n, A, 1, dev)
+    fn = N.lib().fastbcc_solve if offsets.dtype == torch.int32 else N.lib().fastbcc_solve_off64
+    with torch.cuda.device(dev):
+        st = fn(
+            n,
+            A,
+            offsets.data_ptr(),
+            _dev_ptr(adj) if A else None,
+            _dev_ptr(out.edge_label) if A else None,
+            _dev_ptr(out.is_ap) if n else None,
+            out.num_bcc.data_ptr(),
+            workspace.data_ptr(),
+            workspace.numel(),
+            flags,
+            _stream_handle(stream),
+        )
+    N.check(st, "fastbcc_solve")
+    return out
+
+
+def solve_batched(
+    vbegin: torch.Tensor,
+    offsets: torch.Tensor,
+    adj: torch.Tensor,
+    *,
+    out: Optional[BccResult] = None,
+    workspace: Optional[torch.Tensor] = None,
+    flags: int = 0,
+    stream=None,
+) -> BccResult:
+    """BCCs of many graphs concatenated as one CSR (graph g owns vertices
+    vbegin[g]..vbegin[g+1]); labels are graph-local, num_bcc is per graph."""
+    _check_tensor(vbegin, "vbegin", (torch.int32,))
+    _check_tensor(offsets, "offsets", (torch.int32,))
+    _check_tensor(adj, "adj", (torch.int32,))
+    G = vbegin.numel() - 1
+    if G < 1:
+        raise ValueError("vbegin needs at least 2 entries")
+    n = offsets.numel() - 1
+    A = adj.numel()
+    dev = offsets.device
+    if out is None:
+        out = BccResult(
+            torch.empty(A, dtype=torch.int32, device=dev),
+            torch.empty(n, dtype=torch.uint8, device=dev),
+            torch.empty(G, dtype=torch.int64, device=dev),
+        )
+    _check_tensor(out.edge_label, "edge_label", (torch.int32,), A)
+    _check_tensor(out.is_ap, "is_ap", (torch.uint8,), n)
+    _check_tensor(out.num_bcc, "num_bcc", (torch.int64,), G)
+    if workspace is None:
+        workspace = alloc_workspace(n, A, G, dev)
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_solve_batched(
+            G,
+            vbegin.data_ptr(),
+            n,
+            A,
+            offsets.data_ptr(),
+            _dev_ptr(adj) if A else None,
+            _dev_ptr(out.edge_label) if A else None,
+            _dev_ptr(out.is_ap) if n else None,
+            out.num_bcc.data_ptr(),
+            workspace.data_ptr(),
+            workspace.numel(),
+            flags,
+            _stream_handle(stream),
+        )
+    N.check(st, "fastbcc_solve_batched")
+    return out
+
+
+def read_device_status(workspace: torch.Tensor, stream=None) -> int:
+    import ctypes
+
+    out = ctypes.c_int32(0)
+    N.check(N.lib().fastbcc_read_device_status(workspace.data_ptr(), _stream_handle(stream), ctypes.byref(out)))
+    return int(out.value)

@@ -25,6 +25,7 @@ HIP_FLAGS = [
     "-std=c++17",
     "-shared",
     "-fPIC",
+    "-fvisibility=hidden",
     "-Wall",
     "-Wno-unused-function",
     # packed fp32 ops are kept out of every code object built here

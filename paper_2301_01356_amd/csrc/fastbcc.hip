@@ -1,0 +1,1065 @@
+// FAST-BCC on gfx950: phase kernels and the C ABI declared in fastbcc.h.
+//
+// Pipeline (paper: Algorithm 1 and Section "Algorithmic Details"; the
+// GPU-specific readings are listed in the design notes):
+//
+//   First-CC   union-find over all arcs, the hooking edge of every hooked root
+//              kept as a spanning-forest edge; a few sampling rounds first,
+//              then the full sweep skips rows already in the largest set.
+//   Rooting    tree arcs grouped by source (count, scan, scatter) with twin
+//              indices; Euler circuit by "arc u->v continues with the arc
+//              after v->u in v's row" (paper: "Euler Tour Technique");
+//              all trees' tours plus one entry node per tree root are chained
+//              into ONE list in root order, so list ranking yields global
+//              positions directly; ruling-set list ranking (rulers at every
+//              K-th node index, each walks to the next ruler) and pointer
+//              jumping over the rulers.
+//   Tagging    down arcs (rank(u->v) < rank(v->u)) give parent and preorder
+//              number first[v] = #entries before (scan of entry flags);
+//              last[v] = first[v] + |T_v| - 1; w1/w2 = min/max of first over
+//              v and its neighbours (one arc-balanced sweep); low/high by
+//              range min/max over the preorder interval (blocked sparse
+//              table); fence bit per vertex.
+//   Last-CC    union-find on the skeleton: plain tree edges linked per
+//              vertex, non-tree arcs kept iff neither endpoint is an ancestor
+//              of the other (cross edges); fence and back edges skipped.
+//   Read-out   head(l[u]) = p(u) where l[u] != l[p(u)]; articulation points;
+//              canonical label per BCC = its smallest arc (found in the row
+//              of the BCC's smallest vertex); arc label = canonical label of
+//              the deeper endpoint's vertex label.
+//
+// Every kernel is enqueued on the caller's stream; data-dependent sizes
+// (number of trees, tree arcs, rulers) stay in device memory and grids are
+// sized by upper bounds, so a solve needs no host synchronisation.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "fastbcc.h"
+#include "prims.hpp"
+
+using namespace fastbcc;
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int MODE_SAMPLES = 1024;
+constexpr int MIN_RULER_SHIFT = 3;
+constexpr int MAX_RULER_SHIFT = 10;
+constexpr int DEF_RULER_SHIFT = 5;
+constexpr int DEF_SAMPLE_ROUNDS = 2;
+constexpr int MIN_TILE_ARCS = 256;  // workspace is sized for this tile size
+constexpr int DEF_TILE_SHIFT = 2;   // 4 windows of 64 arcs
+constexpr int MAX_TILE_SHIFT = 6;
+
+// scalar slots at the head of the workspace
+enum Scalar : int {
+  S_STATUS = 0,
+  S_BIG_CC = 1,
+  S_BIG_LAB = 2,
+  S_COUNT = 64,
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int ilog2_floor(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << (l + 1)) <= x) ++l;
+  return l;
+}
+
+// ------------------------------------------------------------ workspace
+struct Layout {
+  size_t total = 0;
+  size_t scalars, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
+      rval1, rnx0, rnx1, pos, eflag, first, last, par, w1, w2, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax,
+      rec, lab, head, rootlab, minid, cand, fc, tile_row, scan_tmp;
+  int64_t nb = 0;      // rmq blocks of 64
+  int levels = 0;      // sparse-table levels
+  int64_t rmax = 0;    // ruler capacity
+  int64_t tiles = 0;   // tile capacity
+  int64_t scan_blocks = 0;
+};
+
+inline size_t take(size_t& cur, size_t bytes) {
+  size_t at = cur;
+  cur += (bytes + 255) & ~size_t(255);
+  return at;
+}
+
+Layout make_layout(int64_t n, int64_t A) {
+  Layout L;
+  size_t c = 0;
+  const int64_t n1 = n + 1, n2 = 2 * n + 1;
+  L.nb = cdiv(n > 0 ? n : 1, 64);
+  L.levels = ilog2_floor(L.nb) + 1;
+  L.rmax = cdiv(n2, int64_t(1) << MIN_RULER_SHIFT) + 1;
+  L.tiles = cdiv(A > 0 ? A : 1, MIN_TILE_ARCS) + 1;
+  L.scan_blocks = cdiv(n2, SCAN_TILE) + 1;
+  const size_t I = sizeof(int);
+  L.scalars = take(c, S_COUNT * I);
+  L.cc = take(c, n * I);
+  L.hu = take(c, n * I);
+  L.hv = take(c, n * I);
+  L.toff = take(c, n1 * I);
+  L.su = take(c, n * I);
+  L.sv = take(c, n * I);
+  L.tadj = take(c, n2 * I);
+  L.twin = take(c, n2 * I);
+  L.rootidx = take(c, n1 * I);
+  L.roots = take(c, n * I);
+  L.next = take(c, n2 * I);
+  L.ol = take(c, n2 * 2 * I);
+  L.rlen = take(c, L.rmax * I);
+  L.rnext = take(c, L.rmax * I);
+  L.rval0 = take(c, L.rmax * I);
+  L.rval1 = take(c, L.rmax * I);
+  L.rnx0 = take(c, L.rmax * I);
+  L.rnx1 = take(c, L.rmax * I);
+  L.pos = take(c, n2 * I);
+  L.eflag = take(c, n2 * I);
+  L.first = take(c, n * I);
+  L.last = take(c, n * I);
+  L.par = take(c, n * I);
+  L.w1 = take(c, n * I);
+  L.w2 = take(c, n * I);
+  L.W1 = take(c, n * I);
+  L.W2 = take(c, n * I);
+  L.pre1 = take(c, n * I);
+  L.suf1 = take(c, n * I);
+  L.pre2 = take(c, n * I);
+  L.suf2 = take(c, n * I);
+  L.tmin = take(c, (size_t)L.levels * L.nb * I);
+  L.tmax = take(c, (size_t)L.levels * L.nb * I);
+  L.rec = take(c, n * sizeof(int4));
+  L.lab = take(c, n * I);
+  L.head = take(c, n * I);
+  L.rootlab = take(c, n * I);
+  L.minid = take(c, n * I);
+  L.cand = take(c, n);
+  L.fc = take(c, n * sizeof(int2));
+  L.tile_row = take(c, L.tiles * I);
+  L.scan_tmp = take(c, L.scan_blocks * I);
+  L.total = c;
+  return L;
+}
+
+struct Tune {
+  int ruler_shift = DEF_RULER_SHIFT;
+  int sample_rounds = DEF_SAMPLE_ROUNDS;
+  int tile_windows = 1 << DEF_TILE_SHIFT;
+};
+
+bool decode_flags(uint32_t flags, Tune& t) {
+  const uint32_t known = FASTBCC_FLAG_VALIDATE | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
+                         (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT);
+  if (flags & ~known) return false;
+  uint32_t r = (flags >> FASTBCC_TUNE_RULER_SHIFT) & 0xF;
+  uint32_t s = (flags >> FASTBCC_TUNE_SAMPLE_SHIFT) & 0x3;
+  uint32_t w = (flags >> FASTBCC_TUNE_TILE_SHIFT) & 0x7;
+  if (r) {
+    if (r < MIN_RULER_SHIFT || r > MAX_RULER_SHIFT) return false;
+    t.ruler_shift = (int)r;
+  }
+  if (s) t.sample_rounds = (s == 3) ? 0 : (int)s;
+  if (w) {
+    if (w < 2 || w > MAX_TILE_SHIFT) return false;
+    t.tile_windows = 1 << w;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void k_fill_i32(int* p, int v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename OffT>
+__global__ void k_tile_rows(const OffT* __restrict__ off, int n, int64_t A, int64_t tile_arcs, int64_t ntiles,
+                            int* __restrict__ tile_row) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int64_t a = t * tile_arcs;
+  int lo = 0, hi = n;  // off[lo] <= a < off[hi]
+  while (hi - lo > 1) {
+    int mid = lo + (hi - lo) / 2;
+    if ((int64_t)off[mid] <= a) lo = mid;
+    else hi = mid;
+  }
+  tile_row[t] = lo;
+}
+
+// Most frequent value of p[] over a stratified sample of vertices (one block).
+__global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(const int* __restrict__ p, int n, int* out) {
+  __shared__ int s[MODE_SAMPLES];
+  __shared__ int best_len[MODE_SAMPLES / WAVE];
+  __shared__ int best_val[MODE_SAMPLES / WAVE];
+  const int i = threadIdx.x;
+  int64_t stride = n / MODE_SAMPLES;
+  if (stride < 1) stride = 1;
+  uint32_t h = (uint32_t)i * 2654435761u + 0x9e3779b9u;
+  h ^= h >> 15;
+  h *= 0x2c1b3c6du;
+  h ^= h >> 12;
+  int64_t v = ((int64_t)i * stride + (int64_t)(h % (uint32_t)stride)) % n;
+  s[i] = p[v];
+  __syncthreads();
+  // bitonic sort of MODE_SAMPLES values
+  for (int k = 2; k <= MODE_SAMPLES; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      int ix = i ^ j;
+      if (ix > i) {
+        int a = s[i], b = s[ix];
+        bool up = (i & k) == 0;
+        if ((a > b) == up) {
+          s[i] = b;
+          s[ix] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int len = 0, val = s[i];
+  if (i == 0 || s[i - 1] != val) {
+    int j = i;
+    while (j < MODE_SAMPLES && s[j] == val) ++j;
+    len = j - i;
+  }
+  // block argmax of (len, val)
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int l2 = __shfl_down(len, o, WAVE), v2 = __shfl_down(val, o, WAVE);
+    if (l2 > len) {
+      len = l2;
+      val = v2;
+    }
+  }
+  if (lane_id() == 0) {
+    best_len[i / WAVE] = len;
+    best_val[i / WAVE] = val;
+  }
+  __syncthreads();
+  if (i == 0) {
+    int bl = -1, bv = 0;
+    for (int w = 0; w < MODE_SAMPLES / WAVE; ++w)
+      if (best_len[w] > bl) {
+        bl = best_len[w];
+        bv = best_val[w];
+      }
+    out[0] = bv;
+  }
+}
+
+__global__ void k_compress(int* p, int n) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int r = uf_find(p, v);
+  if (ld_relaxed(p + v) != r) st_relaxed(p + v, r);
+}
+
+// ------------------------------------------------------------ validation
+template <typename OffT>
+__global__ void k_validate_rows(const OffT* __restrict__ off, int n, int64_t A, int* status) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  bool bad = false;
+  if (v == 0 && off[0] != 0) bad = true;
+  if (v == n && (int64_t)off[n] != A) bad = true;
+  if (v < n && off[v] > off[v + 1]) bad = true;
+  if (bad) atomicExch(status, (int)FASTBCC_ERR_INVALID_GRAPH);
+}
+
+template <typename OffT>
+__global__ void k_validate_arcs(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                                const int* __restrict__ tile_row, int tw, int* status) {
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    if (!ok) return;
+    const int y = adj[a];
+    bool bad = (y < 0 || y >= n);
+    if (!bad && a > (int64_t)off[x] && adj[a - 1] > y) bad = true;  // rows sorted
+    if (!bad) {
+      // x must occur in row y (binary search; rows sorted)
+      int64_t lo = off[y], hi = off[y + 1];
+      while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (adj[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo >= (int64_t)off[y + 1] || adj[lo] != x) bad = true;
+    }
+    if (bad) atomicExch(status, (int)FASTBCC_ERR_INVALID_GRAPH);
+  });
+}
+
+// ------------------------------------------------------------ First-CC
+__global__ void k_cc_init(int* __restrict__ cc, int* __restrict__ hu, int n) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  cc[v] = v;
+  hu[v] = -1;
+}
+
+// Sampling round r: every vertex links to its r-th neighbour.
+template <typename OffT>
+__global__ void k_cc_sample(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
+                            int* hu, int* hv) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t b = off[v], e = off[v + 1];
+  if (e - b > r) {
+    int w = adj[b + r];
+    if (w != v) uf_link_record(cc, v, w, hu, hv);
+  }
+}
+
+// Full sweep: rows whose set is the sampled largest one are skipped (every
+// edge they share with another set is seen from that set's side).
+template <typename OffT>
+__global__ void k_cc_sweep(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                           const int* __restrict__ tile_row, int tw, int rounds, int* cc, int* hu, int* hv,
+                           const int* __restrict__ scal) {
+  const int big = scal[S_BIG_CC];
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    if (!ok) return;
+    if (ld_relaxed(cc + x) == big) return;
+    if (a - (int64_t)off[x] < rounds) return;
+    const int w = adj[a];
+    if (w != x) uf_link_record(cc, x, w, hu, hv);
+  });
+}
+
+// ------------------------------------------------------------ Rooting
+// Tree degree counts; the slot each forest edge takes in both rows.
+__global__ void k_tree_count(const int* __restrict__ hu, const int* __restrict__ hv, int n, int* toff,
+                             int* __restrict__ su, int* __restrict__ sv) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n) return;
+  int u = hu[h];
+  if (u < 0) return;
+  int v = hv[h];
+  su[h] = atomicAdd(toff + u, 1);
+  sv[h] = atomicAdd(toff + v, 1);
+}
+
+__global__ void k_tree_fill(const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ su,
+                            const int* __restrict__ sv, const int* __restrict__ toff, int n, int* __restrict__ tadj,
+                            int* __restrict__ twin) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n) return;
+  int u = hu[h];
+  if (u < 0) return;
+  int v = hv[h];
+  int pu = toff[u] + su[h], pv = toff[v] + sv[h];
+  tadj[pu] = v;
+  tadj[pv] = u;
+  twin[pu] = pv;
+  twin[pv] = pu;
+}
+
+__global__ void k_root_flags(const int* __restrict__ cc, int n, int* __restrict__ rootidx) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  rootidx[v] = cc[v] == v ? 1 : 0;
+}
+
+__global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ rootidx, int n,
+                            int* __restrict__ roots) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (cc[v] == v) roots[rootidx[v]] = v;
+}
+
+// List nodes: [0, C) one entry node per tree root (root order), then
+// C + [0, 2T) the tree arcs.  The chain runs entry_0, tour_0, entry_1, ...
+__global__ void k_euler_next(const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
+                             const int* __restrict__ cc, const int* __restrict__ rootidx,
+                             const int* __restrict__ roots, int n, int* __restrict__ next) {
+  const int C = rootidx[n], T2 = toff[n], NL = C + T2;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NL) return;
+  if (i < C) {
+    int r = roots[i];
+    next[i] = toff[r + 1] > toff[r] ? C + toff[r] : (i + 1 < C ? i + 1 : -1);
+    return;
+  }
+  const int a = i - C;
+  const int v = tadj[a];
+  int nx = twin[a] + 1;
+  if (nx == toff[v + 1]) {
+    nx = toff[v];
+    if (cc[v] == v) {  // closes the tour of v's tree: continue with the next tree
+      int k = rootidx[v] + 1;
+      next[i] = k < C ? k : -1;
+      return;
+    }
+  }
+  next[i] = C + nx;
+}
+
+__global__ void k_node_count(const int* __restrict__ rootidx, const int* __restrict__ toff, int n, int* out) {
+  *out = rootidx[n] + toff[n];
+}
+
+// Each ruler (node index multiple of K) walks to the next ruler.
+__global__ void k_lr_walk(const int* __restrict__ next, const int* __restrict__ rootidx,
+                          const int* __restrict__ toff, int n, int shift, int2* __restrict__ ol,
+                          int* __restrict__ rnext, int* __restrict__ rlen) {
+  const int NL = rootidx[n] + toff[n];
+  const int R = (NL + (1 << shift) - 1) >> shift;
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int mask = (1 << shift) - 1;
+  int i = r << shift, cnt = 0, nr = -1;
+  for (int steps = 0; steps < NL; ++steps) {
+    ol[i] = make_int2(r, cnt++);
+    int j = next[i];
+    if (j < 0) break;
+    if ((j & mask) == 0) {
+      nr = j >> shift;
+      break;
+    }
+    i = j;
+  }
+  rnext[r] = nr;
+  rlen[r] = cnt;
+}
+
+// One pointer-jumping round over rulers: suffix sums of segment lengths.
+__global__ void k_lr_jump(const int* __restrict__ rootidx, const int* __restrict__ toff, int n, int shift,
+                          const int* __restrict__ vin, const int* __restrict__ nin, int* __restrict__ vout,
+                          int* __restrict__ nout) {
+  const int NL = rootidx[n] + toff[n];
+  const int R = (NL + (1 << shift) - 1) >> shift;
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  int nx = nin[r];
+  if (nx >= 0) {
+    vout[r] = vin[r] + vin[nx];
+    nout[r] = nin[nx];
+  } else {
+    vout[r] = vin[r];
+    nout[r] = -1;
+  }
+}
+
+// Global position of every node, then its entry flag scattered by position.
+__global__ void k_lr_pos(const int* __restrict__ rootidx, const int* __restrict__ toff, const int* __restrict__ twin,
+                         int n, const int2* __restrict__ ol, const int* __restrict__ suf, int* __restrict__ pos) {
+  const int NL = rootidx[n] + toff[n];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NL) return;
+  int2 o = ol[i];
+  pos[i] = NL - suf[o.x] + o.y;
+}
+
+__global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __restrict__ toff,
+                              const int* __restrict__ twin, int n, const int* __restrict__ pos,
+                              int* __restrict__ eflag, int* status) {
+  const int C = rootidx[n], NL = C + toff[n];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NL) return;
+  int f = 1;
+  if (i >= C) f = pos[i] < pos[C + twin[i - C]] ? 1 : 0;
+  const int p = pos[i];
+  if (p < 0 || p >= NL) {
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    return;
+  }
+  eflag[p] = f;
+}
+
+// first/last/parent from the ranked tour; w1 = w2 = first as the start value.
+__global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ roots,
+                       const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
+                       int n, const int* __restrict__ pos, const int* __restrict__ escan, int* __restrict__ first,
+                       int* __restrict__ last, int* __restrict__ par, int* __restrict__ w1, int* __restrict__ w2,
+                       int* status) {
+  const int C = rootidx[n], NL = C + toff[n];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NL) return;
+  int v, f, l, p;
+  if (i < C) {
+    v = roots[i];
+    f = escan[pos[i]];
+    int nf = (i + 1 < C) ? escan[pos[i + 1]] : n;
+    l = nf - 1;
+    p = -1;
+  } else {
+    const int a = i - C, ta = twin[a], tw = C + ta;
+    const int pi = pos[i], pt = pos[tw];
+    if (pi > pt) return;  // up arc
+    v = tadj[a];
+    p = tadj[ta];
+    f = escan[pi];
+    l = f + (pt - pi - 1) / 2;
+  }
+  if (v < 0 || v >= n) {
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    return;
+  }
+  first[v] = f;
+  last[v] = l;
+  par[v] = p;
+  w1[v] = f;
+  w2[v] = f;
+}
+
+// ------------------------------------------------------------ Tagging
+// w1[x] = min, w2[x] = max of first[] over x and all its neighbours.  Using
+// every neighbour instead of non-tree ones only adds first[p(x)] and values
+// inside T_x; neither changes any fence decision.
+template <typename OffT>
+__global__ void k_tag_sweep(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                            const int* __restrict__ tile_row, int tw, const int* __restrict__ first,
+                            int* __restrict__ w1, int* __restrict__ w2) {
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    int mn = INT32_MAX, mx = INT32_MIN;
+    const int key = ok ? x : -1;
+    if (ok) {
+      const int y = adj[a];
+      if (y != x) {
+        mn = mx = first[y];
+      }
+    }
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      int k2 = __shfl_up(key, o, WAVE);
+      int m2 = __shfl_up(mn, o, WAVE);
+      int x2 = __shfl_up(mx, o, WAVE);
+      if (lane >= o && k2 == key) {
+        mn = m2 < mn ? m2 : mn;
+        mx = x2 > mx ? x2 : mx;
+      }
+    }
+    const int knext = __shfl_down(key, 1, WAVE);
+    const bool tail = (lane == WAVE - 1) || knext != key;
+    if (tail && key >= 0 && mn != INT32_MAX) {
+      atomicMin(w1 + key, mn);
+      atomicMax(w2 + key, mx);
+    }
+  });
+}
+
+__global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restrict__ w1, const int* __restrict__ w2,
+                              int n, int* __restrict__ W1, int* __restrict__ W2, int* status) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int f = first[v];
+  if (f < 0 || f >= n) {  // preorder numbers must be a permutation of [0, n)
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    return;
+  }
+  W1[f] = w1[v];
+  W2[f] = w2[v];
+}
+
+// In-block prefix/suffix min and max (block = 64 consecutive preorder slots
+// = one wave), block minima/maxima into sparse-table level 0.
+__global__ void k_rmq_block(const int* __restrict__ W1, const int* __restrict__ W2, int n, int64_t nb,
+                            int* __restrict__ pre1, int* __restrict__ suf1, int* __restrict__ pre2,
+                            int* __restrict__ suf2, int* __restrict__ tmin, int* __restrict__ tmax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = lane_id();
+  const bool in = i < n;
+  const int a = in ? W1[i] : INT32_MAX;
+  const int b = in ? W2[i] : INT32_MIN;
+  int pa = a, pb = b, sa = a, sb = b;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int ta = __shfl_up(pa, o, WAVE), tb = __shfl_up(pb, o, WAVE);
+    int ua = __shfl_down(sa, o, WAVE), ub = __shfl_down(sb, o, WAVE);
+    if (lane >= o) {
+      pa = ta < pa ? ta : pa;
+      pb = tb > pb ? tb : pb;
+    }
+    if (lane + o < WAVE) {
+      sa = ua < sa ? ua : sa;
+      sb = ub > sb ? ub : sb;
+    }
+  }
+  if (in) {
+    pre1[i] = pa;
+    suf1[i] = sa;
+    pre2[i] = pb;
+    suf2[i] = sb;
+  }
+  const int64_t blk = i / WAVE;
+  if (lane == 0 && blk < nb) {
+    tmin[blk] = sa;
+    tmax[blk] = sb;
+  }
+}
+
+__global__ void k_rmq_level(int* __restrict__ tmin, int* __restrict__ tmax, int64_t nb, int j) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t h = int64_t(1) << (j - 1);
+  const int* pm = tmin + (size_t)(j - 1) * nb;
+  const int* px = tmax + (size_t)(j - 1) * nb;
+  int m = pm[b], x = px[b];
+  if (b + h < nb) {
+    int m2 = pm[b + h], x2 = px[b + h];
+    m = m2 < m ? m2 : m;
+    x = x2 > x ? x2 : x;
+  }
+  tmin[(size_t)j * nb + b] = m;
+  tmax[(size_t)j * nb + b] = x;
+}
+
+// low/high over [first, last]; fence(p(v), v) = first[p] <= low[v] and
+// last[p] >= high[v] (paper: Algorithm 1, function Fence).
+__global__ void k_rmq_query(const int* __restrict__ first, const int* __restrict__ last, const int* __restrict__ par,
+                            int n, int64_t nb, const int* __restrict__ W1, const int* __restrict__ W2,
+                            const int* __restrict__ pre1, const int* __restrict__ suf1, const int* __restrict__ pre2,
+                            const int* __restrict__ suf2, const int* __restrict__ tmin, const int* __restrict__ tmax,
+                            int4* __restrict__ rec, int* status) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int l = first[v], r = last[v];
+  if (l < 0 || r < l || r >= n) {
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    rec[v] = make_int4(0, n - 1, -1, 0);
+    return;
+  }
+  const int bl = l / WAVE, br = r / WAVE;
+  int lo, hi;
+  if (bl == br) {
+    lo = INT32_MAX;
+    hi = INT32_MIN;
+    for (int k = l; k <= r; ++k) {
+      int a = W1[k], b = W2[k];
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+  } else {
+    lo = suf1[l] < pre1[r] ? suf1[l] : pre1[r];
+    hi = suf2[l] > pre2[r] ? suf2[l] : pre2[r];
+    const int len = br - bl - 1;
+    if (len > 0) {
+      const int j = 31 - __clz(len);
+      const size_t lv = (size_t)j * nb;
+      int m1 = tmin[lv + bl + 1], m2 = tmin[lv + br - (1 << j)];
+      int x1 = tmax[lv + bl + 1], x2 = tmax[lv + br - (1 << j)];
+      lo = m1 < lo ? m1 : lo;
+      lo = m2 < lo ? m2 : lo;
+      hi = x1 > hi ? x1 : hi;
+      hi = x2 > hi ? x2 : hi;
+    }
+  }
+  const int p = par[v];
+  int fence = 0;
+  if (p >= 0) fence = (first[p] <= lo && last[p] >= hi) ? 1 : 0;
+  rec[v] = make_int4(l, r, p, fence);
+}
+
+// ------------------------------------------------------------ Last-CC
+__global__ void k_lcc_init(int* __restrict__ lab, int n) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) lab[v] = v;
+}
+
+// Plain (non-fence) tree edges are skeleton edges.
+__global__ void k_lcc_tree(const int4* __restrict__ rec, int n, int* lab) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int4 r = rec[v];
+  if (r.z >= 0 && r.w == 0) uf_link(lab, v, r.z);
+}
+
+// Non-tree arc x-y is a skeleton edge iff neither endpoint is an ancestor of
+// the other (paper: InSkeleton and Back).  Tree arcs (either endpoint the
+// other's parent; also repeated copies of a tree edge) are left to k_lcc_tree.
+__device__ __forceinline__ bool cross_edge(int x, int4 rx, int y, int4 ry) {
+  if (ry.z == x || rx.z == y) return false;
+  const bool y_under_x = rx.x <= ry.x && ry.x <= rx.y;
+  const bool x_under_y = ry.x <= rx.x && rx.x <= ry.y;
+  return !y_under_x && !x_under_y;
+}
+
+template <typename OffT>
+__global__ void k_lcc_sample(const OffT* __restrict__ off, const int* __restrict__ adj, const int4* __restrict__ rec,
+                             int n, int r, int* lab) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t b = off[v], e = off[v + 1];
+  if (e - b > r) {
+    int y = adj[b + r];
+    if (y != v && cross_edge(v, rec[v], y, rec[y])) uf_link(lab, v, y);
+  }
+}
+
+template <typename OffT>
+__global__ void k_lcc_sweep(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                            const int* __restrict__ tile_row, int tw, int rounds, const int4* __restrict__ rec,
+                            int* lab, const int* __restrict__ scal) {
+  const int big = scal[S_BIG_LAB];
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    if (!ok) return;
+    if (ld_relaxed(lab + x) == big) return;
+    if (a - (int64_t)off[x] < rounds) return;
+    const int y = adj[a];
+    if (y != x && cross_edge(x, rec[x], y, rec[y])) uf_link(lab, x, y);
+  });
+}
+
+// ------------------------------------------------------------ read-out
+// head(l[u]) = p(u) when l[u] != l[p(u)] (paper: Algorithm 1, component
+// heads).  A non-root head is an articulation point; a tree root is one iff
+// it heads two different labels.
+__global__ void k_bcc_heads(const int4* __restrict__ rec, const int* __restrict__ lab, int n, int* __restrict__ head,
+                            int* rootlab, uint8_t* __restrict__ ap) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int p = rec[v].z;
+  if (p < 0) return;
+  const int L = lab[v];
+  if (L == lab[p]) return;
+  head[L] = p;
+  if (ap == nullptr) return;
+  if (rec[p].z >= 0) {
+    ap[p] = 1;
+  } else {
+    int old = atomicCAS(rootlab + p, -1, L);
+    if (old != -1 && old != L) ap[p] = 1;
+  }
+}
+
+__device__ __forceinline__ int graph_of(const int* __restrict__ vbegin, int G, int v) {
+  int lo = 0, hi = G;  // vbegin[lo] <= v < vbegin[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (vbegin[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Every BCC label L (a Last-CC root that is not a tree root) marks the row of
+// its smallest vertex min(L, head(L)), where its smallest arc lies; counts BCCs.
+__global__ void k_bcc_cand(const int4* __restrict__ rec, const int* __restrict__ lab, const int* __restrict__ head,
+                           int n, uint8_t* __restrict__ cand, const int* __restrict__ vbegin, int G,
+                           int64_t* nbcc) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_label = false;
+  if (v < n && lab[v] == v && rec[v].z >= 0) {
+    is_label = true;
+    int h = head[v];
+    cand[(h >= 0 && h < v) ? h : v] = 1;
+  }
+  if (nbcc == nullptr) return;
+  if (G <= 1) {
+    uint64_t m = __ballot(is_label);
+    if (lane_id() == 0 && m) atomicAdd((unsigned long long*)nbcc, (unsigned long long)__popcll(m));
+  } else if (is_label) {
+    atomicAdd((unsigned long long*)(nbcc + graph_of(vbegin, G, v)), 1ull);
+  }
+}
+
+template <typename OffT>
+__global__ void k_bcc_minid(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                            const int* __restrict__ tile_row, int tw, const uint8_t* __restrict__ cand,
+                            const int4* __restrict__ rec, const int* __restrict__ lab, const int* __restrict__ head,
+                            int* __restrict__ minid) {
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    if (!ok || !cand[x]) return;
+    const int y = adj[a];
+    if (y == x) return;
+    const int fx = rec[x].x, fy = rec[y].x;
+    const int L = lab[fy > fx ? y : x];
+    const int h = head[L];
+    if (((h >= 0 && h < L) ? h : L) == x) atomicMin(minid + L, (int)a);
+  });
+}
+
+__global__ void k_bcc_canon(const int4* __restrict__ rec, const int* __restrict__ lab, const int* __restrict__ minid,
+                            int n, const int* __restrict__ vbegin, int G, const void* off, int off64,
+                            int2* __restrict__ fc) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int4 r = rec[v];
+  int canon = -1;
+  if (r.z >= 0) {
+    canon = minid[lab[v]];
+    if (G > 1) {
+      int g = graph_of(vbegin, G, v);
+      int vb = vbegin[g];
+      int64_t base = off64 ? ((const int64_t*)off)[vb] : (int64_t)((const int*)off)[vb];
+      canon -= (int)base;
+    }
+  }
+  fc[v] = make_int2(r.x, canon);
+}
+
+// Arc x->y belongs to the BCC of its deeper endpoint's label.
+template <typename OffT>
+__global__ void k_bcc_output(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                             const int* __restrict__ tile_row, int tw, const int2* __restrict__ fc,
+                             int* __restrict__ out) {
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    if (!ok) return;
+    const int y = adj[a];
+    int lbl = -1;
+    if (y != x) {
+      const int2 cx = fc[x], cy = fc[y];
+      lbl = cy.x > cx.x ? cy.y : cx.y;
+    }
+    out[a] = lbl;
+  });
+}
+
+// ------------------------------------------------------------ host driver
+inline unsigned grid_for(int64_t count, int block = BLOCK) { return (unsigned)cdiv(count, block); }
+
+struct Ctx {
+  hipStream_t st;
+  bool ok = true;
+  void check() {
+    if (hipGetLastError() != hipSuccess) ok = false;
+  }
+};
+
+#define LAUNCH(ctx, kern, grid, block, ...)                                 \
+  do {                                                                      \
+    if ((grid) > 0) {                                                       \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (ctx).st, __VA_ARGS__); \
+      (ctx).check();                                                        \
+    }                                                                       \
+  } while (0)
+
+void fill_i32(Ctx& c, int* p, int v, int64_t count) {
+  if (count <= 0) return;
+  unsigned g = grid_for(count);
+  if (g > 65536) g = 65536;
+  LAUNCH(c, k_fill_i32, g, BLOCK, p, v, count);
+}
+
+void fill_u8(Ctx& c, uint8_t* p, uint8_t v, int64_t count) {
+  if (count <= 0) return;
+  unsigned g = grid_for(count);
+  if (g > 65536) g = 65536;
+  LAUNCH(c, k_fill_u8, g, BLOCK, p, v, count);
+}
+
+// Exclusive scan in place over max_count ints (count from device if given);
+// the total goes to data[count] when total_out is null, else to *total_out.
+void scan_inplace(Ctx& c, int* data, int64_t max_count, const int* count_dev, int* tmp, int* total_out) {
+  if (max_count <= 0) return;
+  const int64_t nbk = cdiv(max_count, SCAN_TILE);
+  LAUNCH(c, k_scan_reduce, (unsigned)nbk, SCAN_BLOCK, data, max_count, count_dev, tmp);
+  LAUNCH(c, k_scan_spine, 1, 1024, tmp, (int)nbk, total_out);
+  LAUNCH(c, k_scan_down, (unsigned)nbk, SCAN_BLOCK, data, data, max_count, count_dev, tmp);
+}
+
+template <typename OffT>
+fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* adj, int G, const int* vbegin,
+                          int* out_label, uint8_t* out_ap, int64_t* out_nbcc, void* ws, size_t ws_bytes,
+                          uint32_t flags, hipStream_t st) {
+  Tune tune;
+  if (!decode_flags(flags, tune)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n64 < 0 || A < 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n64 >= (int64_t(1) << 30) || A >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  if (n64 > 0 && off == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (A > 0 && (adj == nullptr || out_label == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (G > 1 && vbegin == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  const Layout L = make_layout(n64, A);
+  if (ws == nullptr || ws_bytes < L.total) return FASTBCC_ERR_WORKSPACE_TOO_SMALL;
+  if (((uintptr_t)ws & 255) != 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+
+  Ctx c{st};
+  char* w = (char*)ws;
+  auto I = [&](size_t o) { return (int*)(w + o); };
+  int* scal = I(L.scalars);
+  const int n = (int)n64;
+  const int GG = G < 1 ? 1 : G;
+
+  fill_i32(c, scal, 0, S_COUNT);
+  if (out_nbcc) {
+    LAUNCH(c, k_fill_i64, 1, BLOCK, out_nbcc, (int64_t)0, (int64_t)GG);
+  }
+  if (n == 0) return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+
+  const int tw = tune.tile_windows;
+  const int64_t tile_arcs = (int64_t)WAVE * tw;
+  const int64_t ntiles = cdiv(A, tile_arcs);
+  int* tile_row = I(L.tile_row);
+  const unsigned tile_grid = (unsigned)cdiv(ntiles * WAVE, BLOCK);
+  LAUNCH(c, (k_tile_rows<OffT>), grid_for(ntiles), BLOCK, off, n, A, tile_arcs, ntiles, tile_row);
+
+  if (flags & FASTBCC_FLAG_VALIDATE) {
+    LAUNCH(c, (k_validate_rows<OffT>), grid_for(n + 1), BLOCK, off, n, A, scal + S_STATUS);
+    int h = 0;
+    if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FASTBCC_ERR_HIP;
+    if (h != 0) return FASTBCC_ERR_INVALID_GRAPH;
+    LAUNCH(c, (k_tile_rows<OffT>), grid_for(ntiles), BLOCK, off, n, A, tile_arcs, ntiles, tile_row);
+    LAUNCH(c, (k_validate_arcs<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, scal + S_STATUS);
+    if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FASTBCC_ERR_HIP;
+    if (h != 0) return FASTBCC_ERR_INVALID_GRAPH;
+  }
+
+  const unsigned gn = grid_for(n);
+  int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
+
+  // ---- First-CC (spanning forest)
+  LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
+  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, (k_cc_sample<OffT>), gn, BLOCK, off, adj, n, r, cc, hu, hv);
+  LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+  LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
+  LAUNCH(c, (k_cc_sweep<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, tune.sample_rounds, cc, hu, hv,
+         scal);
+  LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+
+  // ---- Rooting
+  int *toff = I(L.toff), *su = I(L.su), *sv = I(L.sv), *tadj = I(L.tadj), *twin = I(L.twin);
+  int *rootidx = I(L.rootidx), *roots = I(L.roots), *next = I(L.next), *tmp = I(L.scan_tmp);
+  fill_i32(c, toff, 0, n + 1);
+  LAUNCH(c, k_tree_count, gn, BLOCK, hu, hv, n, toff, su, sv);
+  scan_inplace(c, toff, n, nullptr, tmp, toff + n);
+  LAUNCH(c, k_tree_fill, gn, BLOCK, hu, hv, su, sv, toff, n, tadj, twin);
+  LAUNCH(c, k_root_flags, gn, BLOCK, cc, n, rootidx);
+  scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
+  LAUNCH(c, k_root_list, gn, BLOCK, cc, rootidx, n, roots);
+  const int64_t nodes_max = 2 * n64;  // C + 2T <= 2n - 1
+  const unsigned gnode = grid_for(nodes_max);
+  LAUNCH(c, k_euler_next, gnode, BLOCK, toff, tadj, twin, cc, rootidx, roots, n, next);
+
+  // list ranking: ruling set + pointer jumping over rulers
+  const int sh = tune.ruler_shift;
+  const int64_t rmax = cdiv(nodes_max, int64_t(1) << sh);
+  int2* ol = (int2*)(w + L.ol);
+  int *rlen = I(L.rlen), *rnext = I(L.rnext);
+  LAUNCH(c, k_lr_walk, grid_for(rmax), BLOCK, next, rootidx, toff, n, sh, ol, rnext, rlen);
+  const int* vin = rlen;
+  const int* nin = rnext;
+  int* bufv[2] = {I(L.rval0), I(L.rval1)};
+  int* bufn[2] = {I(L.rnx0), I(L.rnx1)};
+  const int rounds = ilog2_floor(rmax) + 1;  // 2^rounds > ruler count
+  for (int k = 0; k < rounds; ++k) {
+    LAUNCH(c, k_lr_jump, grid_for(rmax), BLOCK, rootidx, toff, n, sh, vin, nin, bufv[k & 1], bufn[k & 1]);
+    vin = bufv[k & 1];
+    nin = bufn[k & 1];
+  }
+  int* pos = I(L.pos);
+  int* eflag = I(L.eflag);
+  LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, toff, twin, n, ol, vin, pos);
+  LAUNCH(c, k_enter_flags, gnode, BLOCK, rootidx, toff, twin, n, pos, eflag, scal + S_STATUS);
+  // number of list nodes, for the scan of entry flags
+  int* nl_dev = scal + 8;
+  LAUNCH(c, k_node_count, 1, 1, rootidx, toff, n, nl_dev);
+  scan_inplace(c, eflag, nodes_max, nl_dev, tmp, scal + 9);
+
+  // ---- Tagging
+  int *first = I(L.first), *last = I(L.last), *par = I(L.par), *w1 = I(L.w1), *w2 = I(L.w2);
+  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, n, pos, eflag, first, last, par, w1, w2,
+         scal + S_STATUS);
+  LAUNCH(c, (k_tag_sweep<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, w1, w2);
+  int *W1 = I(L.W1), *W2 = I(L.W2), *pre1 = I(L.pre1), *suf1 = I(L.suf1), *pre2 = I(L.pre2), *suf2 = I(L.suf2);
+  int *tmin = I(L.tmin), *tmax = I(L.tmax);
+  LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, scal + S_STATUS);
+  LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W1, W2, n, L.nb, pre1, suf1, pre2, suf2, tmin,
+         tmax);
+  for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tmin, tmax, L.nb, j);
+  int4* rec = (int4*)(w + L.rec);
+  LAUNCH(c, k_rmq_query, gn, BLOCK, first, last, par, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec,
+         scal + S_STATUS);
+
+  // ---- Last-CC on the implicit skeleton
+  int* lab = I(L.lab);
+  LAUNCH(c, k_lcc_init, gn, BLOCK, lab, n);
+  LAUNCH(c, k_lcc_tree, gn, BLOCK, rec, n, lab);
+  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, (k_lcc_sample<OffT>), gn, BLOCK, off, adj, rec, n, r, lab);
+  LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+  LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
+  LAUNCH(c, (k_lcc_sweep<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, tune.sample_rounds, rec, lab, scal);
+  LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+
+  // ---- heads, articulation points, canonical labels
+  int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid);
+  uint8_t* cand = (uint8_t*)(w + L.cand);
+  int2* fc = (int2*)(w + L.fc);
+  fill_i32(c, head, -1, n);
+  fill_i32(c, rootlab, -1, n);
+  fill_i32(c, minid, INT32_MAX, n);
+  fill_u8(c, cand, 0, n);
+  if (out_ap) fill_u8(c, out_ap, 0, n);
+  LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, rootlab, out_ap);
+  LAUNCH(c, k_bcc_cand, gn, BLOCK, rec, lab, head, n, cand, vbegin, G, out_nbcc);
+  LAUNCH(c, (k_bcc_minid<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, cand, rec, lab, head, minid);
+  LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, (const void*)off,
+         (int)(sizeof(OffT) == 8), fc);
+  LAUNCH(c, (k_bcc_output<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, fc, out_label);
+  return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+fastbcc_status fastbcc_workspace_size(int64_t n, int64_t num_arcs, int32_t num_graphs, size_t* bytes) {
+  if (bytes == nullptr || n < 0 || num_arcs < 0 || num_graphs < 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  *bytes = make_layout(n, num_arcs).total;
+  return FASTBCC_OK;
+}
+
+fastbcc_status fastbcc_solve(int64_t n, int64_t num_arcs, const int32_t* offsets, const int32_t* adj,
+                             int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc, void* workspace,
+                             size_t workspace_bytes, uint32_t flags, void* stream) {
+  return solve_impl<int>(n, num_arcs, offsets, adj, 1, nullptr, out_edge_label, out_is_ap, out_num_bcc, workspace,
+                         workspace_bytes, flags, (hipStream_t)stream);
+}
+
+fastbcc_status fastbcc_solve_off64(int64_t n, int64_t num_arcs, const int64_t* offsets, const int32_t* adj,
+                                   int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
+                                   void* workspace, size_t workspace_bytes, uint32_t flags, void* stream) {
+  return solve_impl<int64_t>(n, num_arcs, offsets, adj, 1, nullptr, out_edge_label, out_is_ap, out_num_bcc,
+                             workspace, workspace_bytes, flags, (hipStream_t)stream);
+}
+
+fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32_t* graph_vbegin, int64_t n_total,
+                                     int64_t num_arcs, const int32_t* offsets, const int32_t* adj,
+                                     int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
+                                     void* workspace, size_t workspace_bytes, uint32_t flags, void* stream) {
+  if (num_graphs < 1 || graph_vbegin == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  return solve_impl<int>(n_total, num_arcs, offsets, adj, num_graphs, graph_vbegin, out_edge_label, out_is_ap,
+                         out_num_bcc, workspace, workspace_bytes, flags, (hipStream_t)stream);
+}
+
+fastbcc_status fastbcc_read_device_status(const void* workspace, void* stream, int32_t* out_status) {
+  if (workspace == nullptr || out_status == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  hipStream_t st = (hipStream_t)stream;
+  const int* scal = (const int*)workspace;  // scalars sit at offset 0
+  int h = 0;
+  if (hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return FASTBCC_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return FASTBCC_ERR_HIP;
+  *out_status = h;
+  return FASTBCC_OK;
+}
+
+const char* fastbcc_status_string(fastbcc_status s) {
+  switch (s) {
+    case FASTBCC_OK: return "ok";
+    case FASTBCC_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case FASTBCC_ERR_TOO_LARGE: return "graph too large (n >= 2^30 or arcs >= 2^31)";
+    case FASTBCC_ERR_WORKSPACE_TOO_SMALL: return "workspace too small or missing";
+    case FASTBCC_ERR_HIP: return "HIP runtime error";
+    case FASTBCC_ERR_INVALID_GRAPH: return "input is not a valid symmetric CSR";
+  }
+  return "unknown status";
+}
+
+const char* fastbcc_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+// Device primitives for the FAST-BCC kernels (gfx950, wave64).
+//
+//  * wave helpers (64-bit shuffles, lane id)
+//  * exclusive prefix scan over int32 (reduce -> spine -> downsweep), with an
+//    optional element count read from device memory so a launch sequence
+//    needs no host round trip for data-dependent sizes
+//  * union-find on a parent array in which every pointer goes to a smaller
+//    or equal id: find with path halving, link by CAS of the larger root
+//    under the smaller one (so a set's root is its smallest member), and a
+//    variant that records the edge behind every successful hook (the
+//    spanning-forest by-product of connectivity, paper: Section
+//    "Implementation Details", "Spanning Forest")
+//  * arc tiles: a wave walks a contiguous range of arcs 64 at a time and
+//    finds the source row of every arc by a shuffle binary search over 64
+//    consecutive row ends, so every sweep over the CSR is arc-balanced and
+//    reads adjacency coalesced no matter how skewed the degrees are.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fastbcc {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
+  int lo = __shfl((int)(uint32_t)(uint64_t)v, src, WAVE);
+  int hi = __shfl((int)(uint32_t)((uint64_t)v >> 32), src, WAVE);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+__device__ __forceinline__ int ld_relaxed(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+// Exclusive scan of one value per thread over the block; `total` gets the sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total) {
+  const int lane = lane_id(), wid = threadIdx.x / WAVE;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == WAVE - 1) lds[wid] = x;
+  __syncthreads();
+  int before = 0, sum = 0;
+  const int nw = blockDim.x / WAVE;
+  for (int w = 0; w < nw; ++w) {
+    int s = lds[w];
+    if (w < wid) before += s;
+    sum += s;
+  }
+  __syncthreads();
+  total = sum;
+  return before + x - v;
+}
+
+__device__ __forceinline__ int64_t scan_count(int64_t max_count, const int* count_dev) {
+  if (count_dev == nullptr) return max_count;
+  int64_t c = (int64_t)*count_dev;
+  return c < max_count ? (c < 0 ? 0 : c) : max_count;
+}
+
+__device__ __forceinline__ void load_items(const int* in, int64_t base, int64_t count, int (&v)[SCAN_ITEMS]) {
+  if (base + SCAN_ITEMS <= count) {
+    const int4* p = reinterpret_cast<const int4*>(in + base);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS / 4; ++k) {
+      int4 q = p[k];
+      v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = (base + k < count) ? in[base + k] : 0;
+  }
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const int* __restrict__ in, int64_t max_count,
+                                                             const int* count_dev, int* __restrict__ bsum) {
+  __shared__ int lds[SCAN_BLOCK / WAVE];
+  const int64_t count = scan_count(max_count, count_dev);
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load_items(in, base, count, v);
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+  int total;
+  block_exclusive_scan(s, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One block scans the per-block sums in place (exclusive) and stores the total.
+__global__ void __launch_bounds__(1024) k_scan_spine(int* __restrict__ bsum, int nblocks, int* total_out) {
+  __shared__ int lds[1024 / WAVE];
+  int carry = 0;
+  for (int base = 0; base < nblocks; base += 1024 * 4) {
+    int v[4];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int i = base + threadIdx.x * 4 + k;
+      v[k] = i < nblocks ? bsum[i] : 0;
+      s += v[k];
+    }
+    int tot;
+    int ex = block_exclusive_scan(s, lds, tot) + carry;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int i = base + threadIdx.x * 4 + k;
+      if (i < nblocks) bsum[i] = ex;
+      ex += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down(const int* in, int* out, int64_t max_count,
+                                                           const int* count_dev, const int* __restrict__ bsum) {
+  __shared__ int lds[SCAN_BLOCK / WAVE];
+  const int64_t count = scan_count(max_count, count_dev);
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load_items(in, base, count, v);
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+  int total;
+  int ex = block_exclusive_scan(s, lds, total) + bsum[blockIdx.x];
+  if (base + SCAN_ITEMS <= count) {
+    int4* p = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS / 4; ++k) {
+      int4 q;
+      q.x = ex; ex += v[4 * k];
+      q.y = ex; ex += v[4 * k + 1];
+      q.z = ex; ex += v[4 * k + 2];
+      q.w = ex; ex += v[4 * k + 3];
+      p[k] = q;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (base + k < count) out[base + k] = ex;
+      ex += v[k];
+    }
+  }
+}
+
+// ------------------------------------------------------------ union-find
+// Every parent pointer goes to an id <= its own, so loops always end.
+__device__ __forceinline__ int uf_find(int* p, int x) {
+  int px = ld_relaxed(p + x);
+  while (px != x) {
+    int gx = ld_relaxed(p + px);
+    if (gx == px) return px;
+    st_relaxed(p + x, gx);  // path halving: an ancestor of x, same set
+    x = gx;
+    px = ld_relaxed(p + x);
+  }
+  return x;
+}
+
+// Union by CAS: the larger root goes under the smaller one.
+__device__ __forceinline__ void uf_link(int* p, int u, int v) {
+  int ru = uf_find(p, u), rv = uf_find(p, v);
+  while (ru != rv) {
+    int hi = ru > rv ? ru : rv, lo = ru > rv ? rv : ru;
+    if (atomicCAS(p + hi, hi, lo) == hi) return;
+    ru = uf_find(p, ru);
+    rv = uf_find(p, rv);
+  }
+}
+
+// As uf_link; a successful hook of root h stores the edge (u, v) at h.  At
+// the CAS, u's set (rooted at the hooked root) and v's set are disjoint, so
+// the recorded edges form a spanning forest.
+__device__ __forceinline__ void uf_link_record(int* p, int u, int v, int* hook_u, int* hook_v) {
+  int ru = uf_find(p, u), rv = uf_find(p, v);
+  while (ru != rv) {
+    int hi = ru > rv ? ru : rv, lo = ru > rv ? rv : ru;
+    if (atomicCAS(p + hi, hi, lo) == hi) {
+      hook_u[hi] = u;
+      hook_v[hi] = v;
+      return;
+    }
+    ru = uf_find(p, ru);
+    rv = uf_find(p, rv);
+  }
+}
+
+// ------------------------------------------------------------- arc tiles
+// A wave owns arcs [t*tile_arcs, (t+1)*tile_arcs).  tile_row[t] is the row
+// containing the tile's first arc.  `body(a, x, ok)` is called by all 64
+// lanes for every 64-arc window; ok says whether arc a (source row x) exists.
+template <typename OffT, typename Body>
+__device__ __forceinline__ void arc_tiles(const OffT* __restrict__ off, int n, int64_t A,
+                                          const int* __restrict__ tile_row, int tile_windows, Body&& body) {
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t tile_arcs = (int64_t)WAVE * tile_windows;
+  const int64_t tbeg = wave * tile_arcs;
+  if (tbeg >= A) return;
+  const int64_t tend = tbeg + tile_arcs < A ? tbeg + tile_arcs : A;
+  int row = tile_row[wave];
+  for (int64_t base = tbeg; base < tend; base += WAVE) {
+    const int64_t a = base + lane;
+    int my_row = -1;
+    int lo = row;
+    while (lo < n) {
+      int idx = lo + 1 + lane;
+      idx = idx < n ? idx : n;
+      const int64_t e = (int64_t)off[idx];  // end of row lo + lane
+      const int64_t e_last = shfl64(e, WAVE - 1);
+      // pos = number of the 64 row ends that are <= a (0..64)
+      int pos = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        int64_t ej = shfl64(e, pos + step - 1);
+        if (ej <= a) pos += step;
+      }
+      if (pos == WAVE - 1 && e_last <= a) pos = WAVE;
+      if (my_row < 0 && pos < WAVE) my_row = lo + pos;
+      const bool need = (a < tend) && my_row < 0;
+      if (!__any(need)) break;
+      lo += WAVE;
+    }
+    const bool ok = (a < tend) && my_row >= 0 && my_row < n;
+    body(a, ok ? my_row : -1, ok);
+    int last = __shfl(my_row, WAVE - 1, WAVE);
+    row = last >= 0 ? last : row;
+  }
+}
+
+}  // namespace fastbcc

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed: nothing here launches work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2301_01356_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastbcc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"FASTBCC_API\s+[\w\s\*]+?\b(fastbcc_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_bound_entry_points():
+    assert declared_functions() == sorted(N.EXPORTED)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = N.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.fastbcc_version().decode().count(".") == 2
+
+
+def test_no_other_symbols_exported():
+    import subprocess
+
+    out = subprocess.run(["nm", "-D", "--defined-only", N.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    text_syms = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert text_syms == sorted(N.EXPORTED)
+
+
+def test_workspace_size_is_linear_in_n():
+    a = N.workspace_size(1 << 16, 1 << 20)
+    b = N.workspace_size(1 << 17, 1 << 20)
+    c = N.workspace_size(1 << 17, 1 << 24)
+    assert 0 < a < b
+    # arcs only add tile bookkeeping: 4 bytes per 256 arcs
+    assert c - b <= ((1 << 24) - (1 << 20)) // 256 * 4 + 4096
+    # the O(n) part: well under 256 bytes per vertex
+    assert b / (1 << 17) < 256
+
+
+def test_workspace_size_rejects_bad_arguments():
+    lib = N.lib()
+    out = ctypes.c_size_t(0)
+    assert lib.fastbcc_workspace_size(-1, 0, 1, ctypes.byref(out)) == N.ERR_INVALID_ARGUMENT
+    assert lib.fastbcc_workspace_size(1 << 30, 0, 1, ctypes.byref(out)) == N.ERR_TOO_LARGE
+    assert lib.fastbcc_workspace_size(10, 1 << 31, 1, ctypes.byref(out)) == N.ERR_TOO_LARGE
+    assert lib.fastbcc_workspace_size(10, 10, 1, None) == N.ERR_INVALID_ARGUMENT
+
+
+def _solve(n, arcs, ws, ws_bytes, flags=0, off=1):
+    # pointers are never dereferenced on these error paths
+    return N.lib().fastbcc_solve(n, arcs, off, 1, 1, None, None, ws, ws_bytes, flags, None)
+
+
+def test_solve_argument_errors_are_synchronous():
+    need = N.workspace_size(100, 400)
+    assert _solve(100, 400, None, need) == N.ERR_WORKSPACE_TOO_SMALL
+    assert _solve(100, 400, 256, need - 1) == N.ERR_WORKSPACE_TOO_SMALL
+    assert _solve(100, 400, 256 + 4, need) == N.ERR_INVALID_ARGUMENT  # misaligned workspace
+    assert _solve(-5, 400, 256, need) == N.ERR_INVALID_ARGUMENT
+    assert _solve(1 << 30, 400, 256, 1 << 40) == N.ERR_TOO_LARGE
+    assert _solve(100, 400, 256, need, flags=1 << 30) == N.ERR_INVALID_ARGUMENT  # unknown flag bit
+    assert _solve(100, 400, 256, need, flags=2 << N.TUNE_RULER_SHIFT) == N.ERR_INVALID_ARGUMENT
+    assert _solve(100, 400, 256, need, flags=1 << N.TUNE_TILE_SHIFT) == N.ERR_INVALID_ARGUMENT
+    assert _solve(100, 400, 256, need, off=0) == N.ERR_INVALID_ARGUMENT
+    lib = N.lib()
+    assert lib.fastbcc_solve_batched(0, 1, 10, 10, 1, 1, 1, None, None, 256, need, 0, None) == N.ERR_INVALID_ARGUMENT
+    assert lib.fastbcc_solve_batched(2, None, 10, 10, 1, 1, 1, None, None, 256, need, 0, None) == N.ERR_INVALID_ARGUMENT
+    st = ctypes.c_int32(0)
+    assert lib.fastbcc_read_device_status(None, None, ctypes.byref(st)) == N.ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("code", range(6))
+def test_status_strings(code):
+    s = N.lib().fastbcc_status_string(code).decode()
+    assert s and s != "unknown status"
+
+
+def test_tune_flag_encoding():
+    assert N.tune_flags() == 0
+    f = N.tune_flags(ruler_shift=6, sample_rounds=0, tile_shift=3)
+    assert (f >> N.TUNE_RULER_SHIFT) & 0xF == 6
+    assert (f >> N.TUNE_SAMPLE_SHIFT) & 0x3 == 3
+    assert (f >> N.TUNE_TILE_SHIFT) & 0x7 == 3

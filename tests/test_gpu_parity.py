@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+All outputs are integers, so the bar is bit-exact equality of the canonical
+edge labels, the articulation-point flags and the BCC count.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2301_01356_amd import _native as N
+from paper_2301_01356_amd import gen, solve, solve_batched
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(g, off64=False):
+    off = torch.from_numpy(g.offsets if off64 else g.offsets32()).to(DEV)
+    adj = torch.from_numpy(g.adj).to(DEV)
+    return off, adj
+
+
+def gpu_solve(g, off64=False, flags=0):
+    off, adj = to_dev(g, off64)
+    r = solve(off, adj, flags=flags)
+    torch.cuda.synchronize()
+    return r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), int(r.num_bcc.item())
+
+
+def assert_parity(g, got, what=""):
+    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+    glab, gap, gnb = got
+    if not np.array_equal(glab, lab):
+        bad = np.flatnonzero(glab != lab)
+        pytest.fail(f"{what}: {bad.size} edge labels differ, first at arc {bad[0]}: gpu {glab[bad[0]]} oracle {lab[bad[0]]}")
+    assert np.array_equal(gap, ap), f"{what}: articulation points differ at {np.flatnonzero(gap != ap)[:10]}"
+    assert gnb == nb, f"{what}: num_bcc {gnb} != {nb}"
+
+
+SMALL = ["plain_small", "grid_small", "rmat_small", "batch_small"]
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("off64", [False, True])
+def test_small_configs(name, off64):
+    note(f"{name} off64={off64}")
+    g = gen.config(name)
+    assert_parity(g, gpu_solve(g, off64), name)
+
+
+def cycle(n):
+    return [(i, (i + 1) % n) for i in range(n)]
+
+
+def path(n):
+    return [(i, i + 1) for i in range(n - 1)]
+
+
+CLOSED = {
+    "cycle3": (3, cycle(3)),
+    "cycle1000": (1000, cycle(1000)),
+    "path2": (2, path(2)),
+    "path5000": (5000, path(5000)),
+    "star": (65, [(0, i) for i in range(1, 65)]),
+    "k7": (7, [(i, j) for i in range(7) for j in range(i + 1, 7)]),
+    "two_cycles": (8, cycle(5) + [(0, 5), (5, 6), (6, 7), (7, 0)]),
+    "isolated_plus_edge": (6, [(1, 2)]),
+    "single_vertex": (1, []),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLOSED))
+def test_closed_forms(name):
+    n, e = CLOSED[name]
+    note(name)
+    g = gen.from_edges(n, e) if e else gen.Csr(n, np.zeros(n + 1, np.int64), np.zeros(0, np.int32))
+    assert_parity(g, gpu_solve(g), name)
+
+
+def test_open_grid_and_long_path():
+    note("grid 64x80 p=1 + path 3000")
+    g = gen.grid(seed=5, rows=64, cols=80, p=1.0, path_len=3000, chord_block=100)
+    assert_parity(g, gpu_solve(g), "grid+path")
+
+
+def test_multigraph_self_loops_unsorted_rows():
+    rng = np.random.default_rng(3)
+    for t in range(60):
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(0, 80))
+        edges = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(m)]
+        edges += edges[: int(rng.integers(0, 5))]
+        g = gen.multigraph_csr(n, edges)
+        adj = g.adj.copy()
+        for v in range(n):
+            s, e = g.offsets[v], g.offsets[v + 1]
+            adj[s:e] = rng.permutation(adj[s:e])
+        g = gen.Csr(n, g.offsets, adj)
+        note(f"multigraph #{t} n={n} arcs={g.num_arcs}")
+        assert_parity(g, gpu_solve(g), f"multigraph {t}")
+
+
+@pytest.mark.parametrize("flags", [
+    N.tune_flags(ruler_shift=3), N.tune_flags(ruler_shift=10), N.tune_flags(sample_rounds=0),
+    N.tune_flags(sample_rounds=1), N.tune_flags(tile_shift=6), N.tune_flags(ruler_shift=7, tile_shift=3),
+])
+def test_tuning_fields_never_change_results(flags):
+    note(f"rmat_small flags={flags:#x}")
+    g = gen.config("rmat_small")
+    assert_parity(g, gpu_solve(g, flags=flags), f"flags {flags:#x}")
+
+
+def test_repeated_solves_identical():
+    g = gen.config("grid_small")
+    note("grid_small x5")
+    first = gpu_solve(g)
+    for _ in range(4):
+        again = gpu_solve(g)
+        assert np.array_equal(first[0], again[0]) and np.array_equal(first[1], again[1]) and first[2] == again[2]
+
+
+def test_batched_equals_each_graph_alone():
+    rng = np.random.default_rng(9)
+    graphs = [gen.mixed(41, i, 8, 3000, 4.0, 16.0) for i in range(40)]
+    graphs.append(gen.Csr(3, np.zeros(4, np.int64), np.zeros(0, np.int32)))  # an edgeless graph
+    graphs.insert(5, gen.from_edges(4, cycle(4)))
+    u = gen.unite(graphs)
+    note(f"batched {len(graphs)} graphs n={u.n} arcs={u.num_arcs}")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    r = solve_batched(vb, off, adj)
+    torch.cuda.synchronize()
+    lab = r.edge_label.cpu().numpy()
+    ap = r.is_ap.cpu().numpy()
+    nb = r.num_bcc.cpu().numpy()
+    for i, g in enumerate(graphs):
+        a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+        got = (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i]))
+        assert_parity(g, got, f"graph {i} in batch")
+    del rng
+
+
+def test_validate_flag():
+    g = gen.config("plain_small")
+    note("validate ok")
+    assert_parity(g, gpu_solve(g, flags=N.FLAG_VALIDATE), "validate")
+    # asymmetric: drop one arc
+    bad = gen.Csr(3, np.array([0, 1, 2, 2], np.int64), np.array([1, 0], np.int32))
+    bad = gen.Csr(3, np.array([0, 2, 3, 3], np.int64), np.array([1, 2, 0], np.int32))
+    note("validate asymmetric")
+    off, adj = to_dev(bad)
+    with pytest.raises(N.FastBccError) as ei:
+        solve(off, adj, flags=N.FLAG_VALIDATE)
+    assert ei.value.status == N.ERR_INVALID_GRAPH
+    # out-of-range id
+    bad = gen.Csr(2, np.array([0, 1, 2], np.int64), np.array([7, 0], np.int32))
+    note("validate out-of-range")
+    off, adj = to_dev(bad)
+    with pytest.raises(N.FastBccError) as ei:
+        solve(off, adj, flags=N.FLAG_VALIDATE)
+    assert ei.value.status == N.ERR_INVALID_GRAPH
+
+
+@pytest.mark.parametrize("name", ["plain", "grid"])
+def test_full_size_configs(name):
+    note(f"full {name}")
+    g = gen.config(name)
+    assert_parity(g, gpu_solve(g), name)
