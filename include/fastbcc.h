@@ -132,6 +132,35 @@ FASTBCC_API fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32
  */
 FASTBCC_API fastbcc_status fastbcc_read_device_status(const void* workspace, void* stream, int32_t* out_status);
 
+/*
+ * Per-kernel timing (profiling aid).  A trace owns a pool of HIP events
+ * (created by fastbcc_trace_create, freed by fastbcc_trace_destroy).
+ * fastbcc_solve_traced enqueues the same kernels as the plain entry points
+ * with an event pair around every launch; fastbcc_trace_collect waits for
+ * the recorded events and adds each launch's duration to a per-kernel
+ * total.  Launches beyond the pool's capacity are not timed (counted in
+ * fastbcc_trace_dropped).  A trace must not be shared by concurrent solves.
+ */
+typedef struct fastbcc_trace fastbcc_trace;
+
+FASTBCC_API fastbcc_trace* fastbcc_trace_create(int32_t max_launches);
+FASTBCC_API void fastbcc_trace_destroy(fastbcc_trace* trace);
+/* General solve with tracing: offsets_bits is 32 or 64; graph_vbegin may be
+ * null when num_graphs == 1; other arguments as in fastbcc_solve_batched. */
+FASTBCC_API fastbcc_status fastbcc_solve_traced(int32_t num_graphs, const int32_t* graph_vbegin, int64_t n,
+                                                int64_t num_arcs, const void* offsets, int32_t offsets_bits,
+                                                const int32_t* adj, int32_t* out_edge_label, uint8_t* out_is_ap,
+                                                int64_t* out_num_bcc, void* workspace, size_t workspace_bytes,
+                                                uint32_t flags, void* stream, fastbcc_trace* trace);
+FASTBCC_API fastbcc_status fastbcc_trace_collect(fastbcc_trace* trace);
+/* Number of distinct kernels seen; entry i: kernel name (static string),
+ * summed milliseconds and number of timed launches (all host pointers). */
+FASTBCC_API int32_t fastbcc_trace_count(const fastbcc_trace* trace);
+FASTBCC_API fastbcc_status fastbcc_trace_entry(const fastbcc_trace* trace, int32_t i, const char** name,
+                                               double* total_ms, int64_t* launches);
+FASTBCC_API int64_t fastbcc_trace_dropped(const fastbcc_trace* trace);
+FASTBCC_API void fastbcc_trace_reset(fastbcc_trace* trace);
+
 /* Static string for a status code. */
 FASTBCC_API const char* fastbcc_status_string(fastbcc_status status);
 

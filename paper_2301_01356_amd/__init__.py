@@ -3,6 +3,6 @@
 The compute path is ``libfastbcc.so`` (hand-written HIP for gfx950, C ABI in
 ``include/fastbcc.h``); this package only marshals torch tensors into it.
 """
-from .api import BccResult, alloc_workspace, read_device_status, solve, solve_batched, workspace_size  # noqa: F401
+from .api import BccResult, alloc_workspace, read_device_status, solve, solve_batched, solve_traced, workspace_size  # noqa: F401
 
-__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "workspace_size"]
+__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "solve_traced", "workspace_size"]

@@ -33,6 +33,14 @@ EXPORTED = (
     "fastbcc_read_device_status",
     "fastbcc_status_string",
     "fastbcc_version",
+    "fastbcc_solve_traced",
+    "fastbcc_trace_create",
+    "fastbcc_trace_destroy",
+    "fastbcc_trace_collect",
+    "fastbcc_trace_count",
+    "fastbcc_trace_entry",
+    "fastbcc_trace_dropped",
+    "fastbcc_trace_reset",
 )
 
 
@@ -73,6 +81,23 @@ def lib():
     h.fastbcc_status_string.argtypes = [st]
     h.fastbcc_version.restype = ctypes.c_char_p
     h.fastbcc_version.argtypes = []
+    h.fastbcc_solve_traced.restype = st
+    h.fastbcc_solve_traced.argtypes = [i32, vp, i64, i64, vp, i32, vp, vp, vp, vp, vp, sz, u32, vp, vp]
+    h.fastbcc_trace_create.restype = vp
+    h.fastbcc_trace_create.argtypes = [i32]
+    h.fastbcc_trace_destroy.restype = None
+    h.fastbcc_trace_destroy.argtypes = [vp]
+    h.fastbcc_trace_collect.restype = st
+    h.fastbcc_trace_collect.argtypes = [vp]
+    h.fastbcc_trace_count.restype = i32
+    h.fastbcc_trace_count.argtypes = [vp]
+    h.fastbcc_trace_entry.restype = st
+    h.fastbcc_trace_entry.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(i64)]
+    h.fastbcc_trace_dropped.restype = i64
+    h.fastbcc_trace_dropped.argtypes = [vp]
+    h.fastbcc_trace_reset.restype = None
+    h.fastbcc_trace_reset.argtypes = [vp]
     _lib = h
     return h
 
@@ -98,3 +123,43 @@ def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0) ->
     if tile_shift:
         f |= (tile_shift & 0x7) << TUNE_TILE_SHIFT
     return f
+
+
+class Trace:
+    """Per-kernel HIP-event timing over any number of traced solves."""
+
+    def __init__(self, max_launches: int = 8192):
+        self.h = lib().fastbcc_trace_create(int(max_launches))
+        if not self.h:
+            raise FastBccError(ERR_HIP, "fastbcc_trace_create")
+
+    def collect(self) -> None:
+        check(lib().fastbcc_trace_collect(self.h), "fastbcc_trace_collect")
+
+    def totals(self) -> dict:
+        """{kernel name: (total ms, timed launches)} of everything collected."""
+        out = {}
+        for i in range(lib().fastbcc_trace_count(self.h)):
+            name = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            nl = ctypes.c_int64()
+            check(lib().fastbcc_trace_entry(self.h, i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(nl)))
+            out[name.value.decode()] = (ms.value, nl.value)
+        return out
+
+    def dropped(self) -> int:
+        return int(lib().fastbcc_trace_dropped(self.h))
+
+    def reset(self) -> None:
+        lib().fastbcc_trace_reset(self.h)
+
+    def close(self) -> None:
+        if self.h:
+            lib().fastbcc_trace_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

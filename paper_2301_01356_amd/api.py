@@ -159,6 +159,54 @@ def solve_batched(
     return out
 
 
+def solve_traced(
+    offsets: torch.Tensor,
+    adj: torch.Tensor,
+    trace: "N.Trace",
+    *,
+    vbegin: Optional[torch.Tensor] = None,
+    out: Optional[BccResult] = None,
+    workspace: Optional[torch.Tensor] = None,
+    flags: int = 0,
+    stream=None,
+) -> BccResult:
+    """``solve``/``solve_batched`` with an event pair around every kernel."""
+    _check_tensor(offsets, "offsets", (torch.int32, torch.int64))
+    _check_tensor(adj, "adj", (torch.int32,))
+    n = offsets.numel() - 1
+    A = adj.numel()
+    G = 1 if vbegin is None else vbegin.numel() - 1
+    dev = offsets.device
+    if out is None:
+        out = BccResult(
+            torch.empty(A, dtype=torch.int32, device=dev),
+            torch.empty(n, dtype=torch.uint8, device=dev),
+            torch.empty(G, dtype=torch.int64, device=dev),
+        )
+    if workspace is None:
+        workspace = alloc_workspace(n, A, G, dev)
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_solve_traced(
+            G,
+            _dev_ptr(vbegin),
+            n,
+            A,
+            offsets.data_ptr(),
+            32 if offsets.dtype == torch.int32 else 64,
+            _dev_ptr(adj) if A else None,
+            _dev_ptr(out.edge_label) if A else None,
+            _dev_ptr(out.is_ap) if n else None,
+            out.num_bcc.data_ptr(),
+            workspace.data_ptr(),
+            workspace.numel(),
+            flags,
+            _stream_handle(stream),
+            trace.h,
+        )
+    N.check(st, "fastbcc_solve_traced")
+    return out
+
+
 def read_device_status(workspace: torch.Tensor, stream=None) -> int:
     import ctypes
 

@@ -36,10 +36,30 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <string>
+#include <vector>
+
 #include "fastbcc.h"
 #include "prims.hpp"
 
 using namespace fastbcc;
+
+struct fastbcc_trace {
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  struct Total {
+    const char* name;
+    double ms;
+    int64_t launches;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Pending> pending;
+  std::vector<Total> totals;
+  int64_t dropped = 0;
+};
 
 namespace {
 
@@ -71,9 +91,9 @@ inline int ilog2_floor(int64_t x) {
 // ------------------------------------------------------------ workspace
 struct Layout {
   size_t total = 0;
-  size_t scalars, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
-      rval1, rnx0, rnx1, pos, eflag, first, last, par, w1, w2, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax,
-      rec, lab, head, rootlab, minid, cand, fc, tile_row, scan_tmp;
+  size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
+      rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, lab, head,
+      rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, tile_row, scan_tmp;
   int64_t nb = 0;      // rmq blocks of 64
   int levels = 0;      // sparse-table levels
   int64_t rmax = 0;    // ruler capacity
@@ -98,6 +118,7 @@ Layout make_layout(int64_t n, int64_t A) {
   L.scan_blocks = cdiv(n2, SCAN_TILE) + 1;
   const size_t I = sizeof(int);
   L.scalars = take(c, S_COUNT * I);
+  L.off32 = take(c, n1 * I);
   L.cc = take(c, n * I);
   L.hu = take(c, n * I);
   L.hv = take(c, n * I);
@@ -119,8 +140,6 @@ Layout make_layout(int64_t n, int64_t A) {
   L.pos = take(c, n2 * I);
   L.eflag = take(c, n2 * I);
   L.first = take(c, n * I);
-  L.last = take(c, n * I);
-  L.par = take(c, n * I);
   L.w1 = take(c, n * I);
   L.w2 = take(c, n * I);
   L.W1 = take(c, n * I);
@@ -136,8 +155,14 @@ Layout make_layout(int64_t n, int64_t A) {
   L.head = take(c, n * I);
   L.rootlab = take(c, n * I);
   L.minid = take(c, n * I);
-  L.cand = take(c, n);
-  L.fc = take(c, n * sizeof(int2));
+  L.canon = take(c, n * I);
+  L.bsum = take(c, (cdiv(n > 0 ? n : 1, BLOCK) + 1) * I);
+  L.heads = take(c, n);
+  L.foff = take(c, n1 * I);
+  L.frank = take(c, n1 * I);
+  L.frow = take(c, n1 * I);
+  L.fstart = take(c, n1 * I);
+  L.ftile = take(c, L.tiles * I);
   L.tile_row = take(c, L.tiles * I);
   L.scan_tmp = take(c, L.scan_blocks * I);
   L.total = c;
@@ -183,11 +208,15 @@ __global__ void k_fill_i64(int64_t* p, int64_t v, int64_t count) {
     p[i] = v;
 }
 
-template <typename OffT>
-__global__ void k_tile_rows(const OffT* __restrict__ off, int n, int64_t A, int64_t tile_arcs, int64_t ntiles,
+// tile_row[t] = row holding arc t*tile_arcs (count from the device if given).
+__global__ void k_tile_rows(const int* __restrict__ off, int n, int64_t A, const int* rows_dev, int64_t tile_arcs,
                             int* __restrict__ tile_row) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
+  if (rows_dev) {  // rows and arc count both on the device: off[rows] = arcs
+    n = *rows_dev;
+    A = off[n];
+  }
+  if (t * tile_arcs >= A) return;
   const int64_t a = t * tile_arcs;
   int lo = 0, hi = n;  // off[lo] <= a < off[hi]
   while (hi - lo > 1) {
@@ -196,6 +225,37 @@ __global__ void k_tile_rows(const OffT* __restrict__ off, int n, int64_t A, int6
     else hi = mid;
   }
   tile_row[t] = lo;
+}
+
+// Frontier of a connectivity sweep: rows outside the sampled largest set,
+// minus the arcs the sampling rounds already took.  fdeg -> scan gives each
+// row's first virtual arc; the non-empty rows are then compacted (row id +
+// start) so the virtual CSR has no empty rows for a wave to walk over.
+__global__ void k_frontier_deg(const int* __restrict__ off, const int* __restrict__ comp,
+                               const int* __restrict__ scal, int slot, int rounds, int n, int* __restrict__ fdeg,
+                               int* __restrict__ fflag) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int big = scal[slot];
+  const int d = off[v + 1] - off[v] - rounds;
+  const bool in = d > 0 && comp[v] != big;
+  fdeg[v] = in ? d : 0;
+  fflag[v] = in ? 1 : 0;
+}
+
+__global__ void k_frontier_compact(const int* __restrict__ foff, const int* __restrict__ frank, int n,
+                                   int* __restrict__ frow, int* __restrict__ fstart) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  if (v == n) {
+    fstart[frank[n]] = foff[n];  // end of the last compacted row = frontier arc count
+    return;
+  }
+  const int r = frank[v];
+  if (frank[v + 1] != r) {
+    frow[r] = v;
+    fstart[r] = foff[v];
+  }
 }
 
 // Most frequent value of p[] over a stratified sample of vertices (one block).
@@ -277,8 +337,7 @@ __global__ void k_validate_rows(const OffT* __restrict__ off, int n, int64_t A, 
   if (bad) atomicExch(status, (int)FASTBCC_ERR_INVALID_GRAPH);
 }
 
-template <typename OffT>
-__global__ void k_validate_arcs(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+__global__ void k_validate_arcs(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                                 const int* __restrict__ tile_row, int tw, int* status) {
   arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
     if (!ok) return;
@@ -308,8 +367,7 @@ __global__ void k_cc_init(int* __restrict__ cc, int* __restrict__ hu, int n) {
 }
 
 // Sampling round r: every vertex links to its r-th neighbour.
-template <typename OffT>
-__global__ void k_cc_sample(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
+__global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
                             int* hu, int* hv) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
@@ -320,17 +378,18 @@ __global__ void k_cc_sample(const OffT* __restrict__ off, const int* __restrict_
   }
 }
 
-// Full sweep: rows whose set is the sampled largest one are skipped (every
-// edge they share with another set is seen from that set's side).
-template <typename OffT>
-__global__ void k_cc_sweep(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                           const int* __restrict__ tile_row, int tw, int rounds, int* cc, int* hu, int* hv,
-                           const int* __restrict__ scal) {
-  const int big = scal[S_BIG_CC];
-  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+// Full sweep over the frontier: rows whose set is the sampled largest one
+// are skipped (every edge they share with another set is seen from that
+// set's side, and a row found in the largest set stays connected to it).
+__global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
+                           const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
+                           int tw, int rounds, int* cc, int* hu, int* hv) {
+  const int R = *frows;
+  const int64_t F = fstart[R];
+  arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
     if (!ok) return;
-    if (ld_relaxed(cc + x) == big) return;
-    if (a - (int64_t)off[x] < rounds) return;
+    const int x = frow[i];
+    const int64_t a = (int64_t)off[x] + rounds + (k - (int64_t)fstart[i]);
     const int w = adj[a];
     if (w != x) uf_link_record(cc, x, w, hu, hv);
   });
@@ -476,12 +535,12 @@ __global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __rest
   eflag[p] = f;
 }
 
-// first/last/parent from the ranked tour; w1 = w2 = first as the start value.
+// first/last/parent from the ranked tour: one 16-byte record per vertex plus
+// a compact first[] (the array every arc sweep gathers from).
 __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ roots,
                        const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
                        int n, const int* __restrict__ pos, const int* __restrict__ escan, int* __restrict__ first,
-                       int* __restrict__ last, int* __restrict__ par, int* __restrict__ w1, int* __restrict__ w2,
-                       int* status) {
+                       int4* __restrict__ rec, int* status) {
   const int C = rootidx[n], NL = C + toff[n];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NL) return;
@@ -506,18 +565,14 @@ __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ 
     return;
   }
   first[v] = f;
-  last[v] = l;
-  par[v] = p;
-  w1[v] = f;
-  w2[v] = f;
+  rec[v] = make_int4(f, l, p, 0);
 }
 
 // ------------------------------------------------------------ Tagging
 // w1[x] = min, w2[x] = max of first[] over x and all its neighbours.  Using
 // every neighbour instead of non-tree ones only adds first[p(x)] and values
 // inside T_x; neither changes any fence decision.
-template <typename OffT>
-__global__ void k_tag_sweep(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+__global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                             const int* __restrict__ tile_row, int tw, const int* __restrict__ first,
                             int* __restrict__ w1, int* __restrict__ w2) {
   arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
@@ -558,8 +613,9 @@ __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restri
     atomicExch(status, (int)FASTBCC_ERR_HIP);
     return;
   }
-  W1[f] = w1[v];
-  W2[f] = w2[v];
+  int a = w1[v], b = w2[v];
+  W1[f] = a < f ? a : f;
+  W2[f] = b > f ? b : f;
 }
 
 // In-block prefix/suffix min and max (block = 64 consecutive preorder slots
@@ -616,15 +672,16 @@ __global__ void k_rmq_level(int* __restrict__ tmin, int* __restrict__ tmax, int6
 }
 
 // low/high over [first, last]; fence(p(v), v) = first[p] <= low[v] and
-// last[p] >= high[v] (paper: Algorithm 1, function Fence).
-__global__ void k_rmq_query(const int* __restrict__ first, const int* __restrict__ last, const int* __restrict__ par,
-                            int n, int64_t nb, const int* __restrict__ W1, const int* __restrict__ W2,
+// last[p] >= high[v] (paper: Algorithm 1, function Fence).  Updates the
+// vertex record in place (only its fence field changes).
+__global__ void k_rmq_query(int n, int64_t nb, const int* __restrict__ W1, const int* __restrict__ W2,
                             const int* __restrict__ pre1, const int* __restrict__ suf1, const int* __restrict__ pre2,
                             const int* __restrict__ suf2, const int* __restrict__ tmin, const int* __restrict__ tmax,
-                            int4* __restrict__ rec, int* status) {
+                            int4* rec, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int l = first[v], r = last[v];
+  const int4 me = rec[v];
+  const int l = me.x, r = me.y;
   if (l < 0 || r < l || r >= n) {
     atomicExch(status, (int)FASTBCC_ERR_HIP);
     rec[v] = make_int4(0, n - 1, -1, 0);
@@ -655,10 +712,11 @@ __global__ void k_rmq_query(const int* __restrict__ first, const int* __restrict
       hi = x2 > hi ? x2 : hi;
     }
   }
-  const int p = par[v];
-  int fence = 0;
-  if (p >= 0) fence = (first[p] <= lo && last[p] >= hi) ? 1 : 0;
-  rec[v] = make_int4(l, r, p, fence);
+  const int p = me.z;
+  if (p >= 0) {
+    const int4 pr = rec[p];
+    if (pr.x <= lo && pr.y >= hi) rec[v].w = 1;
+  }
 }
 
 // ------------------------------------------------------------ Last-CC
@@ -685,8 +743,7 @@ __device__ __forceinline__ bool cross_edge(int x, int4 rx, int y, int4 ry) {
   return !y_under_x && !x_under_y;
 }
 
-template <typename OffT>
-__global__ void k_lcc_sample(const OffT* __restrict__ off, const int* __restrict__ adj, const int4* __restrict__ rec,
+__global__ void k_lcc_sample(const int* __restrict__ off, const int* __restrict__ adj, const int4* __restrict__ rec,
                              int n, int r, int* lab) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
@@ -697,15 +754,15 @@ __global__ void k_lcc_sample(const OffT* __restrict__ off, const int* __restrict
   }
 }
 
-template <typename OffT>
-__global__ void k_lcc_sweep(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                            const int* __restrict__ tile_row, int tw, int rounds, const int4* __restrict__ rec,
-                            int* lab, const int* __restrict__ scal) {
-  const int big = scal[S_BIG_LAB];
-  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+__global__ void k_lcc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
+                            const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
+                            int tw, int rounds, const int4* __restrict__ rec, int* lab) {
+  const int R = *frows;
+  const int64_t F = fstart[R];
+  arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
     if (!ok) return;
-    if (ld_relaxed(lab + x) == big) return;
-    if (a - (int64_t)off[x] < rounds) return;
+    const int x = frow[i];
+    const int64_t a = (int64_t)off[x] + rounds + (k - (int64_t)fstart[i]);
     const int y = adj[a];
     if (y != x && cross_edge(x, rec[x], y, rec[y])) uf_link(lab, x, y);
   });
@@ -716,7 +773,7 @@ __global__ void k_lcc_sweep(const OffT* __restrict__ off, const int* __restrict_
 // heads).  A non-root head is an articulation point; a tree root is one iff
 // it heads two different labels.
 __global__ void k_bcc_heads(const int4* __restrict__ rec, const int* __restrict__ lab, int n, int* __restrict__ head,
-                            int* rootlab, uint8_t* __restrict__ ap) {
+                            uint8_t* __restrict__ heads, int* rootlab, uint8_t* __restrict__ ap) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int p = rec[v].z;
@@ -724,6 +781,7 @@ __global__ void k_bcc_heads(const int4* __restrict__ rec, const int* __restrict_
   const int L = lab[v];
   if (L == lab[p]) return;
   head[L] = p;
+  heads[p] = 1;
   if (ap == nullptr) return;
   if (rec[p].z >= 0) {
     ap[p] = 1;
@@ -743,77 +801,130 @@ __device__ __forceinline__ int graph_of(const int* __restrict__ vbegin, int G, i
   return lo;
 }
 
-// Every BCC label L (a Last-CC root that is not a tree root) marks the row of
-// its smallest vertex min(L, head(L)), where its smallest arc lies; counts BCCs.
-__global__ void k_bcc_cand(const int4* __restrict__ rec, const int* __restrict__ lab, const int* __restrict__ head,
-                           int n, uint8_t* __restrict__ cand, const int* __restrict__ vbegin, int G,
-                           int64_t* nbcc) {
+// A BCC label is a Last-CC root that is not a tree root (a tree root is a
+// singleton of the skeleton and heads, but never labels, a BCC).
+__device__ __forceinline__ bool is_bcc_label(const int4* __restrict__ rec, const int* __restrict__ lab, int v) {
+  return lab[v] == v && rec[v].z >= 0;
+}
+
+// BCC count: per-block partial sums (one graph) or per-graph counters.
+__global__ void k_bcc_count(const int4* __restrict__ rec, const int* __restrict__ lab, int n,
+                            const int* __restrict__ vbegin, int G, int* __restrict__ bsum, int64_t* nbcc) {
+  __shared__ int part[BLOCK / WAVE];
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  bool is_label = false;
-  if (v < n && lab[v] == v && rec[v].z >= 0) {
-    is_label = true;
-    int h = head[v];
-    cand[(h >= 0 && h < v) ? h : v] = 1;
-  }
-  if (nbcc == nullptr) return;
+  const bool is_label = v < n && is_bcc_label(rec, lab, v);
   if (G <= 1) {
     uint64_t m = __ballot(is_label);
-    if (lane_id() == 0 && m) atomicAdd((unsigned long long*)nbcc, (unsigned long long)__popcll(m));
-  } else if (is_label) {
-    atomicAdd((unsigned long long*)(nbcc + graph_of(vbegin, G, v)), 1ull);
-  }
-}
-
-template <typename OffT>
-__global__ void k_bcc_minid(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                            const int* __restrict__ tile_row, int tw, const uint8_t* __restrict__ cand,
-                            const int4* __restrict__ rec, const int* __restrict__ lab, const int* __restrict__ head,
-                            int* __restrict__ minid) {
-  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
-    if (!ok || !cand[x]) return;
-    const int y = adj[a];
-    if (y == x) return;
-    const int fx = rec[x].x, fy = rec[y].x;
-    const int L = lab[fy > fx ? y : x];
-    const int h = head[L];
-    if (((h >= 0 && h < L) ? h : L) == x) atomicMin(minid + L, (int)a);
-  });
-}
-
-__global__ void k_bcc_canon(const int4* __restrict__ rec, const int* __restrict__ lab, const int* __restrict__ minid,
-                            int n, const int* __restrict__ vbegin, int G, const void* off, int off64,
-                            int2* __restrict__ fc) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int4 r = rec[v];
-  int canon = -1;
-  if (r.z >= 0) {
-    canon = minid[lab[v]];
-    if (G > 1) {
-      int g = graph_of(vbegin, G, v);
-      int vb = vbegin[g];
-      int64_t base = off64 ? ((const int64_t*)off)[vb] : (int64_t)((const int*)off)[vb];
-      canon -= (int)base;
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int w = 0; w < BLOCK / WAVE; ++w) t += part[w];
+      bsum[blockIdx.x] = t;
     }
+    return;
   }
-  fc[v] = make_int2(r.x, canon);
+  // several graphs: one atomic per wave when the wave's labels share a graph
+  const int g = v < n ? graph_of(vbegin, G, v) : -1;
+  const int g0 = __shfl(g, 0, WAVE);
+  const bool same = __all(g == g0 || v >= n);
+  if (same) {
+    uint64_t m = __ballot(is_label);
+    if (lane_id() == 0 && m) atomicAdd((unsigned long long*)(nbcc + g0), (unsigned long long)__popcll(m));
+  } else if (is_label) {
+    atomicAdd((unsigned long long*)(nbcc + g), 1ull);
+  }
 }
 
-// Arc x->y belongs to the BCC of its deeper endpoint's label.
-template <typename OffT>
-__global__ void k_bcc_output(const OffT* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                             const int* __restrict__ tile_row, int tw, const int2* __restrict__ fc,
-                             int* __restrict__ out) {
+__global__ void __launch_bounds__(1024) k_sum_blocks(const int* __restrict__ bsum, int nblocks, int64_t* out) {
+  __shared__ long long part[1024 / WAVE];
+  long long t = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) t += bsum[i];
+  for (int o = WAVE / 2; o > 0; o >>= 1) t += __shfl_down(t, o, WAVE);
+  if (lane_id() == 0) part[threadIdx.x / WAVE] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long s = 0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) s += part[w];
+    *out = s;
+  }
+}
+
+// Pass 1 over the arcs.  Arc x->y lies in the BCC whose vertex set holds both
+// endpoints: the label of x when l[x] == l[y] or y heads l[x] (x's BCC is
+// {l == l[x]} plus its head), else the label of y (then x heads l[y]).  Two
+// BCCs share at most one vertex, so this is the edge's unique BCC.  A vertex
+// that heads no BCC lies in exactly one BCC, so its row needs no gather.  The
+// smallest arc of BCC L lies in the row of its smallest vertex
+// m(L) = min(L, head(L)) (L is the smallest non-head vertex, the Last-CC
+// root); arcs of that row update minid[L].  The raw label goes to out[].
+__global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                            const int* __restrict__ tile_row, int tw, const int* __restrict__ lab,
+                            const int* __restrict__ head, const uint8_t* __restrict__ heads, int* __restrict__ minid,
+                            int* __restrict__ out) {
   arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
     if (!ok) return;
     const int y = adj[a];
-    int lbl = -1;
-    if (y != x) {
-      const int2 cx = fc[x], cy = fc[y];
-      lbl = cy.x > cx.x ? cy.y : cx.y;
+    if (y == x) {
+      out[a] = -1;
+      return;
     }
-    out[a] = lbl;
+    const int lx = lab[x];
+    const int hx = head[lx];
+    int L, m;
+    if (!heads[x]) {
+      L = lx;
+      m = (hx >= 0 && hx < lx) ? hx : lx;
+    } else {
+      const int ly = lab[y];
+      if (ly == lx || hx == y) {
+        L = lx;
+        m = (hx >= 0 && hx < lx) ? hx : lx;
+      } else {
+        L = ly;
+        const int hy = head[ly];
+        m = (hy >= 0 && hy < ly) ? hy : ly;
+      }
+    }
+    out[a] = L;
+    if (m == x) atomicMin(minid + L, (int)a);
   });
+}
+
+// canon[L] = smallest arc of BCC L, made graph-local for batches.
+__global__ void k_bcc_canon(const int4* __restrict__ rec, const int* __restrict__ lab,
+                            const int* __restrict__ minid, int n, const int* __restrict__ vbegin, int G,
+                            const int* __restrict__ off, int* __restrict__ canon) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || !is_bcc_label(rec, lab, v)) return;
+  int c = minid[v];
+  if (G > 1) c -= off[vbegin[graph_of(vbegin, G, v)]];
+  canon[v] = c;
+}
+
+// Pass 2: raw label -> canonical label (elementwise, 4 arcs per thread).
+__global__ void k_bcc_remap4(int4* __restrict__ out, int64_t n4, const int* __restrict__ canon) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    int4 q = out[i];
+    q.x = q.x < 0 ? -1 : canon[q.x];
+    q.y = q.y < 0 ? -1 : canon[q.y];
+    q.z = q.z < 0 ? -1 : canon[q.z];
+    q.w = q.w < 0 ? -1 : canon[q.w];
+    out[i] = q;
+  }
+}
+
+__global__ void k_bcc_remap1(int* __restrict__ out, int64_t begin, int64_t end, const int* __restrict__ canon) {
+  int64_t i = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= end) return;
+  int q = out[i];
+  out[i] = q < 0 ? -1 : canon[q];
+}
+
+// int64 offsets are narrowed once (every offset is < 2^31 because arcs are).
+__global__ void k_narrow_offsets(const int64_t* __restrict__ in, int64_t count, int* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int)in[i];
 }
 
 // ------------------------------------------------------------ host driver
@@ -821,18 +932,39 @@ inline unsigned grid_for(int64_t count, int block = BLOCK) { return (unsigned)cd
 
 struct Ctx {
   hipStream_t st;
+  fastbcc_trace* trace = nullptr;
   bool ok = true;
+  hipEvent_t pending_start = nullptr;
   void check() {
     if (hipGetLastError() != hipSuccess) ok = false;
   }
+  void before() {
+    pending_start = nullptr;
+    if (!trace) return;
+    if (trace->used + 2 > trace->pool.size()) {
+      ++trace->dropped;
+      return;
+    }
+    pending_start = trace->pool[trace->used++];
+    if (hipEventRecord(pending_start, st) != hipSuccess) ok = false;
+  }
+  void after(const char* name) {
+    if (!trace || !pending_start) return;
+    hipEvent_t e = trace->pool[trace->used++];
+    if (hipEventRecord(e, st) != hipSuccess) ok = false;
+    trace->pending.push_back({name, pending_start, e});
+    pending_start = nullptr;
+  }
 };
 
-#define LAUNCH(ctx, kern, grid, block, ...)                                 \
-  do {                                                                      \
-    if ((grid) > 0) {                                                       \
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (ctx).st, __VA_ARGS__); \
-      (ctx).check();                                                        \
-    }                                                                       \
+#define LAUNCH(ctx, kern, grid, block, ...)                                              \
+  do {                                                                                   \
+    if ((grid) > 0) {                                                                    \
+      (ctx).before();                                                                    \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (ctx).st, __VA_ARGS__);      \
+      (ctx).check();                                                                     \
+      (ctx).after(#kern);                                                                \
+    }                                                                                    \
   } while (0)
 
 void fill_i32(Ctx& c, int* p, int v, int64_t count) {
@@ -859,52 +991,34 @@ void scan_inplace(Ctx& c, int* data, int64_t max_count, const int* count_dev, in
   LAUNCH(c, k_scan_down, (unsigned)nbk, SCAN_BLOCK, data, data, max_count, count_dev, tmp);
 }
 
-template <typename OffT>
-fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* adj, int G, const int* vbegin,
-                          int* out_label, uint8_t* out_ap, int64_t* out_nbcc, void* ws, size_t ws_bytes,
-                          uint32_t flags, hipStream_t st) {
-  Tune tune;
-  if (!decode_flags(flags, tune)) return FASTBCC_ERR_INVALID_ARGUMENT;
-  if (n64 < 0 || A < 0) return FASTBCC_ERR_INVALID_ARGUMENT;
-  if (n64 >= (int64_t(1) << 30) || A >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
-  if (n64 > 0 && off == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
-  if (A > 0 && (adj == nullptr || out_label == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
-  if (G > 1 && vbegin == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
-  const Layout L = make_layout(n64, A);
-  if (ws == nullptr || ws_bytes < L.total) return FASTBCC_ERR_WORKSPACE_TOO_SMALL;
-  if (((uintptr_t)ws & 255) != 0) return FASTBCC_ERR_INVALID_ARGUMENT;
-
-  Ctx c{st};
-  char* w = (char*)ws;
+// The solve proper, on int32 offsets.
+fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* off, const int* adj, int G,
+                          const int* vbegin, int* out_label, uint8_t* out_ap, int64_t* out_nbcc, char* w,
+                          const Tune& tune, bool validate) {
   auto I = [&](size_t o) { return (int*)(w + o); };
   int* scal = I(L.scalars);
-  const int n = (int)n64;
-  const int GG = G < 1 ? 1 : G;
-
-  fill_i32(c, scal, 0, S_COUNT);
-  if (out_nbcc) {
-    LAUNCH(c, k_fill_i64, 1, BLOCK, out_nbcc, (int64_t)0, (int64_t)GG);
-  }
-  if (n == 0) return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
-
   const int tw = tune.tile_windows;
   const int64_t tile_arcs = (int64_t)WAVE * tw;
   const int64_t ntiles = cdiv(A, tile_arcs);
   int* tile_row = I(L.tile_row);
   const unsigned tile_grid = (unsigned)cdiv(ntiles * WAVE, BLOCK);
-  LAUNCH(c, (k_tile_rows<OffT>), grid_for(ntiles), BLOCK, off, n, A, tile_arcs, ntiles, tile_row);
+  LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, off, n, A, (const int*)nullptr, tile_arcs, tile_row);
+  int *foff = I(L.foff), *frank = I(L.frank), *frow = I(L.frow), *fstart = I(L.fstart), *ftile = I(L.ftile);
+  int* frows = frank + n;  // number of compacted frontier rows (scan total)
+  // frontier virtual CSR of the rows a sweep still has to visit
+  auto frontier = [&](const int* comp, int slot) {
+    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, tune.sample_rounds, n, foff, frank);
+    scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
+    scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
+    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, frow, fstart);
+    LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
+  };
 
-  if (flags & FASTBCC_FLAG_VALIDATE) {
-    LAUNCH(c, (k_validate_rows<OffT>), grid_for(n + 1), BLOCK, off, n, A, scal + S_STATUS);
+  if (validate) {
     int h = 0;
-    if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return FASTBCC_ERR_HIP;
-    if (h != 0) return FASTBCC_ERR_INVALID_GRAPH;
-    LAUNCH(c, (k_tile_rows<OffT>), grid_for(ntiles), BLOCK, off, n, A, tile_arcs, ntiles, tile_row);
-    LAUNCH(c, (k_validate_arcs<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, scal + S_STATUS);
-    if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    LAUNCH(c, k_validate_arcs, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, scal + S_STATUS);
+    if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, c.st) != hipSuccess ||
+        hipStreamSynchronize(c.st) != hipSuccess)
       return FASTBCC_ERR_HIP;
     if (h != 0) return FASTBCC_ERR_INVALID_GRAPH;
   }
@@ -914,11 +1028,11 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
 
   // ---- First-CC (spanning forest)
   LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
-  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, (k_cc_sample<OffT>), gn, BLOCK, off, adj, n, r, cc, hu, hv);
+  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, k_cc_sample, gn, BLOCK, off, adj, n, r, cc, hu, hv);
   LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
-  LAUNCH(c, (k_cc_sweep<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, tune.sample_rounds, cc, hu, hv,
-         scal);
+  frontier(cc, S_BIG_CC);
+  LAUNCH(c, k_cc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, tune.sample_rounds, cc, hu, hv);
   LAUNCH(c, k_compress, gn, BLOCK, cc, n);
 
   // ---- Rooting
@@ -931,7 +1045,7 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
   LAUNCH(c, k_root_flags, gn, BLOCK, cc, n, rootidx);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   LAUNCH(c, k_root_list, gn, BLOCK, cc, rootidx, n, roots);
-  const int64_t nodes_max = 2 * n64;  // C + 2T <= 2n - 1
+  const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
   const unsigned gnode = grid_for(nodes_max);
   LAUNCH(c, k_euler_next, gnode, BLOCK, toff, tadj, twin, cc, rootidx, roots, n, next);
 
@@ -955,52 +1069,112 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
   int* eflag = I(L.eflag);
   LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, toff, twin, n, ol, vin, pos);
   LAUNCH(c, k_enter_flags, gnode, BLOCK, rootidx, toff, twin, n, pos, eflag, scal + S_STATUS);
-  // number of list nodes, for the scan of entry flags
-  int* nl_dev = scal + 8;
+  int* nl_dev = scal + 8;  // number of list nodes, for the scan of entry flags
   LAUNCH(c, k_node_count, 1, 1, rootidx, toff, n, nl_dev);
   scan_inplace(c, eflag, nodes_max, nl_dev, tmp, scal + 9);
 
   // ---- Tagging
-  int *first = I(L.first), *last = I(L.last), *par = I(L.par), *w1 = I(L.w1), *w2 = I(L.w2);
-  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, n, pos, eflag, first, last, par, w1, w2,
-         scal + S_STATUS);
-  LAUNCH(c, (k_tag_sweep<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, w1, w2);
+  int *first = I(L.first), *w1 = I(L.w1), *w2 = I(L.w2);
+  int4* rec = (int4*)(w + L.rec);
+  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, n, pos, eflag, first, rec, scal + S_STATUS);
+  fill_i32(c, w1, INT32_MAX, n);
+  fill_i32(c, w2, INT32_MIN, n);
+  LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, w1, w2);
   int *W1 = I(L.W1), *W2 = I(L.W2), *pre1 = I(L.pre1), *suf1 = I(L.suf1), *pre2 = I(L.pre2), *suf2 = I(L.suf2);
   int *tmin = I(L.tmin), *tmax = I(L.tmax);
   LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, scal + S_STATUS);
   LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W1, W2, n, L.nb, pre1, suf1, pre2, suf2, tmin,
          tmax);
   for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tmin, tmax, L.nb, j);
-  int4* rec = (int4*)(w + L.rec);
-  LAUNCH(c, k_rmq_query, gn, BLOCK, first, last, par, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec,
-         scal + S_STATUS);
+  LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, scal + S_STATUS);
 
   // ---- Last-CC on the implicit skeleton
   int* lab = I(L.lab);
   LAUNCH(c, k_lcc_init, gn, BLOCK, lab, n);
   LAUNCH(c, k_lcc_tree, gn, BLOCK, rec, n, lab);
-  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, (k_lcc_sample<OffT>), gn, BLOCK, off, adj, rec, n, r, lab);
+  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, k_lcc_sample, gn, BLOCK, off, adj, rec, n, r, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
-  LAUNCH(c, (k_lcc_sweep<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, tune.sample_rounds, rec, lab, scal);
+  frontier(lab, S_BIG_LAB);
+  LAUNCH(c, k_lcc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, tune.sample_rounds, rec, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
 
   // ---- heads, articulation points, canonical labels
-  int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid);
-  uint8_t* cand = (uint8_t*)(w + L.cand);
-  int2* fc = (int2*)(w + L.fc);
+  int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid), *canon = I(L.canon), *bsum = I(L.bsum);
+  uint8_t* heads = (uint8_t*)(w + L.heads);
   fill_i32(c, head, -1, n);
+  fill_u8(c, heads, 0, n);
   fill_i32(c, rootlab, -1, n);
   fill_i32(c, minid, INT32_MAX, n);
-  fill_u8(c, cand, 0, n);
   if (out_ap) fill_u8(c, out_ap, 0, n);
-  LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, rootlab, out_ap);
-  LAUNCH(c, k_bcc_cand, gn, BLOCK, rec, lab, head, n, cand, vbegin, G, out_nbcc);
-  LAUNCH(c, (k_bcc_minid<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, cand, rec, lab, head, minid);
-  LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, (const void*)off,
-         (int)(sizeof(OffT) == 8), fc);
-  LAUNCH(c, (k_bcc_output<OffT>), tile_grid, BLOCK, off, adj, n, A, tile_row, tw, fc, out_label);
+  LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, heads, rootlab, out_ap);
+  if (out_nbcc) {
+    LAUNCH(c, k_bcc_count, gn, BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
+    if (G <= 1) LAUNCH(c, k_sum_blocks, 1, 1024, bsum, (int)gn, out_nbcc);
+  }
+  LAUNCH(c, k_bcc_label, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, lab, head, heads, minid, out_label);
+  LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, canon);
+  if (A > 0) {
+    if (((uintptr_t)out_label & 15) == 0) {
+      const int64_t n4 = A / 4;
+      unsigned g4 = grid_for(n4);
+      if (g4 > 65536) g4 = 65536;
+      LAUNCH(c, k_bcc_remap4, g4, BLOCK, (int4*)out_label, n4, canon);
+      LAUNCH(c, k_bcc_remap1, grid_for(A - 4 * n4), BLOCK, out_label, 4 * n4, A, canon);
+    } else {
+      LAUNCH(c, k_bcc_remap1, grid_for(A), BLOCK, out_label, (int64_t)0, A, canon);
+    }
+  }
   return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+}
+
+template <typename OffT>
+fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* adj, int G, const int* vbegin,
+                          int* out_label, uint8_t* out_ap, int64_t* out_nbcc, void* ws, size_t ws_bytes,
+                          uint32_t flags, hipStream_t st, fastbcc_trace* trace = nullptr) {
+  Tune tune;
+  if (!decode_flags(flags, tune)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n64 < 0 || A < 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n64 >= (int64_t(1) << 30) || A >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  if (n64 > 0 && off == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (A > 0 && (adj == nullptr || out_label == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (G > 1 && vbegin == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  const Layout L = make_layout(n64, A);
+  if (ws == nullptr || ws_bytes < L.total) return FASTBCC_ERR_WORKSPACE_TOO_SMALL;
+  if (((uintptr_t)ws & 255) != 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+
+  Ctx c{st, trace};
+  char* w = (char*)ws;
+  int* scal = (int*)(w + L.scalars);
+  const int n = (int)n64;
+  const int GG = G < 1 ? 1 : G;
+
+  fill_i32(c, scal, 0, S_COUNT);
+  if (out_nbcc) {
+    LAUNCH(c, k_fill_i64, 1, BLOCK, out_nbcc, (int64_t)0, (int64_t)GG);
+  }
+  if (n == 0) return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+
+  const bool validate = (flags & FASTBCC_FLAG_VALIDATE) != 0;
+  if (validate) {
+    LAUNCH(c, k_validate_rows<OffT>, grid_for(n64 + 1), BLOCK, off, n, A, scal + S_STATUS);
+    int h = 0;
+    if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FASTBCC_ERR_HIP;
+    if (h != 0) return FASTBCC_ERR_INVALID_GRAPH;
+  }
+  const int* off32;
+  if (sizeof(OffT) == 8) {
+    int* o = (int*)(w + L.off32);
+    unsigned g = grid_for(n64 + 1);
+    if (g > 65536) g = 65536;
+    LAUNCH(c, k_narrow_offsets, g, BLOCK, (const int64_t*)off, n64 + 1, o);
+    off32 = o;
+  } else {
+    off32 = (const int*)off;
+  }
+  return solve_core(L, c, n, A, off32, adj, G, vbegin, out_label, out_ap, out_nbcc, w, tune, validate);
 }
 
 }  // namespace
@@ -1046,6 +1220,87 @@ fastbcc_status fastbcc_read_device_status(const void* workspace, void* stream, i
   if (hipStreamSynchronize(st) != hipSuccess) return FASTBCC_ERR_HIP;
   *out_status = h;
   return FASTBCC_OK;
+}
+
+fastbcc_status fastbcc_solve_traced(int32_t num_graphs, const int32_t* graph_vbegin, int64_t n, int64_t num_arcs,
+                                    const void* offsets, int32_t offsets_bits, const int32_t* adj,
+                                    int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc, void* workspace,
+                                    size_t workspace_bytes, uint32_t flags, void* stream, fastbcc_trace* trace) {
+  if (num_graphs < 1 || (num_graphs > 1 && graph_vbegin == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (offsets_bits == 32)
+    return solve_impl<int>(n, num_arcs, (const int*)offsets, adj, num_graphs, graph_vbegin, out_edge_label, out_is_ap,
+                           out_num_bcc, workspace, workspace_bytes, flags, (hipStream_t)stream, trace);
+  if (offsets_bits == 64)
+    return solve_impl<int64_t>(n, num_arcs, (const int64_t*)offsets, adj, num_graphs, graph_vbegin, out_edge_label,
+                               out_is_ap, out_num_bcc, workspace, workspace_bytes, flags, (hipStream_t)stream, trace);
+  return FASTBCC_ERR_INVALID_ARGUMENT;
+}
+
+fastbcc_trace* fastbcc_trace_create(int32_t max_launches) {
+  if (max_launches < 1) return nullptr;
+  fastbcc_trace* t = new fastbcc_trace;
+  t->pool.resize((size_t)max_launches * 2);
+  for (auto& e : t->pool) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+  }
+  for (auto e : t->pool)
+    if (!e) {
+      fastbcc_trace_destroy(t);
+      return nullptr;
+    }
+  return t;
+}
+
+void fastbcc_trace_destroy(fastbcc_trace* t) {
+  if (!t) return;
+  for (auto e : t->pool)
+    if (e) (void)hipEventDestroy(e);
+  delete t;
+}
+
+fastbcc_status fastbcc_trace_collect(fastbcc_trace* t) {
+  if (!t) return FASTBCC_ERR_INVALID_ARGUMENT;
+  fastbcc_status rc = FASTBCC_OK;
+  for (auto& p : t->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+      rc = FASTBCC_ERR_HIP;
+      continue;
+    }
+    bool found = false;
+    for (auto& tot : t->totals)
+      if (strcmp(tot.name, p.name) == 0) {
+        tot.ms += ms;
+        tot.launches += 1;
+        found = true;
+        break;
+      }
+    if (!found) t->totals.push_back({p.name, (double)ms, 1});
+  }
+  t->pending.clear();
+  t->used = 0;
+  return rc;
+}
+
+int32_t fastbcc_trace_count(const fastbcc_trace* t) { return t ? (int32_t)t->totals.size() : 0; }
+
+fastbcc_status fastbcc_trace_entry(const fastbcc_trace* t, int32_t i, const char** name, double* total_ms,
+                                   int64_t* launches) {
+  if (!t || i < 0 || (size_t)i >= t->totals.size()) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (name) *name = t->totals[i].name;
+  if (total_ms) *total_ms = t->totals[i].ms;
+  if (launches) *launches = t->totals[i].launches;
+  return FASTBCC_OK;
+}
+
+int64_t fastbcc_trace_dropped(const fastbcc_trace* t) { return t ? t->dropped : 0; }
+
+void fastbcc_trace_reset(fastbcc_trace* t) {
+  if (!t) return;
+  t->totals.clear();
+  t->dropped = 0;
 }
 
 const char* fastbcc_status_string(fastbcc_status s) {
