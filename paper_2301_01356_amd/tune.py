@@ -1,0 +1,118 @@
+"""Autotuner for the solve's tuning fields.
+
+The C ABI exposes three speed-only knobs in its flags word (they never change
+results; a GPU test checks that): the list-ranking ruler spacing, the number
+of union-find sampling rounds before the full connectivity sweep (0 turns
+sampling off, i.e. a different union-find schedule), and the arc-tile size
+(64-arc windows per wave, i.e. work per wave).  The tuner times candidates by
+coordinate descent on the real input and keeps the winner per
+(GPU arch, size bucket, degree-skew class) in a JSON cache.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Callable, Dict, Optional
+
+import numpy as np
+
+from . import _native as N
+
+DEFAULT_CACHE = os.environ.get("FASTBCC_TUNE_CACHE", os.path.expanduser("~/.cache/fastbcc_tune.json"))
+
+RULER = (4, 5, 6, 7, 8)
+SAMPLE = (0, 1, 2)
+TILE = (2, 3, 4, 5)
+START = {"ruler": 5, "sample": 2, "tile": 2}
+
+
+def skew_class(degrees: np.ndarray) -> str:
+    """'skewed' when the largest degree dwarfs the mean (power-law graphs),
+    else 'flat' (lattices, k-NN, road-like graphs)."""
+    d = np.asarray(degrees)
+    if d.size == 0:
+        return "flat"
+    mean = max(float(d.mean()), 1e-9)
+    return "skewed" if float(d.max()) > 64.0 * mean else "flat"
+
+
+def bucket(x: int) -> int:
+    return int(math.floor(math.log2(max(int(x), 1))))
+
+
+def cache_key(arch: str, n: int, arcs: int, graphs: int, skew: str) -> str:
+    return f"{arch}|n2^{bucket(n)}|a2^{bucket(arcs)}|g2^{bucket(graphs)}|{skew}"
+
+
+def encode(cfg: Dict[str, int]) -> int:
+    return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"])
+
+
+class Tuner:
+    def __init__(self, cache_path: Optional[str] = DEFAULT_CACHE):
+        self.cache_path = cache_path
+        self.cache: Dict[str, Dict[str, int]] = {}
+        if cache_path and os.path.exists(cache_path):
+            try:
+                with open(cache_path) as f:
+                    self.cache = json.load(f)
+            except (OSError, ValueError):
+                self.cache = {}
+
+    def save(self) -> None:
+        if not self.cache_path:
+            return
+        os.makedirs(os.path.dirname(self.cache_path) or ".", exist_ok=True)
+        tmp = self.cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.cache_path)
+
+    def lookup(self, key: str) -> Optional[int]:
+        cfg = self.cache.get(key)
+        return encode(cfg) if cfg else None
+
+    def tune(self, key: str, time_ms: Callable[[int], float], reps: int = 3, force: bool = False) -> int:
+        """Coordinate descent over (sample, tile, ruler); ``time_ms(flags)``
+        runs one solve and returns its duration.  Returns the best flags."""
+        if not force and key in self.cache:
+            return encode(self.cache[key])
+        cfg = dict(START)
+        measured: Dict[tuple, float] = {}
+
+        def cost(c):
+            t = tuple(sorted(c.items()))
+            if t not in measured:
+                f = encode(c)
+                time_ms(f)  # warm
+                measured[t] = float(np.median([time_ms(f) for _ in range(reps)]))
+            return measured[t]
+
+        for _ in range(2):
+            changed = False
+            for knob, values in (("sample", SAMPLE), ("tile", TILE), ("ruler", RULER)):
+                best_v, best_t = cfg[knob], cost(cfg)
+                for v in values:
+                    c = dict(cfg, **{knob: v})
+                    t = cost(c)
+                    if t < best_t:
+                        best_v, best_t = v, t
+                if best_v != cfg[knob]:
+                    cfg[knob] = best_v
+                    changed = True
+            if not changed:
+                break
+        self.cache[key] = dict(cfg, ms=round(cost(cfg), 4))
+        self.save()
+        return encode(cfg)
+
+
+def gpu_arch() -> str:
+    try:
+        import torch
+
+        p = torch.cuda.get_device_properties(0)
+        return getattr(p, "gcnArchName", p.name).split(":")[0]
+    except Exception:
+        return "unknown"

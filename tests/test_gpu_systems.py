@@ -1,0 +1,84 @@
+"""GPU tests of the batched (HIP-graph replay) and serving paths."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2301_01356_amd import gen, solve
+from paper_2301_01356_amd.batch import BatchedSolver
+from paper_2301_01356_amd.serve import Request, Server, hip_slots, latency_summary, poisson_arrivals
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def check_oracle(g, lab, ap, nb, what):
+    olab, oap, onb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+    assert np.array_equal(lab, olab), f"{what}: labels differ"
+    assert np.array_equal(ap, oap), f"{what}: articulation points differ"
+    assert nb == onb, f"{what}: num_bcc {nb} != {onb}"
+
+
+def test_graph_replay_matches_oracle_across_batches():
+    batch_a = [gen.mixed(51, i, 8, 2500, 4.0, 16.0) for i in range(24)]
+    batch_b = [gen.mixed(52, i, 8, 4000, 4.0, 16.0) for i in range(9)]
+    cap_v = 1 + max(sum(g.n for g in batch_a), sum(g.n for g in batch_b)) + 100
+    cap_a = max(sum(g.num_arcs for g in batch_a), sum(g.num_arcs for g in batch_b)) + 1000
+    s = BatchedSolver(cap_v, cap_a, 32, device=DEV, use_graph=True)
+    for rnd, batch in enumerate([batch_a, batch_b, batch_a, batch_b, batch_a]):
+        note(f"replay {rnd}: {len(batch)} graphs")
+        res = s.solve(batch)
+        assert s.graph is not None
+        # the program's own eager work between replays
+        x = torch.arange(1 << 20, device=DEV, dtype=torch.int64).sum().item()
+        assert x == (1 << 20) * ((1 << 20) - 1) // 2
+        torch.cuda.synchronize()
+        for i, (g, r) in enumerate(zip(batch, res)):
+            check_oracle(g, r.edge_label, r.is_ap, r.num_bcc, f"replay {rnd} graph {i}")
+
+
+def test_graph_replay_equals_eager():
+    batch = [gen.mixed(53, i, 8, 3000, 4.0, 16.0) for i in range(16)]
+    cap_v = sum(g.n for g in batch) + 64
+    cap_a = sum(g.num_arcs for g in batch) + 64
+    note("eager vs graph")
+    eager = BatchedSolver(cap_v, cap_a, 16, device=DEV, use_graph=False).solve(batch)
+    graph_s = BatchedSolver(cap_v, cap_a, 16, device=DEV, use_graph=True)
+    for rep in range(3):
+        got = graph_s.solve(batch)
+        for e, g in zip(eager, got):
+            assert np.array_equal(e.edge_label, g.edge_label) and np.array_equal(e.is_ap, g.is_ap)
+            assert e.num_bcc == g.num_bcc
+
+
+def test_serving_each_result_same_alone_and_in_the_mix():
+    count = 40
+    reqs = []
+    arr = poisson_arrivals(count, 400.0, 5)
+    for i in range(count):
+        reqs.append(Request(i, gen.mixed(55, i, 64, 60000, 4.0, 32.0), float(arr[i])))
+    slots = hip_slots(3, cap_v=200000, cap_a=4_000_000, cap_g=16, device=DEV)
+    srv = Server(slots, hbm_budget=8 << 30)
+    note(f"serving {count} requests on {len(slots)} slots")
+    comps = srv.run(reqs)
+    assert srv.stats["batches"] < count  # requests were batched together
+    for r, c in zip(reqs, comps):
+        assert c.ok, c.error
+        off = torch.from_numpy(r.graph.offsets32()).to(DEV)
+        adj = torch.from_numpy(r.graph.adj).to(DEV)
+        alone = solve(off, adj)
+        torch.cuda.synchronize()
+        assert np.array_equal(alone.edge_label.cpu().numpy(), c.edge_label), f"request {r.rid}: labels differ"
+        assert np.array_equal(alone.is_ap.cpu().numpy(), c.is_ap), f"request {r.rid}: APs differ"
+        assert int(alone.num_bcc.item()) == c.num_bcc
+        if r.rid % 5 == 0:
+            check_oracle(r.graph, c.edge_label, c.is_ap, c.num_bcc, f"request {r.rid}")
+    s = latency_summary(comps)
+    note(f"p50 {s['p50_ms']:.2f} ms p99 {s['p99_ms']:.2f} ms")
