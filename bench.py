@@ -44,22 +44,43 @@ def workload_graph(name):
 
 # Algorithmic bytes per launch: each array touched the minimal number of
 # times the kernel's definition needs, 4 bytes per gathered word (no cache
-# lines).  o = offset width, A = arcs, n = vertices.
-def alg_bytes(kernel, n, A, o):
-    k = kernel.split("<")[0].strip("()")
+# lines).  Offsets are read as int32 inside the solve (int64 input offsets are
+# narrowed once).  A = arcs, n = vertices, h = arcs in rows of BCC heads.
+def alg_bytes(kernel, n, A, h=None):
+    h = A if h is None else h
     models = {
         # offsets + adjacency + first[y] per arc + w1/w2 read-modify-write per row
-        "k_tag_sweep": o * (n + 1) + 8 * A + 16 * n,
-        # offsets + adjacency + {first, label}[y] per arc + label write per arc + {first, label}[x] per row
-        "k_bcc_output": o * (n + 1) + 16 * A + 8 * n,
-        # offsets + adjacency + rec[y] (first, last, parent: 12 B) per arc + lab[x] per row
-        "k_lcc_sweep": o * (n + 1) + 16 * A + 4 * n,
-        # offsets + adjacency + cc[x] per row
-        "k_cc_sweep": o * (n + 1) + 4 * A + 4 * n,
-        # offsets + adjacency of candidate rows (upper bound: all) + rec/lab gathers
-        "k_bcc_minid": o * (n + 1) + 12 * A + n,
+        "k_tag_sweep": 4 * (n + 1) + 8 * A + 16 * n,
+        # offsets + adjacency + raw label write per arc + lab[y] per arc of a head row
+        # + lab/head/heads of the row vertex
+        "k_bcc_label": 4 * (n + 1) + 8 * A + 4 * h + 9 * n,
+        # label read + label write per arc (canonical-label lookups hit the few hot labels)
+        "k_bcc_remap4": 8 * A,
     }
-    return models.get(k)
+    return models.get(kernel)
+
+
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch) on R-MAT scale 25, and the factors a 1 GiB
+# device copy gives the same counters (known bytes / counter).  Valid only for
+# the kernel sources they were taken on (hash below); otherwise traffic = null.
+COUNTERS = {
+    "src_sha": "340a1f2047497f7d",
+    "workload": "rmat25",
+    "copy_factor": {"fetch": 2.0, "write": 1.0},
+    "k_tag_sweep": {"fetch_kib": 57134946.3, "write_kib": 1279842.8},
+}
+
+
+def kernel_src_sha():
+    import hashlib
+
+    d = os.path.join(ROOT, "paper_2301_01356_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("fastbcc.hip", "prims.hpp"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(sample_scale):
@@ -134,14 +155,15 @@ def bench_batch(args):
     solver.graph = None
     solver._ensure_graph()
     s = solver.stream
-    for _ in range(args.warmup):
-        solver.graph.replay()
-    s.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(args.steps):
-        solver.graph.replay()
-    e1.record(s)
+    with torch.cuda.stream(s):  # a graph replays on the current stream
+        for _ in range(args.warmup):
+            solver.graph.replay()
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.steps):
+            solver.graph.replay()
+        e1.record(s)
     e1.synchronize()
     ms_batch = e0.elapsed_time(e1) / args.steps
     log(f"[bench] batched (graph replay): {ms_batch:.3f} ms per batch of {G}")
@@ -284,12 +306,27 @@ def main():
     ap.add_argument("--cpu-sample-scale", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=lambda s: int(s, 0), default=0)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-systems", action="store_true", help="skip the batched and serving legs")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the design notes describe how the solve would shard).", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration_mib:
+        import torch
+
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: 3 x {nb} bytes read + {nb} bytes written")
+        del src, dst
     if args.workload == "batch":
         print(json.dumps(bench_batch(args)), flush=True)
         return
@@ -319,6 +356,24 @@ def main():
     )
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+
+    tuned = {}
+    if not args.flags and not args.no_tune:
+        import numpy as np
+
+        from paper_2301_01356_amd.tune import cache_key, gpu_arch, skew_class
+
+        def run_once(f):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            solve(off, adj, out=out, workspace=ws, flags=f, stream=stream)
+            a1.record(stream)
+            a1.synchronize()
+            return a0.elapsed_time(a1)
+
+        key = cache_key(gpu_arch(), n, A, 1, skew_class(np.diff(g.offsets)))
+        args.flags, tuned = tuned_flags(key, run_once)
+        log(f"[bench] tuned flags {args.flags:#x}: {tuned}")
 
     for _ in range(args.warmup):
         solve(off, adj, out=out, workspace=ws, flags=args.flags, stream=stream)
@@ -350,14 +405,19 @@ def main():
     for name, (t, cnt) in rows[:25]:
         log(f"  {t / args.steps:9.3f} ms/step  {cnt // args.steps:4d} launches/step  {name}")
     dom_name, (dom_ms, dom_cnt) = rows[0]
-    o = 8 if off64 else 4
     roofline = None
     for name, (t, cnt) in rows:
-        b = alg_bytes(name, n, A, o)
+        b = alg_bytes(name, n, A)
         if b is None:
             continue
         avg_ms = t / cnt
         achieved = b / (avg_ms * 1e-3) / 1e9
+        traffic = traffic_raw = None
+        c = COUNTERS.get(name)
+        if c and cfg["workload"] == COUNTERS["workload"] and kernel_src_sha() == COUNTERS["src_sha"]:
+            f = COUNTERS["copy_factor"]
+            traffic = (c["fetch_kib"] * f["fetch"] + c["write_kib"] * f["write"]) * 1024
+            traffic_raw = (c["fetch_kib"] + c["write_kib"]) * 1024
         roofline = {
             "kernel": name,
             "bound": "hbm",
@@ -365,7 +425,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_raw_counters": traffic_raw,
+            "traffic_GBps": round(traffic_raw / (avg_ms * 1e-3) / 1e9, 1) if traffic_raw else None,
             "alg_bytes_per_launch": int(b),
             "avg_launch_ms": round(avg_ms, 4),
             "share_of_step": round((t / args.steps) / ms, 3),
@@ -395,12 +457,21 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {**cfg, "arcs": A, "vertices": n, "num_bcc": num_bcc,
+        "config": {**cfg, "arcs": A, "vertices": n, "num_bcc": num_bcc, "flags": args.flags, "tuned": tuned,
                    "edge_convention": "directed arcs (paper Table 1 m)",
                    "undirected_edges_per_s": value / 2, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if not args.no_systems and args.workload == "rmat":
+        del g, off, adj, ws, out
+        torch.cuda.empty_cache()
+        sys_args = argparse.Namespace(**{**vars(args), "flags": 0})
+        b = bench_batch(sys_args)
+        line["batched"] = {"speedup_vs_per_graph": b["value"], "ms_per_batch": b["ms_per_step"], **b["config"]}
+        torch.cuda.empty_cache()
+        sv = bench_serve(sys_args)
+        line["serving"] = {"graphs_per_s": sv["value"], **sv["config"]}
     print(json.dumps(line), flush=True)
 
 

@@ -175,3 +175,21 @@ def test_full_size_configs(name):
     note(f"full {name}")
     g = gen.config(name)
     assert_parity(g, gpu_solve(g), name)
+
+
+def test_traced_solve_same_result_and_times_kernels():
+    from paper_2301_01356_amd import solve_traced
+
+    g = gen.config("rmat_small")
+    note("traced rmat_small")
+    off, adj = to_dev(g)
+    tr = N.Trace(max_launches=512)
+    r = solve_traced(off, adj, tr)
+    tr.collect()
+    got = (r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), int(r.num_bcc.item()))
+    assert_parity(g, got, "traced")
+    tot = tr.totals()
+    for k in ("k_tag_sweep", "k_bcc_label", "k_lr_walk", "k_rmq_query", "k_cc_sweep", "k_lcc_sweep"):
+        assert k in tot and tot[k][1] == 1 and tot[k][0] >= 0.0, k
+    assert tr.dropped() == 0
+    tr.close()
