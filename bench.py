@@ -167,6 +167,16 @@ def bench_batch(args):
     e1.synchronize()
     ms_batch = e0.elapsed_time(e1) / args.steps
     log(f"[bench] batched (graph replay): {ms_batch:.3f} ms per batch of {G}")
+    from paper_2301_01356_amd import _native as N
+    from paper_2301_01356_amd import solve_traced
+
+    tr = N.Trace(max_launches=512)
+    solve_traced(solver.d_off, solver.d_adj, tr, vbegin=solver.d_vbegin, out=solver.out, workspace=solver.ws,
+                 flags=solver.flags, stream=s)
+    tr.collect()
+    for name, (t, cnt) in sorted(tr.totals().items(), key=lambda kv: -kv[1][0])[:12]:
+        log(f"  {t:9.3f} ms  {cnt:3d} launches  {name}")
+    tr.close()
 
     # per-graph plain solves (device-resident inputs, one launch sequence each)
     dgs = [(torch.from_numpy(g.offsets32()).to(dev), torch.from_numpy(g.adj).to(dev)) for g in graphs]

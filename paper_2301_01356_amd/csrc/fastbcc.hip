@@ -227,17 +227,18 @@ __global__ void k_tile_rows(const int* __restrict__ off, int n, int64_t A, const
   tile_row[t] = lo;
 }
 
-// Frontier of a connectivity sweep: rows outside the sampled largest set,
-// minus the arcs the sampling rounds already took.  fdeg -> scan gives each
+// Frontier of a connectivity sweep: the rows outside the sampled largest set
+// (their sampled arcs are visited again; re-linking joined ends costs two
+// finds).  fdeg -> scan gives each
 // row's first virtual arc; the non-empty rows are then compacted (row id +
 // start) so the virtual CSR has no empty rows for a wave to walk over.
 __global__ void k_frontier_deg(const int* __restrict__ off, const int* __restrict__ comp,
-                               const int* __restrict__ scal, int slot, int rounds, int n, int* __restrict__ fdeg,
+                               const int* __restrict__ scal, int slot, int n, int* __restrict__ fdeg,
                                int* __restrict__ fflag) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int big = scal[slot];
-  const int d = off[v + 1] - off[v] - rounds;
+  const int d = off[v + 1] - off[v];
   const bool in = d > 0 && comp[v] != big;
   fdeg[v] = in ? d : 0;
   fflag[v] = in ? 1 : 0;
@@ -366,14 +367,25 @@ __global__ void k_cc_init(int* __restrict__ cc, int* __restrict__ hu, int n) {
   hu[v] = -1;
 }
 
-// Sampling round r: every vertex links to its r-th neighbour.
+// Position of the neighbour a vertex samples in round r: a hash of (v, r)
+// over its row, so sampled links do not all point to each row's smallest id
+// (sorted rows would otherwise build long union-find chains).
+__device__ __forceinline__ int64_t sample_pos(int v, int r, int64_t deg) {
+  uint32_t h = (uint32_t)v * 0x9E3779B1u ^ (uint32_t)(r + 1) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return (int64_t)(h % (uint32_t)deg);
+}
+
+// Sampling round r: every vertex links to one hashed neighbour.
 __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
                             int* hu, int* hv) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
-  if (e - b > r) {
-    int w = adj[b + r];
+  if (e > b) {
+    int w = adj[b + sample_pos(v, r, e - b)];
     if (w != v) uf_link_record(cc, v, w, hu, hv);
   }
 }
@@ -383,13 +395,13 @@ __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__
 // set's side, and a row found in the largest set stays connected to it).
 __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                            const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                           int tw, int rounds, int* cc, int* hu, int* hv) {
+                           int tw, int* cc, int* hu, int* hv) {
   const int R = *frows;
   const int64_t F = fstart[R];
   arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
     if (!ok) return;
     const int x = frow[i];
-    const int64_t a = (int64_t)off[x] + rounds + (k - (int64_t)fstart[i]);
+    const int64_t a = (int64_t)off[x] + (k - (int64_t)fstart[i]);
     const int w = adj[a];
     if (w != x) uf_link_record(cc, x, w, hu, hv);
   });
@@ -748,21 +760,21 @@ __global__ void k_lcc_sample(const int* __restrict__ off, const int* __restrict_
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
-  if (e - b > r) {
-    int y = adj[b + r];
+  if (e > b) {
+    int y = adj[b + sample_pos(v, r, e - b)];
     if (y != v && cross_edge(v, rec[v], y, rec[y])) uf_link(lab, v, y);
   }
 }
 
 __global__ void k_lcc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                             const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                            int tw, int rounds, const int4* __restrict__ rec, int* lab) {
+                            int tw, const int4* __restrict__ rec, int* lab) {
   const int R = *frows;
   const int64_t F = fstart[R];
   arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
     if (!ok) return;
     const int x = frow[i];
-    const int64_t a = (int64_t)off[x] + rounds + (k - (int64_t)fstart[i]);
+    const int64_t a = (int64_t)off[x] + (k - (int64_t)fstart[i]);
     const int y = adj[a];
     if (y != x && cross_edge(x, rec[x], y, rec[y])) uf_link(lab, x, y);
   });
@@ -1007,7 +1019,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int* frows = frank + n;  // number of compacted frontier rows (scan total)
   // frontier virtual CSR of the rows a sweep still has to visit
   auto frontier = [&](const int* comp, int slot) {
-    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, tune.sample_rounds, n, foff, frank);
+    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, foff, frank);
     scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
     scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
     LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, frow, fstart);
@@ -1028,11 +1040,15 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
 
   // ---- First-CC (spanning forest)
   LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
-  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, k_cc_sample, gn, BLOCK, off, adj, n, r, cc, hu, hv);
-  LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+  // compress after every round: the next round's finds then take one hop
+  for (int r = 0; r < tune.sample_rounds; ++r) {
+    LAUNCH(c, k_cc_sample, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+    LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+  }
+  if (tune.sample_rounds == 0) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
   frontier(cc, S_BIG_CC);
-  LAUNCH(c, k_cc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, tune.sample_rounds, cc, hu, hv);
+  LAUNCH(c, k_cc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
   LAUNCH(c, k_compress, gn, BLOCK, cc, n);
 
   // ---- Rooting
@@ -1092,11 +1108,14 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int* lab = I(L.lab);
   LAUNCH(c, k_lcc_init, gn, BLOCK, lab, n);
   LAUNCH(c, k_lcc_tree, gn, BLOCK, rec, n, lab);
-  for (int r = 0; r < tune.sample_rounds; ++r) LAUNCH(c, k_lcc_sample, gn, BLOCK, off, adj, rec, n, r, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+  for (int r = 0; r < tune.sample_rounds; ++r) {
+    LAUNCH(c, k_lcc_sample, gn, BLOCK, off, adj, rec, n, r, lab);
+    LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+  }
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
   frontier(lab, S_BIG_LAB);
-  LAUNCH(c, k_lcc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, tune.sample_rounds, rec, lab);
+  LAUNCH(c, k_lcc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
 
   // ---- heads, articulation points, canonical labels

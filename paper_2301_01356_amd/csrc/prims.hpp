@@ -173,12 +173,17 @@ __device__ __forceinline__ int uf_find(int* p, int x) {
   return x;
 }
 
-// Union by CAS: the larger root goes under the smaller one.
+// Union by CAS: the larger root goes under the smaller one.  Two vertices
+// with the same parent are in the same set: that common case returns without
+// touching the (hot) root slot.
 __device__ __forceinline__ void uf_link(int* p, int u, int v) {
+  if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
   int ru = uf_find(p, u), rv = uf_find(p, v);
   while (ru != rv) {
     int hi = ru > rv ? ru : rv, lo = ru > rv ? rv : ru;
-    if (atomicCAS(p + hi, hi, lo) == hi) return;
+    // test before the CAS: when many threads race to hook the same root,
+    // only the ones that still see it as a root pay for an atomic
+    if (ld_relaxed(p + hi) == hi && atomicCAS(p + hi, hi, lo) == hi) return;
     ru = uf_find(p, ru);
     rv = uf_find(p, rv);
   }
@@ -188,10 +193,11 @@ __device__ __forceinline__ void uf_link(int* p, int u, int v) {
 // the CAS, u's set (rooted at the hooked root) and v's set are disjoint, so
 // the recorded edges form a spanning forest.
 __device__ __forceinline__ void uf_link_record(int* p, int u, int v, int* hook_u, int* hook_v) {
+  if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
   int ru = uf_find(p, u), rv = uf_find(p, v);
   while (ru != rv) {
     int hi = ru > rv ? ru : rv, lo = ru > rv ? rv : ru;
-    if (atomicCAS(p + hi, hi, lo) == hi) {
+    if (ld_relaxed(p + hi) == hi && atomicCAS(p + hi, hi, lo) == hi) {
       hook_u[hi] = u;
       hook_v[hi] = v;
       return;
