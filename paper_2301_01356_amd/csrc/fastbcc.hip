@@ -72,12 +72,16 @@ constexpr int DEF_SAMPLE_ROUNDS = 2;
 constexpr int MIN_TILE_ARCS = 256;  // workspace is sized for this tile size
 constexpr int DEF_TILE_SHIFT = 2;   // 4 windows of 64 arcs
 constexpr int MAX_TILE_SHIFT = 6;
+constexpr int HUB_DEG = 4096;    // graph degree from which tree-degree counters are sharded
+constexpr int HUB_SHARDS = 32;   // counters per hub (power of two, <= 32: 5 bits of a slot)
 
 // scalar slots at the head of the workspace
 enum Scalar : int {
   S_STATUS = 0,
   S_BIG_CC = 1,
   S_BIG_LAB = 2,
+  S_LBIG = 3,       // final Last-CC root of the sampled largest skeleton component
+  S_CANON_BIG = 4,  // canonical label of that component's BCC (-1 if it is no BCC)
   S_COUNT = 64,
 };
 
@@ -93,12 +97,13 @@ struct Layout {
   size_t total = 0;
   size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
       rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, lab, head,
-      rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, tile_row, scan_tmp;
+      rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, hubidx, shard, bigbits, tile_row, scan_tmp;
   int64_t nb = 0;      // rmq blocks of 64
   int levels = 0;      // sparse-table levels
   int64_t rmax = 0;    // ruler capacity
   int64_t tiles = 0;   // tile capacity
   int64_t scan_blocks = 0;
+  int64_t hubs = 0;    // hub capacity (sharded tree-degree counters)
 };
 
 inline size_t take(size_t& cur, size_t bytes) {
@@ -163,6 +168,10 @@ Layout make_layout(int64_t n, int64_t A) {
   L.frow = take(c, n1 * I);
   L.fstart = take(c, n1 * I);
   L.ftile = take(c, L.tiles * I);
+  L.hubs = (A / HUB_DEG) + 1;  // at most arcs / HUB_DEG vertices reach the hub degree
+  L.hubidx = take(c, n1 * I);
+  L.shard = take(c, (size_t)L.hubs * HUB_SHARDS * I);
+  L.bigbits = take(c, (size_t)cdiv(n > 0 ? n : 1, 64) * 8);
   L.tile_row = take(c, L.tiles * I);
   L.scan_tmp = take(c, L.scan_blocks * I);
   L.total = c;
@@ -408,19 +417,61 @@ __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ 
 }
 
 // ------------------------------------------------------------ Rooting
-// Tree degree counts; the slot each forest edge takes in both rows.
-__global__ void k_tree_count(const int* __restrict__ hu, const int* __restrict__ hv, int n, int* toff,
-                             int* __restrict__ su, int* __restrict__ sv) {
+// Tree degree counts and the slot each forest edge takes in both rows.
+// A vertex of graph degree >= HUB_DEG may get a huge tree degree, and one
+// counter would serialise every edge's atomic on one address: such hubs get
+// HUB_SHARDS counters, the shard picked from the edge's index h; a hub slot
+// is stored as -1 - (position within the shard), so the fill knows hub-ness
+// from the sign and the shard from h.  k_hub_finish turns shard counts into
+// in-row prefixes.
+__device__ __forceinline__ bool is_hub(const int* __restrict__ off, int x) { return off[x + 1] - off[x] >= HUB_DEG; }
+
+__device__ __forceinline__ int tree_slot(const int* __restrict__ off, const int* __restrict__ hubidx, int* toff,
+                                         int* shard, int x, int h) {
+  if (is_hub(off, x)) return -1 - atomicAdd(shard + (size_t)hubidx[x] * HUB_SHARDS + (h & (HUB_SHARDS - 1)), 1);
+  return atomicAdd(toff + x, 1);
+}
+
+__device__ __forceinline__ int tree_pos(const int* __restrict__ toff, const int* __restrict__ hubidx,
+                                        const int* __restrict__ shard, int x, int h, int slot) {
+  if (slot >= 0) return toff[x] + slot;
+  return toff[x] + shard[(size_t)hubidx[x] * HUB_SHARDS + (h & (HUB_SHARDS - 1))] + (-1 - slot);
+}
+
+__global__ void k_hub_flags(const int* __restrict__ off, int n, int* __restrict__ hubidx) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) hubidx[v] = is_hub(off, v) ? 1 : 0;
+}
+
+__global__ void k_tree_count(const int* __restrict__ off, const int* __restrict__ hubidx, const int* __restrict__ hu,
+                             const int* __restrict__ hv, int n, int* toff, int* shard, int* __restrict__ su,
+                             int* __restrict__ sv) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= n) return;
   int u = hu[h];
   if (u < 0) return;
   int v = hv[h];
-  su[h] = atomicAdd(toff + u, 1);
-  sv[h] = atomicAdd(toff + v, 1);
+  su[h] = tree_slot(off, hubidx, toff, shard, u, h);
+  sv[h] = tree_slot(off, hubidx, toff, shard, v, h);
 }
 
-__global__ void k_tree_fill(const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ su,
+// Per hub: total tree degree into toff[x], shard counts -> exclusive prefixes.
+__global__ void k_hub_finish(const int* __restrict__ off, const int* __restrict__ hubidx, int n, int* toff,
+                             int* shard) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || !is_hub(off, v)) return;
+  int* sh = shard + (size_t)hubidx[v] * HUB_SHARDS;
+  int run = 0;
+  for (int s = 0; s < HUB_SHARDS; ++s) {
+    const int c = sh[s];
+    sh[s] = run;
+    run += c;
+  }
+  toff[v] = run;
+}
+
+__global__ void k_tree_fill(const int* __restrict__ hubidx, const int* __restrict__ shard,
+                            const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ su,
                             const int* __restrict__ sv, const int* __restrict__ toff, int n, int* __restrict__ tadj,
                             int* __restrict__ twin) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -428,7 +479,7 @@ __global__ void k_tree_fill(const int* __restrict__ hu, const int* __restrict__ 
   int u = hu[h];
   if (u < 0) return;
   int v = hv[h];
-  int pu = toff[u] + su[h], pv = toff[v] + sv[h];
+  int pu = tree_pos(toff, hubidx, shard, u, h, su[h]), pv = tree_pos(toff, hubidx, shard, v, h, sv[h]);
   tadj[pu] = v;
   tadj[pv] = u;
   twin[pu] = pv;
@@ -591,7 +642,7 @@ __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__
     int mn = INT32_MAX, mx = INT32_MIN;
     const int key = ok ? x : -1;
     if (ok) {
-      const int y = adj[a];
+      const int y = __builtin_nontemporal_load(adj + a);
       if (y != x) {
         mn = mx = first[y];
       }
@@ -862,23 +913,85 @@ __global__ void __launch_bounds__(1024) k_sum_blocks(const int* __restrict__ bsu
   }
 }
 
+// The label of the largest skeleton component (the giant BCC on power-law
+// graphs) and a bitmap of its members: 1 bit per vertex (4 MB at n = 2^25)
+// stays in L2, so most arcs of head rows learn l[y] without a gather.
+__global__ void k_lbig(const int* __restrict__ lab, int* scal) { scal[S_LBIG] = lab[scal[S_BIG_LAB]]; }
+
+__global__ void k_big_bitmap(const int* __restrict__ lab, int n, const int* __restrict__ scal,
+                             unsigned long long* __restrict__ bits) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int big = scal[S_LBIG];
+  const uint64_t m = __ballot(v < n && lab[v] == big);
+  if (lane_id() == 0 && v < n) bits[v / WAVE] = m;
+}
+
+// The canonical label of the largest label's BCC, computed before pass 1 by
+// scanning the one row that holds its smallest arc (the row of its smallest
+// vertex, see pass 1), so pass 1 can write final labels for its arcs.
+__global__ void __launch_bounds__(BLOCK) k_big_canon(const int* __restrict__ off, const int* __restrict__ adj,
+                                                      const int4* __restrict__ rec, const int* __restrict__ lab,
+                                                      const int* __restrict__ head,
+                                                      const uint8_t* __restrict__ heads,
+                                                      const int* __restrict__ vbegin, int G, int* scal) {
+  __shared__ int part[BLOCK / WAVE];
+  const int Lb = scal[S_LBIG];
+  if (rec[Lb].z < 0 || lab[Lb] != Lb) {  // a tree root or an isolated vertex: labels no arc
+    if (threadIdx.x == 0) scal[S_CANON_BIG] = -1;
+    return;
+  }
+  const int hb = head[Lb];
+  const int x = (hb >= 0 && hb < Lb) ? hb : Lb;
+  const int lx = lab[x], hx = head[lx];
+  int best = INT32_MAX;
+  for (int64_t a = (int64_t)off[x] + threadIdx.x; a < off[x + 1]; a += blockDim.x) {
+    const int y = adj[a];
+    if (y == x) continue;
+    int L;
+    if (!heads[x]) {
+      L = lx;
+    } else {
+      const int ly = lab[y];
+      L = (ly == lx || hx == y) ? lx : ly;
+    }
+    if (L == Lb && (int)a < best) best = (int)a;
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    int b2 = __shfl_down(best, o, WAVE);
+    best = b2 < best ? b2 : best;
+  }
+  if (lane_id() == 0) part[threadIdx.x / WAVE] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BLOCK / WAVE; ++w) best = part[w] < best ? part[w] : best;
+    if (best != INT32_MAX && G > 1) best -= off[vbegin[graph_of(vbegin, G, Lb)]];
+    scal[S_CANON_BIG] = best == INT32_MAX ? -1 : best;
+  }
+}
+
 // Pass 1 over the arcs.  Arc x->y lies in the BCC whose vertex set holds both
 // endpoints: the label of x when l[x] == l[y] or y heads l[x] (x's BCC is
 // {l == l[x]} plus its head), else the label of y (then x heads l[y]).  Two
 // BCCs share at most one vertex, so this is the edge's unique BCC.  A vertex
-// that heads no BCC lies in exactly one BCC, so its row needs no gather.  The
+// that heads no BCC lies in exactly one BCC, so its row needs no gather; in
+// head rows l[y] comes from the giant-label bitmap when the bit is set.  The
 // smallest arc of BCC L lies in the row of its smallest vertex
 // m(L) = min(L, head(L)) (L is the smallest non-head vertex, the Last-CC
-// root); arcs of that row update minid[L].  The raw label goes to out[].
+// root); arcs of that row update minid[L].  Arcs of the largest label get
+// its final canonical label; the others get the raw label encoded as -2 - L
+// (self-loops -1), resolved by pass 2.
 __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                             const int* __restrict__ tile_row, int tw, const int* __restrict__ lab,
-                            const int* __restrict__ head, const uint8_t* __restrict__ heads, int* __restrict__ minid,
-                            int* __restrict__ out) {
+                            const int* __restrict__ head, const uint8_t* __restrict__ heads,
+                            const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
+                            int* __restrict__ minid, int* __restrict__ out) {
+  const int big = scal[S_LBIG];
+  const int canon_big = scal[S_CANON_BIG];
   arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
     if (!ok) return;
-    const int y = adj[a];
+    const int y = __builtin_nontemporal_load(adj + a);
     if (y == x) {
-      out[a] = -1;
+      __builtin_nontemporal_store(-1, out + a);
       return;
     }
     const int lx = lab[x];
@@ -888,7 +1001,7 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
       L = lx;
       m = (hx >= 0 && hx < lx) ? hx : lx;
     } else {
-      const int ly = lab[y];
+      const int ly = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? big : lab[y];
       if (ly == lx || hx == y) {
         L = lx;
         m = (hx >= 0 && hx < lx) ? hx : lx;
@@ -898,7 +1011,7 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
         m = (hy >= 0 && hy < ly) ? hy : ly;
       }
     }
-    out[a] = L;
+    __builtin_nontemporal_store((L == big && canon_big >= 0) ? canon_big : -2 - L, out + a);
     if (m == x) atomicMin(minid + L, (int)a);
   });
 }
@@ -914,14 +1027,18 @@ __global__ void k_bcc_canon(const int4* __restrict__ rec, const int* __restrict_
   canon[v] = c;
 }
 
-// Pass 2: raw label -> canonical label (elementwise, 4 arcs per thread).
+// Pass 2: encoded raw label -> canonical label (elementwise, 4 arcs per
+// thread); a vector holding only final labels is not written back.
+__device__ __forceinline__ int resolve(int q, const int* __restrict__ canon) { return q <= -2 ? canon[-2 - q] : q; }
+
 __global__ void k_bcc_remap4(int4* __restrict__ out, int64_t n4, const int* __restrict__ canon) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
     int4 q = out[i];
-    q.x = q.x < 0 ? -1 : canon[q.x];
-    q.y = q.y < 0 ? -1 : canon[q.y];
-    q.z = q.z < 0 ? -1 : canon[q.z];
-    q.w = q.w < 0 ? -1 : canon[q.w];
+    if ((q.x | q.y | q.z | q.w) >= 0 || (q.x > -2 && q.y > -2 && q.z > -2 && q.w > -2)) continue;
+    q.x = resolve(q.x, canon);
+    q.y = resolve(q.y, canon);
+    q.z = resolve(q.z, canon);
+    q.w = resolve(q.w, canon);
     out[i] = q;
   }
 }
@@ -929,8 +1046,7 @@ __global__ void k_bcc_remap4(int4* __restrict__ out, int64_t n4, const int* __re
 __global__ void k_bcc_remap1(int* __restrict__ out, int64_t begin, int64_t end, const int* __restrict__ canon) {
   int64_t i = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= end) return;
-  int q = out[i];
-  out[i] = q < 0 ? -1 : canon[q];
+  out[i] = resolve(out[i], canon);
 }
 
 // int64 offsets are narrowed once (every offset is < 2^31 because arcs are).
@@ -1054,10 +1170,15 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   // ---- Rooting
   int *toff = I(L.toff), *su = I(L.su), *sv = I(L.sv), *tadj = I(L.tadj), *twin = I(L.twin);
   int *rootidx = I(L.rootidx), *roots = I(L.roots), *next = I(L.next), *tmp = I(L.scan_tmp);
+  int *hubidx = I(L.hubidx), *shard = I(L.shard);
   fill_i32(c, toff, 0, n + 1);
-  LAUNCH(c, k_tree_count, gn, BLOCK, hu, hv, n, toff, su, sv);
+  fill_i32(c, shard, 0, L.hubs * HUB_SHARDS);
+  LAUNCH(c, k_hub_flags, gn, BLOCK, off, n, hubidx);
+  scan_inplace(c, hubidx, n, nullptr, tmp, hubidx + n);
+  LAUNCH(c, k_tree_count, gn, BLOCK, off, hubidx, hu, hv, n, toff, shard, su, sv);
+  LAUNCH(c, k_hub_finish, gn, BLOCK, off, hubidx, n, toff, shard);
   scan_inplace(c, toff, n, nullptr, tmp, toff + n);
-  LAUNCH(c, k_tree_fill, gn, BLOCK, hu, hv, su, sv, toff, n, tadj, twin);
+  LAUNCH(c, k_tree_fill, gn, BLOCK, hubidx, shard, hu, hv, su, sv, toff, n, tadj, twin);
   LAUNCH(c, k_root_flags, gn, BLOCK, cc, n, rootidx);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   LAUNCH(c, k_root_list, gn, BLOCK, cc, rootidx, n, roots);
@@ -1131,7 +1252,12 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_bcc_count, gn, BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
     if (G <= 1) LAUNCH(c, k_sum_blocks, 1, 1024, bsum, (int)gn, out_nbcc);
   }
-  LAUNCH(c, k_bcc_label, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, lab, head, heads, minid, out_label);
+  unsigned long long* bigbits = (unsigned long long*)(w + L.bigbits);
+  LAUNCH(c, k_lbig, 1, 1, lab, scal);
+  LAUNCH(c, k_big_bitmap, (unsigned)cdiv((int64_t)n, BLOCK), BLOCK, lab, n, scal, bigbits);
+  LAUNCH(c, k_big_canon, 1, BLOCK, off, adj, rec, lab, head, heads, vbegin, G, scal);
+  LAUNCH(c, k_bcc_label, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, lab, head, heads, bigbits, scal, minid,
+         out_label);
   LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, canon);
   if (A > 0) {
     if (((uintptr_t)out_label & 15) == 0) {
