@@ -231,6 +231,66 @@ def bench_batch(args):
     }
 
 
+def bench_knn_sweep(args):
+    """k-NN k-sweep (the shape of the paper's GL2..GL20 rows): 2^22 uniform
+    points in the unit square, k in {2, 5, 10, 15, 20}; per k the tuned solve
+    time and edges/s (diameter shrinks and edges grow with k)."""
+    import numpy as np
+    import torch
+
+    from paper_2301_01356_amd import alloc_workspace, gen, solve
+    from paper_2301_01356_amd.api import BccResult
+    from paper_2301_01356_amd.tune import cache_key, gpu_arch, skew_class
+
+    rows = []
+    dev = torch.device("cuda:0")
+    for k in (2, 5, 10, 15, 20):
+        t0 = time.perf_counter()
+        g = gen.config(f"knn{k}")
+        off = torch.from_numpy(g.offsets32()).to(dev)
+        adj = torch.from_numpy(g.adj).to(dev)
+        ws = alloc_workspace(g.n, g.num_arcs, 1, dev)
+        out = BccResult(torch.empty(g.num_arcs, dtype=torch.int32, device=dev),
+                        torch.empty(g.n, dtype=torch.uint8, device=dev), torch.empty(1, dtype=torch.int64, device=dev))
+        st = torch.cuda.current_stream()
+
+        def run_once(f):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(st)
+            solve(off, adj, out=out, workspace=ws, flags=f, stream=st)
+            a1.record(st)
+            a1.synchronize()
+            return a0.elapsed_time(a1)
+
+        key = cache_key(gpu_arch(), g.n, g.num_arcs, 1, skew_class(np.diff(g.offsets)))
+        flags, cfg = tuned_flags(key, run_once)
+        times = [run_once(flags) for _ in range(max(3, args.steps))]
+        ms = float(np.median(times))
+        rows.append({"k": k, "vertices": g.n, "arcs": g.num_arcs, "ms": ms, "edges_per_s": g.num_arcs / (ms * 1e-3),
+                     "num_bcc": int(out.num_bcc.item()), "tuned": cfg})
+        log(f"[bench] knn k={k}: {g.num_arcs} arcs, {ms:.3f} ms, {g.num_arcs / ms / 1e6:.2f} G edges/s, "
+            f"#BCC={rows[-1]['num_bcc']} (gen {time.perf_counter() - t0:.1f}s)")
+        del off, adj, ws, out
+        torch.cuda.empty_cache()
+    return {
+        "metric": "BCC edges/s end-to-end (1 GPU), k-NN k-sweep",
+        "value": rows[-1]["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": rows[-1]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "knn2d_2^22_k2..20", "rows": rows},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def bench_serve(args):
     """Serving: Poisson arrivals of mixed-family requests, n log-uniform in
     [2^10, 2^22], mean degree 4-32; continuous batching over HIP streams,
@@ -309,7 +369,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "plain", "batch", "serve"])
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "plain", "batch", "serve", "knn_sweep"])
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--qps", type=float, default=0.0)
@@ -342,6 +402,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "knn_sweep":
+        print(json.dumps(bench_knn_sweep(args)), flush=True)
         return
 
     import torch

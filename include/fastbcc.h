@@ -126,6 +126,24 @@ FASTBCC_API fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32
                                      void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
 
 /*
+ * BC-labeling read-out (paper: Section "Space-Efficient BCC Representation"
+ * and the component heads of Algorithm 1).  Call after a solve on the same
+ * workspace with the same n, num_arcs and graphs (enqueue on the solve's
+ * stream or after it).  For every vertex v:
+ *   out_home[v]      canonical id (smallest arc index, graph-local for
+ *                    batches) of the BCC in which v is a non-head member;
+ *   out_home_head[v] the head vertex of that BCC (graph-local for batches);
+ * both -1 for a spanning-tree root (every isolated vertex is one).  Each BCC
+ * c is {v : out_home[v] = c} plus the shared out_home_head of those v, so the
+ * whole partition takes O(n) space.  Either output may be null.
+ * graph_vbegin may be null when num_graphs == 1.  Device pointers.
+ */
+FASTBCC_API fastbcc_status fastbcc_vertex_labels(int64_t n, int64_t num_arcs, int32_t num_graphs,
+                                                 const int32_t* graph_vbegin, const void* workspace,
+                                                 size_t workspace_bytes, int32_t* out_home,
+                                                 int32_t* out_home_head, void* stream);
+
+/*
  * Synchronise `stream` and copy the device status word kept in `workspace`
  * (0 = fine; otherwise a fastbcc_status written by a device-side check) to
  * *out_status (host).

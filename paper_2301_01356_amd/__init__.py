@@ -3,6 +3,16 @@
 The compute path is ``libfastbcc.so`` (hand-written HIP for gfx950, C ABI in
 ``include/fastbcc.h``); this package only marshals torch tensors into it.
 """
-from .api import BccResult, alloc_workspace, read_device_status, solve, solve_batched, solve_traced, workspace_size  # noqa: F401
+from .api import (  # noqa: F401
+    BccResult,
+    alloc_workspace,
+    read_device_status,
+    solve,
+    solve_batched,
+    solve_traced,
+    vertex_labels,
+    workspace_size,
+)
 
-__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "solve_traced", "workspace_size"]
+__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "solve_traced", "vertex_labels",
+           "workspace_size"]

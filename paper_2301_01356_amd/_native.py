@@ -41,6 +41,7 @@ EXPORTED = (
     "fastbcc_trace_entry",
     "fastbcc_trace_dropped",
     "fastbcc_trace_reset",
+    "fastbcc_vertex_labels",
 )
 
 
@@ -98,6 +99,8 @@ def lib():
     h.fastbcc_trace_dropped.argtypes = [vp]
     h.fastbcc_trace_reset.restype = None
     h.fastbcc_trace_reset.argtypes = [vp]
+    h.fastbcc_vertex_labels.restype = st
+    h.fastbcc_vertex_labels.argtypes = [i64, i64, i32, vp, vp, sz, vp, vp, vp]
     _lib = h
     return h
 

@@ -207,6 +207,23 @@ def solve_traced(
     return out
 
 
+def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Optional[torch.Tensor] = None,
+                  stream=None):
+    """BC-labeling of the last solve on ``workspace``: (home int32[n], home_head
+    int32[n]) -- each vertex's home BCC (canonical id) and that BCC's head;
+    -1 for spanning-tree roots."""
+    dev = workspace.device
+    G = 1 if vbegin is None else vbegin.numel() - 1
+    home = torch.empty(n, dtype=torch.int32, device=dev)
+    head = torch.empty(n, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_vertex_labels(n, num_arcs, G, _dev_ptr(vbegin), workspace.data_ptr(), workspace.numel(),
+                                           home.data_ptr() if n else None, head.data_ptr() if n else None,
+                                           _stream_handle(stream))
+    N.check(st, "fastbcc_vertex_labels")
+    return home, head
+
+
 def read_device_status(workspace: torch.Tensor, stream=None) -> int:
     import ctypes
 

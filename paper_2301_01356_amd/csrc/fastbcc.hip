@@ -1049,6 +1049,24 @@ __global__ void k_bcc_remap1(int* __restrict__ out, int64_t begin, int64_t end, 
   out[i] = resolve(out[i], canon);
 }
 
+// BC-labeling read-out: home BCC (canonical id) and its head per vertex.
+__global__ void k_vertex_labels(const int4* __restrict__ rec, const int* __restrict__ lab,
+                                const int* __restrict__ head, const int* __restrict__ canon, int n,
+                                const int* __restrict__ vbegin, int G, int* __restrict__ home,
+                                int* __restrict__ home_head) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int c = -1, h = -1;
+  if (rec[v].z >= 0) {
+    const int L = lab[v];
+    c = canon[L];
+    h = head[L];
+    if (G > 1 && h >= 0) h -= vbegin[graph_of(vbegin, G, v)];
+  }
+  if (home) home[v] = c;
+  if (home_head) home_head[v] = h;
+}
+
 // int64 offsets are narrowed once (every offset is < 2^31 because arcs are).
 __global__ void k_narrow_offsets(const int64_t* __restrict__ in, int64_t count, int* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -1354,6 +1372,23 @@ fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32_t* graph_vb
   if (num_graphs < 1 || graph_vbegin == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
   return solve_impl<int>(n_total, num_arcs, offsets, adj, num_graphs, graph_vbegin, out_edge_label, out_is_ap,
                          out_num_bcc, workspace, workspace_bytes, flags, (hipStream_t)stream);
+}
+
+fastbcc_status fastbcc_vertex_labels(int64_t n, int64_t num_arcs, int32_t num_graphs, const int32_t* graph_vbegin,
+                                     const void* workspace, size_t workspace_bytes, int32_t* out_home,
+                                     int32_t* out_home_head, void* stream) {
+  if (n < 0 || num_arcs < 0 || num_graphs < 1 || (num_graphs > 1 && graph_vbegin == nullptr))
+    return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  const Layout L = make_layout(n, num_arcs);
+  if (workspace == nullptr || workspace_bytes < L.total) return FASTBCC_ERR_WORKSPACE_TOO_SMALL;
+  if (n == 0 || (out_home == nullptr && out_home_head == nullptr)) return FASTBCC_OK;
+  const char* w = (const char*)workspace;
+  Ctx c{(hipStream_t)stream};
+  LAUNCH(c, k_vertex_labels, grid_for(n), BLOCK, (const int4*)(w + L.rec), (const int*)(w + L.lab),
+         (const int*)(w + L.head), (const int*)(w + L.canon), (int)n, graph_vbegin, num_graphs, out_home,
+         out_home_head);
+  return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
 }
 
 fastbcc_status fastbcc_read_device_status(const void* workspace, void* stream, int32_t* out_status) {

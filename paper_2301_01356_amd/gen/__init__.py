@@ -198,4 +198,6 @@ def config(name: str) -> Csr:
         return batch()
     if name == "batch_small":
         return batch(seed=14, count=64, nmin=16, nmax=2048)
+    if name.startswith("knn"):  # "knn<k>": 2^22 points in the unit square, k nearest neighbours
+        return family("knn", 1 << 22, int(name[3:]), seed=6)
     raise KeyError(name)

@@ -152,6 +152,9 @@ void fam_lattice(Rng& r, int64_t n, double p, Edges& e) {
 
 // family 2: k nearest neighbours (Euclidean, ties by index) of n uniform
 // points in the unit square; each point links to its k nearest, symmetrised.
+// The neighbour search runs in parallel over points (inside an already
+// parallel region it runs serially); edges are appended in point order, so
+// the result does not depend on the thread count.
 void fam_knn(Rng& r, int64_t n, int k, Edges& e) {
   std::vector<double> x(n), y(n);
   for (int64_t i = 0; i < n; ++i) { x[i] = r.uniform(); y[i] = r.uniform(); }
@@ -169,34 +172,42 @@ void fam_knn(Rng& r, int64_t n, int k, Edges& e) {
     std::vector<int64_t> cur(cstart.begin(), cstart.end() - 1);
     for (int64_t i = 0; i < n; ++i) items[cur[cell_of[i]]++] = i;
   }
-  int kk = (int)std::min<int64_t>(k, n - 1);
-  std::vector<std::pair<double, int64_t>> cand;
-  for (int64_t i = 0; i < n; ++i) {
-    int64_t cx = cell_of[i] % g, cy = cell_of[i] / g;
-    for (int64_t rad = 1;; ++rad) {
-      cand.clear();
-      for (int64_t yy = std::max<int64_t>(0, cy - rad); yy <= std::min<int64_t>(g - 1, cy + rad); ++yy)
-        for (int64_t xx = std::max<int64_t>(0, cx - rad); xx <= std::min<int64_t>(g - 1, cx + rad); ++xx) {
-          int64_t c = yy * g + xx;
-          for (int64_t t = cstart[c]; t < cstart[c + 1]; ++t) {
-            int64_t j = items[t];
-            if (j == i) continue;
-            double dx = x[i] - x[j], dy = y[i] - y[j];
-            cand.emplace_back(dx * dx + dy * dy, j);
+  const int kk = (int)std::min<int64_t>(k, n - 1);
+  std::vector<int32_t> nbr((size_t)n * (kk > 0 ? kk : 1), -1);
+  #pragma omp parallel if (n >= 65536 && !omp_in_parallel())
+  {
+    std::vector<std::pair<double, int64_t>> cand;
+    #pragma omp for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t cx = cell_of[i] % g, cy = cell_of[i] / g;
+      for (int64_t rad = 1;; ++rad) {
+        cand.clear();
+        for (int64_t yy = std::max<int64_t>(0, cy - rad); yy <= std::min<int64_t>(g - 1, cy + rad); ++yy)
+          for (int64_t xx = std::max<int64_t>(0, cx - rad); xx <= std::min<int64_t>(g - 1, cx + rad); ++xx) {
+            int64_t c = yy * g + xx;
+            for (int64_t t = cstart[c]; t < cstart[c + 1]; ++t) {
+              int64_t j = items[t];
+              if (j == i) continue;
+              double dx = x[i] - x[j], dy = y[i] - y[j];
+              cand.emplace_back(dx * dx + dy * dy, j);
+            }
           }
+        bool covers_all = (cx - rad <= 0 && cy - rad <= 0 && cx + rad >= g - 1 && cy + rad >= g - 1);
+        if ((int64_t)cand.size() >= kk) {
+          std::partial_sort(cand.begin(), cand.begin() + kk, cand.end());
+          double reach = (double)rad * cs;  // every point within this distance is in the window
+          if (covers_all || cand[kk - 1].first <= reach * reach) break;
+        } else if (covers_all) {
+          break;
         }
-      bool covers_all = (cx - rad <= 0 && cy - rad <= 0 && cx + rad >= g - 1 && cy + rad >= g - 1);
-      if ((int64_t)cand.size() >= kk) {
-        std::partial_sort(cand.begin(), cand.begin() + kk, cand.end());
-        double reach = (double)rad * cs;  // every point within this distance is in the window
-        if (covers_all || cand[kk - 1].first <= reach * reach) break;
-      } else if (covers_all) {
-        break;
       }
+      int take = (int)std::min<int64_t>(kk, (int64_t)cand.size());
+      for (int t = 0; t < take; ++t) nbr[(size_t)i * kk + t] = (int32_t)cand[t].second;
     }
-    int take = (int)std::min<int64_t>(kk, (int64_t)cand.size());
-    for (int t = 0; t < take; ++t) e.add(i, cand[t].second);
   }
+  for (int64_t i = 0; i < n; ++i)
+    for (int t = 0; t < kk; ++t)
+      if (nbr[(size_t)i * kk + t] >= 0) e.add(i, nbr[(size_t)i * kk + t]);
 }
 
 // family 3: random recursive tree plus floor(f*n) extra edges, each from a

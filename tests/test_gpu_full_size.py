@@ -62,3 +62,17 @@ def test_batch4096_full_size_exact():
         assert int(nb[i]) == onb, f"graph {i}"
         assert np.array_equal(ap[v0:v1], oap), f"graph {i}"
         assert np.array_equal(lab[a0:a1], olab), f"graph {i}"
+
+
+@pytest.mark.parametrize("k", [2, 20])
+def test_knn_sweep_endpoints_full_size_exact(k):
+    note(f"k-NN 2^22 points, k={k}")
+    g = gen.config(f"knn{k}")
+    off = torch.from_numpy(g.offsets32()).to(DEV)
+    adj = torch.from_numpy(g.adj).to(DEV)
+    r = solve(off, adj)
+    torch.cuda.synchronize()
+    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+    assert int(r.num_bcc.item()) == nb
+    assert np.array_equal(r.is_ap.cpu().numpy(), ap)
+    assert np.array_equal(r.edge_label.cpu().numpy(), lab)

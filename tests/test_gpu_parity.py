@@ -193,3 +193,77 @@ def test_traced_solve_same_result_and_times_kernels():
         assert k in tot and tot[k][1] == 1 and tot[k][0] >= 0.0, k
     assert tr.dropped() == 0
     tr.close()
+
+
+def vertex_sets_from_edge_labels(n, offsets, adj, lab):
+    """BCC id -> vertex set, from canonical arc labels (unique: no tree involved)."""
+    src = np.repeat(np.arange(n), np.diff(offsets))
+    m = lab >= 0
+    pairs = np.unique(np.stack([lab[m].astype(np.int64), src[m]], 1), axis=0)
+    out = {}
+    for c, v in pairs.tolist():
+        out.setdefault(c, set()).add(v)
+    return out
+
+
+def check_bc_labeling(n, offsets, adj, oracle_lab, home, head, what):
+    expect = vertex_sets_from_edge_labels(n, offsets, adj, oracle_lab)
+    got = {}
+    heads = {}
+    for v in range(n):
+        c = int(home[v])
+        if c < 0:
+            assert head[v] == -1
+            continue
+        got.setdefault(c, set()).add(v)
+        h = int(head[v])
+        assert heads.setdefault(c, h) == h, f"{what}: BCC {c} has two heads"
+    for c, h in heads.items():
+        assert h not in got[c], f"{what}: head of {c} is also a member"
+        got[c].add(h)
+    assert got == expect, f"{what}: BC-labeling does not reproduce the BCC vertex sets"
+
+
+@pytest.mark.parametrize("name", ["plain_small", "grid_small", "rmat_small"])
+def test_vertex_labels_reproduce_bcc_vertex_sets(name):
+    from paper_2301_01356_amd import alloc_workspace, vertex_labels
+
+    g = gen.config(name)
+    note(f"vertex labels {name}")
+    off, adj = to_dev(g)
+    ws = alloc_workspace(g.n, g.num_arcs)
+    solve(off, adj, workspace=ws)
+    home, head = vertex_labels(ws, g.n, g.num_arcs)
+    torch.cuda.synchronize()
+    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+    check_bc_labeling(g.n, g.offsets, g.adj, lab, home.cpu().numpy(), head.cpu().numpy(), name)
+    # an articulation point is exactly a vertex that heads some BCC while also
+    # belonging to another one (or heads two)
+    h = head.cpu().numpy()
+    hv = home.cpu().numpy()
+    counts = np.bincount(h[h >= 0], minlength=g.n)
+    heads_distinct = np.zeros(g.n, np.int64)
+    for c in np.unique(hv[hv >= 0]):
+        heads_distinct[h[np.flatnonzero(hv == c)[0]]] += 1
+    is_ap = ((heads_distinct >= 1) & (hv >= 0)) | (heads_distinct >= 2)
+    assert np.array_equal(is_ap.astype(np.uint8), ap)
+    del counts
+
+
+def test_vertex_labels_batched_are_graph_local():
+    from paper_2301_01356_amd import alloc_workspace, vertex_labels
+
+    graphs = [gen.mixed(71, i, 8, 1500, 4.0, 16.0) for i in range(12)]
+    u = gen.unite(graphs)
+    note("vertex labels batched")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    ws = alloc_workspace(u.n, u.num_arcs, len(graphs))
+    solve_batched(vb, off, adj, workspace=ws)
+    home, head = vertex_labels(ws, u.n, u.num_arcs, vbegin=vb)
+    torch.cuda.synchronize()
+    home, head = home.cpu().numpy(), head.cpu().numpy()
+    for i, g in enumerate(graphs):
+        v0, v1 = u.vbegin[i], u.vbegin[i + 1]
+        lab, _, _, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+        check_bc_labeling(g.n, g.offsets, g.adj, lab, home[v0:v1], head[v0:v1], f"graph {i}")
