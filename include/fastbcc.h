@@ -73,10 +73,13 @@ typedef enum fastbcc_status {
 /* Tuning fields (0 = built-in default).  They change speed, never results.
  *   bits 8-11  log2 of the list-ranking ruler spacing, 3..10
  *   bits 12-13 union-find sampling rounds before the full sweep, 0..3 (value 3 = none)
- *   bits 14-16 log2 of 64-arc windows per wave tile, 2..6 */
+ *   bits 14-16 log2 of 64-arc windows per wave tile, 2..6
+ *   bit  17    First-CC union-find variant: 0 = hook the larger root id under
+ *              the smaller, 1 = hook by hashed random priority */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
+#define FASTBCC_TUNE_CC_PRIORITY 0x20000u
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -24,6 +24,7 @@ FLAG_VALIDATE = 0x1
 TUNE_RULER_SHIFT = 8
 TUNE_SAMPLE_SHIFT = 12
 TUNE_TILE_SHIFT = 14
+TUNE_CC_PRIORITY = 0x20000
 
 EXPORTED = (
     "fastbcc_workspace_size",
@@ -116,9 +117,9 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
     return int(out.value)
 
 
-def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0) -> int:
+def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False) -> int:
     """Encode tuning fields (0/None = library default)."""
-    f = 0
+    f = TUNE_CC_PRIORITY if cc_priority else 0
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT
     if sample_rounds is not None:
@@ -140,14 +141,18 @@ class Trace:
         check(lib().fastbcc_trace_collect(self.h), "fastbcc_trace_collect")
 
     def totals(self) -> dict:
-        """{kernel name: (total ms, timed launches)} of everything collected."""
+        """{kernel name: (total ms, timed launches)} of everything collected.
+        Template arguments are dropped from the names, so the variants of one
+        kernel (e.g. the two union-find hooking rules) share an entry."""
         out = {}
         for i in range(lib().fastbcc_trace_count(self.h)):
             name = ctypes.c_char_p()
             ms = ctypes.c_double()
             nl = ctypes.c_int64()
             check(lib().fastbcc_trace_entry(self.h, i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(nl)))
-            out[name.value.decode()] = (ms.value, nl.value)
+            key = name.value.decode().split("<", 1)[0]
+            t, c = out.get(key, (0.0, 0))
+            out[key] = (t + ms.value, c + nl.value)
         return out
 
     def dropped(self) -> int:

@@ -182,11 +182,14 @@ struct Tune {
   int ruler_shift = DEF_RULER_SHIFT;
   int sample_rounds = DEF_SAMPLE_ROUNDS;
   int tile_windows = 1 << DEF_TILE_SHIFT;
+  bool cc_prio = false;  // First-CC hooks by hashed priority instead of by id
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
   const uint32_t known = FASTBCC_FLAG_VALIDATE | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
-                         (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT);
+                         (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
+                         FASTBCC_TUNE_CC_PRIORITY;
+  t.cc_prio = (flags & FASTBCC_TUNE_CC_PRIORITY) != 0;
   if (flags & ~known) return false;
   uint32_t r = (flags >> FASTBCC_TUNE_RULER_SHIFT) & 0xF;
   uint32_t s = (flags >> FASTBCC_TUNE_SAMPLE_SHIFT) & 0x3;
@@ -387,7 +390,14 @@ __device__ __forceinline__ int64_t sample_pos(int v, int r, int64_t deg) {
   return (int64_t)(h % (uint32_t)deg);
 }
 
+template <bool PRIO>
+__device__ __forceinline__ void cc_link(int* cc, int u, int v, int* hu, int* hv) {
+  if (PRIO) uf_link_record_prio(cc, u, v, hu, hv);
+  else uf_link_record(cc, u, v, hu, hv);
+}
+
 // Sampling round r: every vertex links to one hashed neighbour.
+template <bool PRIO>
 __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
                             int* hu, int* hv) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -395,13 +405,14 @@ __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__
   const int64_t b = off[v], e = off[v + 1];
   if (e > b) {
     int w = adj[b + sample_pos(v, r, e - b)];
-    if (w != v) uf_link_record(cc, v, w, hu, hv);
+    if (w != v) cc_link<PRIO>(cc, v, w, hu, hv);
   }
 }
 
 // Full sweep over the frontier: rows whose set is the sampled largest one
 // are skipped (every edge they share with another set is seen from that
 // set's side, and a row found in the largest set stays connected to it).
+template <bool PRIO>
 __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                            const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
                            int tw, int* cc, int* hu, int* hv) {
@@ -412,7 +423,7 @@ __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ 
     const int x = frow[i];
     const int64_t a = (int64_t)off[x] + (k - (int64_t)fstart[i]);
     const int w = adj[a];
-    if (w != x) uf_link_record(cc, x, w, hu, hv);
+    if (w != x) cc_link<PRIO>(cc, x, w, hu, hv);
   });
 }
 
@@ -1176,13 +1187,15 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
   // compress after every round: the next round's finds then take one hop
   for (int r = 0; r < tune.sample_rounds; ++r) {
-    LAUNCH(c, k_cc_sample, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+    if (tune.cc_prio) LAUNCH(c, k_cc_sample<true>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+    else LAUNCH(c, k_cc_sample<false>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
     LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   }
   if (tune.sample_rounds == 0) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
   frontier(cc, S_BIG_CC);
-  LAUNCH(c, k_cc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
+  if (tune.cc_prio) LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
+  else LAUNCH(c, k_cc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
   LAUNCH(c, k_compress, gn, BLOCK, cc, n);
 
   // ---- Rooting

@@ -4,12 +4,12 @@
 //  * exclusive prefix scan over int32 (reduce -> spine -> downsweep), with an
 //    optional element count read from device memory so a launch sequence
 //    needs no host round trip for data-dependent sizes
-//  * union-find on a parent array in which every pointer goes to a smaller
-//    or equal id: find with path halving, link by CAS of the larger root
-//    under the smaller one (so a set's root is its smallest member), and a
-//    variant that records the edge behind every successful hook (the
-//    spanning-forest by-product of connectivity, paper: Section
-//    "Implementation Details", "Spanning Forest")
+//  * union-find on an acyclic parent array: find with path halving, link by
+//    CAS of the larger root under the smaller one (so a set's root is its
+//    smallest member) or, for connectivity that only needs some root, of the
+//    lower hashed priority under the higher; variants record the edge behind
+//    every successful hook (the spanning-forest by-product of connectivity,
+//    paper: Section "Implementation Details", "Spanning Forest")
 //  * arc tiles: a wave walks a contiguous range of arcs 64 at a time and
 //    finds the source row of every arc by a shuffle binary search over 64
 //    consecutive row ends, so every sweep over the CSR is arc-balanced and
@@ -160,7 +160,8 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down(const int* in, int* ou
 }
 
 // ------------------------------------------------------------ union-find
-// Every parent pointer goes to an id <= its own, so loops always end.
+// Parent pointers form a forest (every hook puts a root under another
+// set's root), so find loops always end.
 __device__ __forceinline__ int uf_find(int* p, int x) {
   int px = ld_relaxed(p + x);
   while (px != x) {
@@ -200,6 +201,36 @@ __device__ __forceinline__ void uf_link_record(int* p, int u, int v, int* hook_u
     if (ld_relaxed(p + hi) == hi && atomicCAS(p + hi, hi, lo) == hi) {
       hook_u[hi] = u;
       hook_v[hi] = v;
+      return;
+    }
+    ru = uf_find(p, ru);
+    rv = uf_find(p, rv);
+  }
+}
+
+// Hook by hashed priority instead of by id: the root whose (bijectively
+// mixed) id is smaller goes under the other.  Roots are then arbitrary
+// members, which connectivity with forest recording allows, and structured
+// ids (lattices, chains) no longer line up into long hook chains.
+__device__ __forceinline__ uint32_t uf_prio(int x) {
+  uint32_t h = (uint32_t)x;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__device__ __forceinline__ void uf_link_record_prio(int* p, int u, int v, int* hook_u, int* hook_v) {
+  if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
+  int ru = uf_find(p, u), rv = uf_find(p, v);
+  while (ru != rv) {
+    const bool u_low = uf_prio(ru) < uf_prio(rv);
+    const int lo = u_low ? ru : rv, hi = u_low ? rv : ru;
+    if (ld_relaxed(p + lo) == lo && atomicCAS(p + lo, lo, hi) == lo) {
+      hook_u[lo] = u;
+      hook_v[lo] = v;
       return;
     }
     ru = uf_find(p, ru);

@@ -1,10 +1,11 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes three speed-only knobs in its flags word (they never change
+The C ABI exposes four speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
-sampling off, i.e. a different union-find schedule), and the arc-tile size
-(64-arc windows per wave, i.e. work per wave).  The tuner times candidates by
+sampling off), the First-CC union-find variant (hook by id or by hashed
+priority), and the arc-tile size (64-arc windows per wave, i.e. work per
+wave).  The tuner times candidates by
 coordinate descent on the real input and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
 """
@@ -24,7 +25,8 @@ DEFAULT_CACHE = os.environ.get("FASTBCC_TUNE_CACHE", os.path.expanduser("~/.cach
 RULER = (4, 5, 6, 7, 8)
 SAMPLE = (0, 1, 2)
 TILE = (2, 3, 4, 5)
-START = {"ruler": 5, "sample": 2, "tile": 2}
+UF = (0, 1)  # First-CC union-find: 0 = min-id hooking, 1 = hashed-priority hooking
+START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0}
 
 
 def skew_class(degrees: np.ndarray) -> str:
@@ -46,7 +48,8 @@ def cache_key(arch: str, n: int, arcs: int, graphs: int, skew: str) -> str:
 
 
 def encode(cfg: Dict[str, int]) -> int:
-    return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"])
+    return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"],
+                        cc_priority=bool(cfg.get("uf", 0)))
 
 
 class Tuner:
@@ -91,7 +94,7 @@ class Tuner:
 
         for _ in range(2):
             changed = False
-            for knob, values in (("sample", SAMPLE), ("tile", TILE), ("ruler", RULER)):
+            for knob, values in (("uf", UF), ("sample", SAMPLE), ("tile", TILE), ("ruler", RULER)):
                 best_v, best_t = cfg[knob], cost(cfg)
                 for v in values:
                     c = dict(cfg, **{knob: v})

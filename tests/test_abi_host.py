@@ -91,3 +91,6 @@ def test_tune_flag_encoding():
     assert (f >> N.TUNE_RULER_SHIFT) & 0xF == 6
     assert (f >> N.TUNE_SAMPLE_SHIFT) & 0x3 == 3
     assert (f >> N.TUNE_TILE_SHIFT) & 0x7 == 3
+    assert f & N.TUNE_CC_PRIORITY == 0
+    assert N.tune_flags(cc_priority=True) == N.TUNE_CC_PRIORITY
+    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=N.TUNE_CC_PRIORITY << 1) == N.ERR_INVALID_ARGUMENT

@@ -112,10 +112,12 @@ def test_multigraph_self_loops_unsorted_rows():
 @pytest.mark.parametrize("flags", [
     N.tune_flags(ruler_shift=3), N.tune_flags(ruler_shift=10), N.tune_flags(sample_rounds=0),
     N.tune_flags(sample_rounds=1), N.tune_flags(tile_shift=6), N.tune_flags(ruler_shift=7, tile_shift=3),
+    N.tune_flags(cc_priority=True), N.tune_flags(cc_priority=True, sample_rounds=0),
 ])
-def test_tuning_fields_never_change_results(flags):
-    note(f"rmat_small flags={flags:#x}")
-    g = gen.config("rmat_small")
+@pytest.mark.parametrize("cfg", ["rmat_small", "grid_small"])
+def test_tuning_fields_never_change_results(flags, cfg):
+    note(f"{cfg} flags={flags:#x}")
+    g = gen.config(cfg)
     assert_parity(g, gpu_solve(g, flags=flags), f"flags {flags:#x}")
 
 
