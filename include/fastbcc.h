@@ -83,11 +83,13 @@ typedef enum fastbcc_status {
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split
- * into num_graphs graphs (1 for a single graph).  O(n + num_arcs/16 +
+ * into num_graphs graphs (1 for a single graph).  O(n + num_arcs/4 +
  * num_graphs); independent of flags.  `bytes` is host memory.
- * The paper's space bound (Theorem on cost bounds: O(n) auxiliary space) is
- * kept: nothing in the workspace grows with the number of arcs except 1/16
- * byte per arc of bookkeeping (arc tiles and sharded hub counters).
+ * The paper's space bound (Theorem on cost bounds: O(n) auxiliary words) is
+ * kept up to bit-level bookkeeping: what grows with the number of arcs is at
+ * most 1/4 byte per arc (arc tiles, sharded hub counters and one
+ * descendant bit per arc that saves the edge-label pass a gather), against
+ * the 4 bytes per arc of the input and of the output.
  */
 FASTBCC_API fastbcc_status fastbcc_workspace_size(int64_t n, int64_t num_arcs, int32_t num_graphs, size_t* bytes);
 

@@ -97,7 +97,7 @@ struct Layout {
   size_t total = 0;
   size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
       rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, lab, head,
-      rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, hubidx, shard, bigbits, tile_row, scan_tmp;
+      rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, hubidx, shard, bigbits, dbits, tile_row, scan_tmp;
   int64_t nb = 0;      // rmq blocks of 64
   int levels = 0;      // sparse-table levels
   int64_t rmax = 0;    // ruler capacity
@@ -172,6 +172,7 @@ Layout make_layout(int64_t n, int64_t A) {
   L.hubidx = take(c, n1 * I);
   L.shard = take(c, (size_t)L.hubs * HUB_SHARDS * I);
   L.bigbits = take(c, (size_t)cdiv(n > 0 ? n : 1, 64) * 8);
+  L.dbits = take(c, (size_t)cdiv(A > 0 ? A : 1, 64) * 8);
   L.tile_row = take(c, L.tiles * I);
   L.scan_tmp = take(c, L.scan_blocks * I);
   L.total = c;
@@ -645,20 +646,27 @@ __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ 
 // ------------------------------------------------------------ Tagging
 // w1[x] = min, w2[x] = max of first[] over x and all its neighbours.  Using
 // every neighbour instead of non-tree ones only adds first[p(x)] and values
-// inside T_x; neither changes any fence decision.
+// inside T_x; neither changes any fence decision.  The gathered first[y] also
+// tells whether y is a proper descendant of x (first[x] < first[y] <=
+// last[x]); that bit is kept per arc (one ballot word per 64-arc window) for
+// the edge-label read-out.
 __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                             const int* __restrict__ tile_row, int tw, const int* __restrict__ first,
-                            int* __restrict__ w1, int* __restrict__ w2) {
-  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+                            const int4* __restrict__ rec, int* __restrict__ w1, int* __restrict__ w2,
+                            unsigned long long* __restrict__ dbits) {
+  arc_windows(off, adj, n, A, tile_row, tw, [&](int64_t a, int x, bool ok, int y) {
     int mn = INT32_MAX, mx = INT32_MIN;
+    bool desc = false;
     const int key = ok ? x : -1;
-    if (ok) {
-      const int y = __builtin_nontemporal_load(adj + a);
-      if (y != x) {
-        mn = mx = first[y];
-      }
+    if (ok && y != x) {
+      const int fy = first[y];
+      mn = mx = fy;
+      const int2 fl = reinterpret_cast<const int2*>(rec)[2 * (int64_t)x];  // (first[x], last[x])
+      desc = fy > fl.x && fy <= fl.y;
     }
     const int lane = lane_id();
+    const uint64_t dm = __ballot(desc);
+    if (lane == 0) dbits[a / WAVE] = dm;  // lane 0 holds the window's first arc, a multiple of 64
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {
       int k2 = __shfl_up(key, o, WAVE);
@@ -984,47 +992,52 @@ __global__ void __launch_bounds__(BLOCK) k_big_canon(const int* __restrict__ off
 // endpoints: the label of x when l[x] == l[y] or y heads l[x] (x's BCC is
 // {l == l[x]} plus its head), else the label of y (then x heads l[y]).  Two
 // BCCs share at most one vertex, so this is the edge's unique BCC.  A vertex
-// that heads no BCC lies in exactly one BCC, so its row needs no gather; in
-// head rows l[y] comes from the giant-label bitmap when the bit is set.  The
+// that heads no BCC lies in exactly one BCC, so its row needs no gather.  In
+// a head row, an arc whose target is not a proper descendant of x (the tag
+// sweep's bit) lies on a cycle through the tree edge (x, p(x)), or that edge
+// itself, whose BCC is l[x]: no gather either.  The remaining arcs read l[y]
+// from the giant-label bitmap when its bit is set.  The
 // smallest arc of BCC L lies in the row of its smallest vertex
 // m(L) = min(L, head(L)) (L is the smallest non-head vertex, the Last-CC
 // root); arcs of that row update minid[L].  Arcs of the largest label get
 // its final canonical label; the others get the raw label encoded as -2 - L
 // (self-loops -1), resolved by pass 2.
 __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                            const int* __restrict__ tile_row, int tw, const int* __restrict__ lab,
-                            const int* __restrict__ head, const uint8_t* __restrict__ heads,
-                            const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
-                            int* __restrict__ minid, int* __restrict__ out) {
+                            const int* __restrict__ tile_row, int tw, const int2* __restrict__ vlh,
+                            const uint8_t* __restrict__ heads, const unsigned long long* __restrict__ bits,
+                            const unsigned long long* __restrict__ dbits, const int* __restrict__ head,
+                            const int* __restrict__ scal, int* __restrict__ minid, int* __restrict__ out) {
   const int big = scal[S_LBIG];
+  const int hbig = head[big];
   const int canon_big = scal[S_CANON_BIG];
-  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+  arc_windows(off, adj, n, A, tile_row, tw, [&](int64_t a, int x, bool ok, int y) {
     if (!ok) return;
-    const int y = __builtin_nontemporal_load(adj + a);
     if (y == x) {
       __builtin_nontemporal_store(-1, out + a);
       return;
     }
-    const int lx = lab[x];
-    const int hx = head[lx];
-    int L, m;
-    if (!heads[x]) {
-      L = lx;
-      m = (hx >= 0 && hx < lx) ? hx : lx;
-    } else {
-      const int ly = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? big : lab[y];
-      if (ly == lx || hx == y) {
-        L = lx;
-        m = (hx >= 0 && hx < lx) ? hx : lx;
-      } else {
-        L = ly;
-        const int hy = head[ly];
-        m = (hy >= 0 && hy < ly) ? hy : ly;
+    const int2 rx = vlh[x];  // (l[x], head(l[x]))
+    const int lx = rx.x, hx = rx.y;
+    int L = lx, m = (hx >= 0 && hx < lx) ? hx : lx;
+    if (heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull)) {
+      const int2 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? make_int2(big, hbig) : vlh[y];
+      if (ry.x != lx && hx != y) {
+        L = ry.x;
+        m = (ry.y >= 0 && ry.y < ry.x) ? ry.y : ry.x;
       }
     }
     __builtin_nontemporal_store((L == big && canon_big >= 0) ? canon_big : -2 - L, out + a);
     if (m == x) atomicMin(minid + L, (int)a);
   });
+}
+
+// (l[v], head(l[v])) per vertex: one 8-byte gather in the edge-label pass
+// instead of two dependent ones.
+__global__ void k_vertex_lh(const int* __restrict__ lab, const int* __restrict__ head, int n, int2* __restrict__ vlh) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int l = lab[v];
+  vlh[v] = make_int2(l, head[l]);
 }
 
 // canon[L] = smallest arc of BCC L, made graph-local for batches.
@@ -1247,7 +1260,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, n, pos, eflag, first, rec, scal + S_STATUS);
   fill_i32(c, w1, INT32_MAX, n);
   fill_i32(c, w2, INT32_MIN, n);
-  LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, w1, w2);
+  unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
+  LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
   int *W1 = I(L.W1), *W2 = I(L.W2), *pre1 = I(L.pre1), *suf1 = I(L.suf1), *pre2 = I(L.pre2), *suf2 = I(L.suf2);
   int *tmin = I(L.tmin), *tmax = I(L.tmax);
   LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, scal + S_STATUS);
@@ -1287,8 +1301,10 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_lbig, 1, 1, lab, scal);
   LAUNCH(c, k_big_bitmap, (unsigned)cdiv((int64_t)n, BLOCK), BLOCK, lab, n, scal, bigbits);
   LAUNCH(c, k_big_canon, 1, BLOCK, off, adj, rec, lab, head, heads, vbegin, G, scal);
-  LAUNCH(c, k_bcc_label, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, lab, head, heads, bigbits, scal, minid,
-         out_label);
+  int2* vlh = (int2*)(w + L.ol);  // the list-ranking array is dead by now
+  LAUNCH(c, k_vertex_lh, gn, BLOCK, lab, head, n, vlh);
+  LAUNCH(c, k_bcc_label, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits, head, scal,
+         minid, out_label);
   LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, canon);
   if (A > 0) {
     if (((uintptr_t)out_label & 15) == 0) {

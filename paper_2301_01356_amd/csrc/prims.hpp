@@ -281,4 +281,58 @@ __device__ __forceinline__ void arc_tiles(const OffT* __restrict__ off, int n, i
   }
 }
 
+// The same tiling for sweeps over the arcs themselves, software-pipelined:
+// the next window's targets and row ends are loaded before the current
+// window's body runs, so the body's gathers overlap them (vector loads of a
+// wave return in issue order, so a load is only useful early if nothing the
+// wave waits for before it was issued later).  `body(a, x, ok, y)` also gets
+// y = adj[a], loaded nontemporally (the adjacency is streamed once).
+template <typename Body>
+__device__ __forceinline__ void arc_windows(const int* __restrict__ off, const int* __restrict__ adj, int n,
+                                            int64_t A, const int* __restrict__ tile_row, int tile_windows,
+                                            Body&& body) {
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t tile_arcs = (int64_t)WAVE * tile_windows;
+  const int64_t tbeg = wave * tile_arcs;
+  if (tbeg >= A) return;
+  const int64_t tend = tbeg + tile_arcs < A ? tbeg + tile_arcs : A;
+  int row = tile_row[wave];
+  int y = tbeg + lane < tend ? __builtin_nontemporal_load(adj + tbeg + lane) : -1;
+  int e = 0;
+  if (row < n) e = off[row + 1 + lane < n ? row + 1 + lane : n];
+  for (int64_t base = tbeg; base < tend; base += WAVE) {
+    const int64_t a = base + lane;
+    int my_row = -1;
+    int lo = row;
+    int ev = e;  // end of row lo + lane
+    while (lo < n) {
+      const int64_t e_last = __shfl(ev, WAVE - 1, WAVE);
+      int pos = 0;  // number of the 64 row ends that are <= a (0..64)
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int64_t ej = __shfl(ev, pos + step - 1, WAVE);
+        if (ej <= a) pos += step;
+      }
+      if (pos == WAVE - 1 && e_last <= a) pos = WAVE;
+      if (my_row < 0 && pos < WAVE) my_row = lo + pos;
+      const bool need = (a < tend) && my_row < 0;
+      if (!__any(need)) break;
+      lo += WAVE;
+      if (lo < n) ev = off[lo + 1 + lane < n ? lo + 1 + lane : n];
+    }
+    const bool ok = (a < tend) && my_row >= 0 && my_row < n;
+    const int last = __shfl(my_row, WAVE - 1, WAVE);
+    row = last >= 0 ? last : row;
+    // next window: its targets and the row ends from its first row on
+    const int64_t an = a + WAVE;
+    const int yn = an < tend ? __builtin_nontemporal_load(adj + an) : -1;
+    int en = 0;
+    if (base + WAVE < tend && row < n) en = off[row + 1 + lane < n ? row + 1 + lane : n];
+    body(a, ok ? my_row : -1, ok, y);
+    y = yn;
+    e = en;
+  }
+}
+
 }  // namespace fastbcc

@@ -41,8 +41,9 @@ def test_workspace_size_is_linear_in_n():
     c = N.workspace_size(1 << 17, 1 << 24)
     assert 0 < a < b
     # arcs only add bookkeeping: two int32 tile-row arrays (one entry per 256
-    # arcs) and 32 hub counters per possible hub (one hub per 4096 arcs)
-    assert c - b <= ((1 << 24) - (1 << 20)) // 16 + 4096
+    # arcs), 32 hub counters per possible hub (one hub per 4096 arcs) and one
+    # descendant bit per arc
+    assert c - b <= ((1 << 24) - (1 << 20)) // 4 + 4096
     # the O(n) part: well under 256 bytes per vertex
     assert b / (1 << 17) < 256
 
