@@ -45,15 +45,16 @@ def workload_graph(name):
 # Algorithmic bytes per launch: each array touched the minimal number of
 # times the kernel's definition needs, 4 bytes per gathered word (no cache
 # lines).  Offsets are read as int32 inside the solve (int64 input offsets are
-# narrowed once).  A = arcs, n = vertices, h = arcs in rows of BCC heads.
-def alg_bytes(kernel, n, A, h=None):
-    h = A if h is None else h
+# narrowed once).  A = arcs, n = vertices.
+def alg_bytes(kernel, n, A):
     models = {
-        # offsets + adjacency + first[y] per arc + w1/w2 read-modify-write per row
-        "k_tag_sweep": 4 * (n + 1) + 8 * A + 16 * n,
-        # offsets + adjacency + raw label write per arc + lab[y] per arc of a head row
-        # + lab/head/heads of the row vertex
-        "k_bcc_label": 4 * (n + 1) + 8 * A + 4 * h + 9 * n,
+        # offsets + adjacency + first[y] per arc + (first, last) of the row vertex
+        # + w1/w2 read-modify-write per row + one descendant bit per arc
+        "k_tag_sweep": 4 * (n + 1) + 8 * A + 24 * n + A // 8,
+        # offsets + adjacency + label write per arc + (l, head) record and head
+        # flag of the row vertex + descendant bits; the gathers for descendant
+        # arcs of head rows are left out, so this is a lower bound
+        "k_bcc_label": 4 * (n + 1) + 8 * A + 9 * n + A // 8,
         # label read + label write per arc (canonical-label lookups hit the few hot labels)
         "k_bcc_remap4": 8 * A,
     }
@@ -65,10 +66,10 @@ def alg_bytes(kernel, n, A, h=None):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources they were taken on (hash below); otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "340a1f2047497f7d",
+    "src_sha": "0ef8113c16453e17",
     "workload": "rmat25",
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_tag_sweep": {"fetch_kib": 57134946.3, "write_kib": 1279842.8},
+    "k_tag_sweep": {"fetch_kib": 58015006.0, "write_kib": 1895020.2},
 }
 
 
