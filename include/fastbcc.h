@@ -75,11 +75,15 @@ typedef enum fastbcc_status {
  *   bits 12-13 union-find sampling rounds before the full sweep, 0..3 (value 3 = none)
  *   bits 14-16 log2 of 64-arc windows per wave tile, 2..6
  *   bit  17    First-CC union-find variant: 0 = hook the larger root id under
- *              the smaller, 1 = hook by hashed random priority */
+ *              the smaller, 1 = hook by hashed random priority
+ *   bits 18-19 First-CC low-diameter decomposition (Miller-Peng-Xu, the LDD
+ *              of the paper's LDD-UF-JTB connectivity) before union-find:
+ *              0 = off, k = on with beta = 2^-k */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
 #define FASTBCC_TUNE_CC_PRIORITY 0x20000u
+#define FASTBCC_TUNE_LDD_SHIFT 18
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -25,6 +25,7 @@ TUNE_RULER_SHIFT = 8
 TUNE_SAMPLE_SHIFT = 12
 TUNE_TILE_SHIFT = 14
 TUNE_CC_PRIORITY = 0x20000
+TUNE_LDD_SHIFT = 18
 
 EXPORTED = (
     "fastbcc_workspace_size",
@@ -117,9 +118,12 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
     return int(out.value)
 
 
-def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False) -> int:
-    """Encode tuning fields (0/None = library default)."""
+def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False,
+               ldd: int = 0) -> int:
+    """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
+    the low-diameter decomposition before First-CC's union-find, beta = 2^-k."""
     f = TUNE_CC_PRIORITY if cc_priority else 0
+    f |= (ldd & 0x3) << TUNE_LDD_SHIFT
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT
     if sample_rounds is not None:

@@ -82,6 +82,9 @@ enum Scalar : int {
   S_BIG_LAB = 2,
   S_LBIG = 3,       // final Last-CC root of the sampled largest skeleton component
   S_CANON_BIG = 4,  // canonical label of that component's BCC (-1 if it is no BCC)
+  S_NODES = 8,      // list nodes of the Euler tour
+  S_ENTRIES = 9,    // entry flags over the tour
+  S_LDD_HUGE = 10,  // two slots: long rows listed by a decomposition round
   S_COUNT = 64,
 };
 
@@ -184,13 +187,15 @@ struct Tune {
   int sample_rounds = DEF_SAMPLE_ROUNDS;
   int tile_windows = 1 << DEF_TILE_SHIFT;
   bool cc_prio = false;  // First-CC hooks by hashed priority instead of by id
+  int ldd = 0;           // First-CC starts with a low-diameter decomposition, beta = 2^-ldd (0 = off)
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
   const uint32_t known = FASTBCC_FLAG_VALIDATE | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
-                         FASTBCC_TUNE_CC_PRIORITY;
+                         FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT);
   t.cc_prio = (flags & FASTBCC_TUNE_CC_PRIORITY) != 0;
+  t.ldd = (int)((flags >> FASTBCC_TUNE_LDD_SHIFT) & 0x3);
   if (flags & ~known) return false;
   uint32_t r = (flags >> FASTBCC_TUNE_RULER_SHIFT) & 0xF;
   uint32_t s = (flags >> FASTBCC_TUNE_SAMPLE_SHIFT) & 0x3;
@@ -428,6 +433,128 @@ __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ 
   });
 }
 
+// ------------------------------------------------- low-diameter decomposition
+// Optional First-CC front end (paper: connectivity by LDD-UF-JTB, Section
+// "Implementation Details" and the appendix on its cost): a Miller-Peng-Xu
+// decomposition grows BFS clusters from centres that wake up at exponentially
+// distributed times, then union-find joins the clusters over the remaining
+// edges (the sampling rounds and the frontier sweep that follow).  Vertex v
+// draws a shift d_v ~ Exp(beta) and wakes in round T0 - floor(d_v) (clamped
+// to [0, T0], T0 = ceil(ln n / beta)) unless a cluster reached it first; every
+// vertex is claimed by round T0.  The local-search analog: a lane that claims
+// a vertex of small degree expands it at once, so clusters grow two hops per
+// round through sparse regions.  A claimed vertex records its BFS edge the way
+// a hooked root records its union-find edge, so the recorded edges still form
+// a spanning forest.
+constexpr int LDD_SMALL = 32;    // rows up to this degree are expanded by one lane
+constexpr int LDD_HUGE = 2048;   // longer rows are queued in chunks for the whole grid
+constexpr int LDD_CHUNK = 1024;  // arcs per queued chunk (<= LDD_HUGE)
+constexpr int LDD_HUGE_GRID = 1024;
+
+// Start round from a splitmix64 hash of the vertex id (Steele, Lea and Flood,
+// "Fast splittable pseudorandom number generators").
+__device__ __forceinline__ int ldd_start(int v, int T0, float inv_beta) {
+  uint64_t z = (uint64_t)(uint32_t)v * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const float u = (float)((z >> 40) + 1) * (1.0f / 16777216.0f);  // (0, 1]
+  const int d = (int)(-logf(u) * inv_beta);
+  const int s = T0 - d;
+  return s < 0 ? 0 : s;
+}
+
+__global__ void k_ldd_init(int* __restrict__ cc, int* __restrict__ hu, int* __restrict__ rnd, int n, int* scal) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) scal[S_LDD_HUGE] = scal[S_LDD_HUGE + 1] = 0;
+  if (v >= n) return;
+  cc[v] = -1;
+  hu[v] = -1;
+  rnd[v] = -1;
+}
+
+__device__ __forceinline__ bool ldd_claim(int* cc, int* rnd, int* hu, int* hv, int u, int cu, int w, int r) {
+  if (ld_relaxed(cc + w) != -1 || atomicCAS(cc + w, -1, cu) != -1) return false;
+  hu[w] = u;
+  hv[w] = w;
+  rnd[w] = r + 1;  // expands next round (unless expanded at once)
+  return true;
+}
+
+// Round r: wake the centres due now, then every vertex of round r claims its
+// unclaimed neighbours.  Rows longer than LDD_SMALL are expanded by the whole
+// wave, 64 arcs at a time; rows longer than LDD_HUGE are queued as chunks of
+// LDD_CHUNK arcs, (row, first arc) each, for k_ldd_huge.  The queue length
+// alternates between two slots, so this round can clear the slot of the round
+// before while appending to its own.  Queue capacity: a row of d > LDD_HUGE
+// arcs takes ceil(d / LDD_CHUNK) < 2d / LDD_CHUNK entries, so all rows together
+// need fewer than 2A / LDD_CHUNK.
+__global__ void k_ldd_round(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int T0,
+                            float inv_beta, int* cc, int* rnd, int* __restrict__ hu, int* __restrict__ hv,
+                            int2* __restrict__ queue, int* scal) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) scal[S_LDD_HUGE + ((r + 1) & 1)] = 0;
+  bool active = false;
+  int b = 0, e = 0, cv = -1;
+  if (v < n) {
+    if (ld_relaxed(cc + v) == -1 && ldd_start(v, T0, inv_beta) <= r && atomicCAS(cc + v, -1, v) == -1) rnd[v] = r;
+    if (ld_relaxed(rnd + v) == r) {
+      active = true;
+      b = off[v];
+      e = off[v + 1];
+      cv = ld_relaxed(cc + v);
+    }
+  }
+  if (active && e - b > LDD_HUGE) {
+    const int chunks = (e - b + LDD_CHUNK - 1) / LDD_CHUNK;
+    const int at = atomicAdd(scal + S_LDD_HUGE + (r & 1), chunks);
+    for (int k = 0; k < chunks; ++k) queue[at + k] = make_int2(v, b + k * LDD_CHUNK);
+    active = false;
+  }
+  if (active && e - b <= LDD_SMALL) {
+    for (int a = b; a < e; ++a) {
+      const int w = adj[a];
+      if (w == v || !ldd_claim(cc, rnd, hu, hv, v, cv, w, r)) continue;
+      const int wb = off[w], we = off[w + 1];
+      if (we - wb > LDD_SMALL) continue;
+      rnd[w] = -2;  // expanded here
+      for (int k = wb; k < we; ++k) {
+        const int x = adj[k];
+        if (x != w) ldd_claim(cc, rnd, hu, hv, w, cv, x, r);
+      }
+    }
+  }
+  uint64_t big = __ballot(active && e - b > LDD_SMALL);
+  while (big) {
+    const int j = __builtin_ctzll(big);
+    big &= big - 1;
+    const int u = __shfl(v, j, WAVE), cu = __shfl(cv, j, WAVE);
+    const int ub = __shfl(b, j, WAVE), ue = __shfl(e, j, WAVE);
+    for (int a = ub + lane_id(); a < ue; a += WAVE) {
+      const int w = adj[a];
+      if (w != u) ldd_claim(cc, rnd, hu, hv, u, cu, w, r);
+    }
+  }
+}
+
+// The queued chunks of round r, one wave per chunk.
+__global__ void k_ldd_huge(const int* __restrict__ off, const int* __restrict__ adj, int r,
+                           const int2* __restrict__ queue, const int* scal, int* cc, int* rnd, int* __restrict__ hu,
+                           int* __restrict__ hv) {
+  const int count = scal[S_LDD_HUGE + (r & 1)];
+  const int waves = gridDim.x * (blockDim.x / WAVE);
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < count; i += waves) {
+    const int2 q = queue[i];
+    const int u = q.x, cu = ld_relaxed(cc + q.x);
+    const int64_t e = off[u + 1];
+    const int64_t end = (int64_t)q.y + LDD_CHUNK < e ? (int64_t)q.y + LDD_CHUNK : e;
+    for (int64_t a = q.y + lane_id(); a < end; a += WAVE) {
+      const int w = adj[a];
+      if (w != u) ldd_claim(cc, rnd, hu, hv, u, cu, w, r);
+    }
+  }
+}
+
 // ------------------------------------------------------------ Rooting
 // Tree degree counts and the slot each forest edge takes in both rows.
 // A vertex of graph degree >= HUB_DEG may get a huge tree degree, and one
@@ -498,21 +625,40 @@ __global__ void k_tree_fill(const int* __restrict__ hubidx, const int* __restric
   twin[pv] = pu;
 }
 
-__global__ void k_root_flags(const int* __restrict__ cc, int n, int* __restrict__ rootidx) {
+// Roots of trees with at least one edge get a list entry node; a one-vertex
+// tree (an isolated vertex, or one with only self-loops) stays out of the
+// Euler tour and takes a preorder number after all others.
+__global__ void k_root_flags(const int* __restrict__ cc, const int* __restrict__ toff, int n,
+                             int* __restrict__ rootidx, int* __restrict__ lone) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  rootidx[v] = cc[v] == v ? 1 : 0;
+  const bool root = cc[v] == v;
+  const bool alone = root && toff[v + 1] == toff[v];
+  rootidx[v] = root && !alone ? 1 : 0;
+  lone[v] = alone ? 1 : 0;
 }
 
-__global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ rootidx, int n,
-                            int* __restrict__ roots) {
+__global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ toff,
+                            const int* __restrict__ rootidx, int n, int* __restrict__ roots) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  if (cc[v] == v) roots[rootidx[v]] = v;
+  if (cc[v] == v && toff[v + 1] > toff[v]) roots[rootidx[v]] = v;
 }
 
-// List nodes: [0, C) one entry node per tree root (root order), then
-// C + [0, 2T) the tree arcs.  The chain runs entry_0, tour_0, entry_1, ...
+// first = last = n - S + (rank among one-vertex trees), S of them in all.
+__global__ void k_lone_tags(const int* __restrict__ lone, int n, int* __restrict__ first, int4* __restrict__ rec) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int k = lone[v];
+  if (lone[v + 1] == k) return;
+  const int f = n - lone[n] + k;
+  first[v] = f;
+  rec[v] = make_int4(f, f, -1, 0);
+}
+
+// List nodes: [0, C) one entry node per root of a tree with edges (root
+// order), then C + [0, 2T) the tree arcs.  The chain runs entry_0, tour_0,
+// entry_1, ...
 __global__ void k_euler_next(const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
                              const int* __restrict__ cc, const int* __restrict__ rootidx,
                              const int* __restrict__ roots, int n, int* __restrict__ next) {
@@ -614,8 +760,8 @@ __global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __rest
 // a compact first[] (the array every arc sweep gathers from).
 __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ roots,
                        const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
-                       int n, const int* __restrict__ pos, const int* __restrict__ escan, int* __restrict__ first,
-                       int4* __restrict__ rec, int* status) {
+                       const int* __restrict__ lone, int n, const int* __restrict__ pos,
+                       const int* __restrict__ escan, int* __restrict__ first, int4* __restrict__ rec, int* status) {
   const int C = rootidx[n], NL = C + toff[n];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NL) return;
@@ -623,7 +769,7 @@ __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ 
   if (i < C) {
     v = roots[i];
     f = escan[pos[i]];
-    int nf = (i + 1 < C) ? escan[pos[i + 1]] : n;
+    int nf = (i + 1 < C) ? escan[pos[i + 1]] : n - lone[n];
     l = nf - 1;
     p = -1;
   } else {
@@ -1197,7 +1343,19 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
 
   // ---- First-CC (spanning forest)
-  LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
+  if (tune.ldd) {
+    int* rnd = I(L.su);  // the tree-slot array is free until Rooting
+    int2* queue = (int2*)(w + L.dbits);  // A/8 bytes, free until Tagging; the queue needs < A/64
+    const float beta = 1.0f / (float)(1 << tune.ldd);
+    const int T0 = (int)ceil(log((double)(n > 2 ? n : 2)) / beta);
+    LAUNCH(c, k_ldd_init, gn, BLOCK, cc, hu, rnd, n, scal);
+    for (int r = 0; r <= T0; ++r) {
+      LAUNCH(c, k_ldd_round, gn, BLOCK, off, adj, n, r, T0, 1.0f / beta, cc, rnd, hu, hv, queue, scal);
+      LAUNCH(c, k_ldd_huge, LDD_HUGE_GRID, BLOCK, off, adj, r, queue, scal, cc, rnd, hu, hv);
+    }
+  } else {
+    LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
+  }
   // compress after every round: the next round's finds then take one hop
   for (int r = 0; r < tune.sample_rounds; ++r) {
     if (tune.cc_prio) LAUNCH(c, k_cc_sample<true>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
@@ -1223,9 +1381,11 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_hub_finish, gn, BLOCK, off, hubidx, n, toff, shard);
   scan_inplace(c, toff, n, nullptr, tmp, toff + n);
   LAUNCH(c, k_tree_fill, gn, BLOCK, hubidx, shard, hu, hv, su, sv, toff, n, tadj, twin);
-  LAUNCH(c, k_root_flags, gn, BLOCK, cc, n, rootidx);
+  int* lone = hubidx;  // the hub numbering is dead after the tree fill
+  LAUNCH(c, k_root_flags, gn, BLOCK, cc, toff, n, rootidx, lone);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
-  LAUNCH(c, k_root_list, gn, BLOCK, cc, rootidx, n, roots);
+  scan_inplace(c, lone, n, nullptr, tmp, lone + n);
+  LAUNCH(c, k_root_list, gn, BLOCK, cc, toff, rootidx, n, roots);
   const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
   const unsigned gnode = grid_for(nodes_max);
   LAUNCH(c, k_euler_next, gnode, BLOCK, toff, tadj, twin, cc, rootidx, roots, n, next);
@@ -1250,14 +1410,15 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int* eflag = I(L.eflag);
   LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, toff, twin, n, ol, vin, pos);
   LAUNCH(c, k_enter_flags, gnode, BLOCK, rootidx, toff, twin, n, pos, eflag, scal + S_STATUS);
-  int* nl_dev = scal + 8;  // number of list nodes, for the scan of entry flags
+  int* nl_dev = scal + S_NODES;  // number of list nodes, for the scan of entry flags
   LAUNCH(c, k_node_count, 1, 1, rootidx, toff, n, nl_dev);
-  scan_inplace(c, eflag, nodes_max, nl_dev, tmp, scal + 9);
+  scan_inplace(c, eflag, nodes_max, nl_dev, tmp, scal + S_ENTRIES);
 
   // ---- Tagging
   int *first = I(L.first), *w1 = I(L.w1), *w2 = I(L.w2);
   int4* rec = (int4*)(w + L.rec);
-  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, n, pos, eflag, first, rec, scal + S_STATUS);
+  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, lone, n, pos, eflag, first, rec, scal + S_STATUS);
+  LAUNCH(c, k_lone_tags, gn, BLOCK, lone, n, first, rec);
   fill_i32(c, w1, INT32_MAX, n);
   fill_i32(c, w2, INT32_MIN, n);
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);

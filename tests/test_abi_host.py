@@ -94,4 +94,5 @@ def test_tune_flag_encoding():
     assert (f >> N.TUNE_TILE_SHIFT) & 0x7 == 3
     assert f & N.TUNE_CC_PRIORITY == 0
     assert N.tune_flags(cc_priority=True) == N.TUNE_CC_PRIORITY
-    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=N.TUNE_CC_PRIORITY << 1) == N.ERR_INVALID_ARGUMENT
+    assert N.tune_flags(ldd=2) == 2 << N.TUNE_LDD_SHIFT
+    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << (N.TUNE_LDD_SHIFT + 2)) == N.ERR_INVALID_ARGUMENT
