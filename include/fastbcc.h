@@ -78,12 +78,17 @@ typedef enum fastbcc_status {
  *              the smaller, 1 = hook by hashed random priority
  *   bits 18-19 First-CC low-diameter decomposition (Miller-Peng-Xu, the LDD
  *              of the paper's LDD-UF-JTB connectivity) before union-find:
- *              0 = off, k = on with beta = 2^-k */
+ *              0 = off, k = on with beta = 2^-k
+ *   bit  20    Tagging from sampled tags: fences are certified from a few
+ *              sampled neighbours per vertex (the tags of Section "Tagging"
+ *              computed on a subset of the edges) and exact tags are swept
+ *              only for the subtrees still undecided */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
 #define FASTBCC_TUNE_CC_PRIORITY 0x20000u
 #define FASTBCC_TUNE_LDD_SHIFT 18
+#define FASTBCC_TUNE_SAMPLED_TAGS 0x100000u
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -26,6 +26,7 @@ TUNE_SAMPLE_SHIFT = 12
 TUNE_TILE_SHIFT = 14
 TUNE_CC_PRIORITY = 0x20000
 TUNE_LDD_SHIFT = 18
+TUNE_SAMPLED_TAGS = 0x100000
 
 EXPORTED = (
     "fastbcc_workspace_size",
@@ -119,10 +120,12 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
 
 
 def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False,
-               ldd: int = 0) -> int:
+               ldd: int = 0, sampled_tags: bool = False) -> int:
     """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
-    the low-diameter decomposition before First-CC's union-find, beta = 2^-k."""
+    the low-diameter decomposition before First-CC's union-find, beta = 2^-k;
+    ``sampled_tags`` certifies fences from sampled tags first."""
     f = TUNE_CC_PRIORITY if cc_priority else 0
+    f |= TUNE_SAMPLED_TAGS if sampled_tags else 0
     f |= (ldd & 0x3) << TUNE_LDD_SHIFT
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT

@@ -85,6 +85,8 @@ enum Scalar : int {
   S_NODES = 8,      // list nodes of the Euler tour
   S_ENTRIES = 9,    // entry flags over the tour
   S_LDD_HUGE = 10,  // two slots: long rows listed by a decomposition round
+  S_GIANT_HUB = 12, // highest-degree sampled vertex of the largest component (-1: none)
+  S_BIG_ROOT = 13,  // final First-CC root of that component
   S_COUNT = 64,
 };
 
@@ -188,12 +190,15 @@ struct Tune {
   int tile_windows = 1 << DEF_TILE_SHIFT;
   bool cc_prio = false;  // First-CC hooks by hashed priority instead of by id
   int ldd = 0;           // First-CC starts with a low-diameter decomposition, beta = 2^-ldd (0 = off)
+  bool sampled_tags = false;  // fences certified from sampled tags, exact tags only where needed
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
   const uint32_t known = FASTBCC_FLAG_VALIDATE | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
-                         FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT);
+                         FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
+                         FASTBCC_TUNE_SAMPLED_TAGS;
+  t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
   t.cc_prio = (flags & FASTBCC_TUNE_CC_PRIORITY) != 0;
   t.ldd = (int)((flags >> FASTBCC_TUNE_LDD_SHIFT) & 0x3);
   if (flags & ~known) return false;
@@ -262,8 +267,9 @@ __global__ void k_frontier_deg(const int* __restrict__ off, const int* __restric
   fflag[v] = in ? 1 : 0;
 }
 
+// Slot v of the flag/degree arrays stands for row map[v] (row v without a map).
 __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __restrict__ frank, int n,
-                                   int* __restrict__ frow, int* __restrict__ fstart) {
+                                   const int* __restrict__ map, int* __restrict__ frow, int* __restrict__ fstart) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v > n) return;
   if (v == n) {
@@ -272,9 +278,83 @@ __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __re
   }
   const int r = frank[v];
   if (frank[v + 1] != r) {
-    frow[r] = v;
+    frow[r] = map ? map[v] : v;
     fstart[r] = foff[v];
   }
+}
+
+// Tree roots: the largest component is rooted at its highest-degree sampled
+// vertex, every other component at a vertex of largest degree.  Any root is
+// valid; a hub almost surely lies in the component's largest BCC, and a root
+// inside the largest BCC keeps the subtrees below fence vertices small (what
+// the sampled-tag certification needs).
+__global__ void __launch_bounds__(1024) k_giant_hub(const int* __restrict__ off, const int* __restrict__ cc, int n,
+                                                    int* scal) {
+  __shared__ int bd[1024 / WAVE], bv[1024 / WAVE];
+  const int big = cc[scal[S_BIG_CC]];  // the sampled root may have been hooked since
+  int best_d = -1, best_v = -1;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t i = (int64_t)k * 1024 + threadIdx.x;
+    const int v = (int)((i * n) / 8192);
+    if (v < n && cc[v] == big) {
+      const int d = off[v + 1] - off[v];
+      if (d > best_d) {
+        best_d = d;
+        best_v = v;
+      }
+    }
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int d2 = __shfl_down(best_d, o, WAVE), v2 = __shfl_down(best_v, o, WAVE);
+    if (d2 > best_d) {
+      best_d = d2;
+      best_v = v2;
+    }
+  }
+  if (lane_id() == 0) {
+    bd[threadIdx.x / WAVE] = best_d;
+    bv[threadIdx.x / WAVE] = best_v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 1024 / WAVE; ++w)
+      if (bd[w] > best_d) {
+        best_d = bd[w];
+        best_v = bv[w];
+      }
+    scal[S_GIANT_HUB] = best_d > 0 ? best_v : -1;
+    scal[S_BIG_ROOT] = big;
+  }
+}
+
+// rdeg[c] = largest degree in component c (c = union-find root), except the
+// largest component; runs of equal c in a wave are reduced first.
+__global__ void k_root_degree(const int* __restrict__ off, const int* __restrict__ cc, int n,
+                              const int* __restrict__ scal, int* rdeg) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int big = scal[S_BIG_ROOT];
+  int c = -1, d = -1;
+  if (v < n) {
+    c = cc[v];
+    d = off[v + 1] - off[v];
+    if (c == big) c = -1;
+  }
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int c2 = __shfl_up(c, o, WAVE), d2 = __shfl_up(d, o, WAVE);
+    if (lane >= o && c2 == c && d2 > d) d = d2;
+  }
+  const int cn = __shfl_down(c, 1, WAVE);
+  if (c >= 0 && (lane == WAVE - 1 || cn != c)) atomicMax(rdeg + c, d);
+}
+
+__global__ void k_root_select(const int* __restrict__ off, const int* __restrict__ cc, int n,
+                              const int* __restrict__ rdeg, int* __restrict__ rsel) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int c = cc[v];
+  if (off[v + 1] - off[v] == rdeg[c]) rsel[c] = v;  // any vertex of largest degree
 }
 
 // Most frequent value of p[] over a stratified sample of vertices (one block).
@@ -639,10 +719,19 @@ __global__ void k_root_flags(const int* __restrict__ cc, const int* __restrict__
 }
 
 __global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ toff,
-                            const int* __restrict__ rootidx, int n, int* __restrict__ roots) {
+                            const int* __restrict__ rootidx, const int* __restrict__ rdeg,
+                            const int* __restrict__ rsel, const int* __restrict__ scal, int n,
+                            int* __restrict__ roots) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  if (cc[v] == v && toff[v + 1] > toff[v]) roots[rootidx[v]] = v;
+  if (cc[v] != v || toff[v + 1] == toff[v]) return;
+  int r = v;
+  if (v == scal[S_BIG_ROOT]) {
+    if (scal[S_GIANT_HUB] >= 0) r = scal[S_GIANT_HUB];
+  } else if (rdeg[v] >= 0) {
+    r = rsel[v];
+  }
+  roots[rootidx[v]] = r;
 }
 
 // first = last = n - S + (rank among one-vertex trees), S of them in all.
@@ -675,9 +764,9 @@ __global__ void k_euler_next(const int* __restrict__ toff, const int* __restrict
   int nx = twin[a] + 1;
   if (nx == toff[v + 1]) {
     nx = toff[v];
-    if (cc[v] == v) {  // closes the tour of v's tree: continue with the next tree
-      int k = rootidx[v] + 1;
-      next[i] = k < C ? k : -1;
+    const int k = rootidx[cc[v]];
+    if (roots[k] == v) {  // closes the tour of v's tree: continue with the next tree
+      next[i] = k + 1 < C ? k + 1 : -1;
       return;
     }
   }
@@ -833,7 +922,8 @@ __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__
 }
 
 __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restrict__ w1, const int* __restrict__ w2,
-                              int n, int* __restrict__ W1, int* __restrict__ W2, int* status) {
+                              int n, int* __restrict__ W1, int* __restrict__ W2, int* __restrict__ order,
+                              int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int f = first[v];
@@ -844,6 +934,7 @@ __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restri
   int a = w1[v], b = w2[v];
   W1[f] = a < f ? a : f;
   W2[f] = b > f ? b : f;
+  if (order) order[f] = v;
 }
 
 // In-block prefix/suffix min and max (block = 64 consecutive preorder slots
@@ -901,18 +992,35 @@ __global__ void k_rmq_level(int* __restrict__ tmin, int* __restrict__ tmax, int6
 
 // low/high over [first, last]; fence(p(v), v) = first[p] <= low[v] and
 // last[p] >= high[v] (paper: Algorithm 1, function Fence).  Updates the
-// vertex record in place (only its fence field changes).
+// vertex record in place (only its fence field changes).  Modes:
+//   QUERY_EXACT    tags are exact: fence bit 0/1;
+//   QUERY_CERTIFY  tags are sampled (low can only be higher, high only lower):
+//                  a failed fence test certifies "no fence" (0); a child of a
+//                  root is always a fence (1); otherwise the vertex stays
+//                  undecided (2) and its preorder interval is counted in cover[]
+//                  (difference array) so that its subtree gets exact tags;
+//   QUERY_RECHECK  exact test for the undecided vertices only.
+enum QueryMode : int { QUERY_EXACT = 0, QUERY_CERTIFY = 1, QUERY_RECHECK = 2 };
+
 __global__ void k_rmq_query(int n, int64_t nb, const int* __restrict__ W1, const int* __restrict__ W2,
                             const int* __restrict__ pre1, const int* __restrict__ suf1, const int* __restrict__ pre2,
                             const int* __restrict__ suf2, const int* __restrict__ tmin, const int* __restrict__ tmax,
-                            int4* rec, int* status) {
+                            int4* rec, int mode, int* __restrict__ cover, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int4 me = rec[v];
+  if (mode == QUERY_RECHECK && me.w != 2) return;
   const int l = me.x, r = me.y;
   if (l < 0 || r < l || r >= n) {
     atomicExch(status, (int)FASTBCC_ERR_HIP);
     rec[v] = make_int4(0, n - 1, -1, 0);
+    return;
+  }
+  const int p = me.z;
+  if (p < 0) return;
+  const int4 pr = rec[p];
+  if (mode == QUERY_CERTIFY && pr.z < 0) {
+    rec[v].w = 1;
     return;
   }
   const int bl = l / WAVE, br = r / WAVE;
@@ -940,11 +1048,116 @@ __global__ void k_rmq_query(int n, int64_t nb, const int* __restrict__ W1, const
       hi = x2 > hi ? x2 : hi;
     }
   }
-  const int p = me.z;
-  if (p >= 0) {
-    const int4 pr = rec[p];
-    if (pr.x <= lo && pr.y >= hi) rec[v].w = 1;
+  const bool fence = pr.x <= lo && pr.y >= hi;
+  if (mode == QUERY_CERTIFY) {
+    if (fence) {
+      rec[v].w = 2;
+      atomicAdd(cover + l, 1);
+      atomicAdd(cover + r + 1, -1);
+    }
+  } else if (mode == QUERY_RECHECK || fence) {
+    rec[v].w = fence ? 1 : 0;
   }
+}
+
+// ------------------------------------------------------------ sampled tags
+// Tags from a sample of each row: TAG_SAMPLES hashed neighbours, or the whole
+// row when it is no longer (then the tags are exact).  Sampled w1 can only
+// be higher and w2 only lower than the exact ones, which is what the
+// certification pass relies on.
+constexpr int TAG_SAMPLES = 4;
+
+__global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ first,
+                             int n, int* __restrict__ w1, int* __restrict__ w2) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const int f = first[x];
+  int mn = f, mx = f;
+  const int b = off[x], d = off[x + 1] - b;
+  if (d <= TAG_SAMPLES) {
+    for (int k = 0; k < d; ++k) {
+      const int y = adj[b + k];
+      if (y == x) continue;
+      const int fy = first[y];
+      mn = fy < mn ? fy : mn;
+      mx = fy > mx ? fy : mx;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < TAG_SAMPLES; ++k) {
+      const int y = adj[b + sample_pos(x, k, d)];
+      if (y == x) continue;
+      const int fy = first[y];
+      mn = fy < mn ? fy : mn;
+      mx = fy > mx ? fy : mx;
+    }
+  }
+  w1[x] = mn;
+  w2[x] = mx;
+}
+
+// Slot i of the preorder: the row order[i] needs exact tags when an undecided
+// interval covers i (cover = exclusive scan of the difference array, so the
+// count at i is cover[i + 1]) and its tags were sampled.
+__global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__ order,
+                            const int* __restrict__ cover, int n, int* __restrict__ fdeg, int* __restrict__ fflag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool in = false;
+  int d = 0;
+  if (cover[i + 1] > 0) {
+    const int x = order[i];
+    d = off[x + 1] - off[x];
+    in = d > TAG_SAMPLES;
+  }
+  fdeg[i] = in ? d : 0;
+  fflag[i] = in ? 1 : 0;
+}
+
+// Exact w1/w2 for the listed rows (all their arcs), then their preorder slots.
+__global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
+                            const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
+                            int tw, const int* __restrict__ first, int* __restrict__ w1, int* __restrict__ w2) {
+  const int R = *frows;
+  const int64_t F = fstart[R];
+  arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
+    int mn = INT32_MAX, mx = INT32_MIN;
+    const int key = ok ? i : -1;
+    int x = -1;
+    if (ok) {
+      x = frow[i];
+      const int y = adj[(int64_t)off[x] + (k - (int64_t)fstart[i])];
+      if (y != x) mn = mx = first[y];
+    }
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      int k2 = __shfl_up(key, o, WAVE);
+      int m2 = __shfl_up(mn, o, WAVE);
+      int x2 = __shfl_up(mx, o, WAVE);
+      if (lane >= o && k2 == key) {
+        mn = m2 < mn ? m2 : mn;
+        mx = x2 > mx ? x2 : mx;
+      }
+    }
+    const int knext = __shfl_down(key, 1, WAVE);
+    const bool tail = (lane == WAVE - 1) || knext != key;
+    if (tail && key >= 0 && mn != INT32_MAX) {
+      atomicMin(w1 + x, mn);
+      atomicMax(w2 + x, mx);
+    }
+  });
+}
+
+__global__ void k_rmq_rescatter(const int* __restrict__ frow, const int* __restrict__ frows,
+                                const int* __restrict__ first, const int* __restrict__ w1,
+                                const int* __restrict__ w2, int* __restrict__ W1, int* __restrict__ W2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= *frows) return;
+  const int x = frow[r], f = first[x];
+  const int a = w1[x], b = w2[x];
+  W1[f] = a < f ? a : f;
+  W2[f] = b > f ? b : f;
 }
 
 // ------------------------------------------------------------ Last-CC
@@ -1148,6 +1361,7 @@ __global__ void __launch_bounds__(BLOCK) k_big_canon(const int* __restrict__ off
 // root); arcs of that row update minid[L].  Arcs of the largest label get
 // its final canonical label; the others get the raw label encoded as -2 - L
 // (self-loops -1), resolved by pass 2.
+template <bool DBITS>
 __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                             const int* __restrict__ tile_row, int tw, const int2* __restrict__ vlh,
                             const uint8_t* __restrict__ heads, const unsigned long long* __restrict__ bits,
@@ -1165,7 +1379,7 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
     const int2 rx = vlh[x];  // (l[x], head(l[x]))
     const int lx = rx.x, hx = rx.y;
     int L = lx, m = (hx >= 0 && hx < lx) ? hx : lx;
-    if (heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull)) {
+    if (heads[x] && (!DBITS || ((dbits[a / WAVE] >> (a % WAVE)) & 1ull))) {
       const int2 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? make_int2(big, hbig) : vlh[y];
       if (ry.x != lx && hx != y) {
         L = ry.x;
@@ -1326,7 +1540,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, foff, frank);
     scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
     scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
-    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, frow, fstart);
+    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)nullptr, frow,
+           fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
   };
 
@@ -1385,7 +1600,14 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_root_flags, gn, BLOCK, cc, toff, n, rootidx, lone);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   scan_inplace(c, lone, n, nullptr, tmp, lone + n);
-  LAUNCH(c, k_root_list, gn, BLOCK, cc, toff, rootidx, n, roots);
+  int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
+  if (n > 0) {
+    fill_i32(c, rdeg, -1, n);
+    LAUNCH(c, k_giant_hub, 1, 1024, off, cc, n, scal);
+    LAUNCH(c, k_root_degree, gn, BLOCK, off, cc, n, scal, rdeg);
+    LAUNCH(c, k_root_select, gn, BLOCK, off, cc, n, rdeg, rsel);
+  }
+  LAUNCH(c, k_root_list, gn, BLOCK, cc, toff, rootidx, rdeg, rsel, scal, n, roots);
   const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
   const unsigned gnode = grid_for(nodes_max);
   LAUNCH(c, k_euler_next, gnode, BLOCK, toff, tadj, twin, cc, rootidx, roots, n, next);
@@ -1419,17 +1641,45 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int4* rec = (int4*)(w + L.rec);
   LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, lone, n, pos, eflag, first, rec, scal + S_STATUS);
   LAUNCH(c, k_lone_tags, gn, BLOCK, lone, n, first, rec);
-  fill_i32(c, w1, INT32_MAX, n);
-  fill_i32(c, w2, INT32_MIN, n);
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
-  LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
   int *W1 = I(L.W1), *W2 = I(L.W2), *pre1 = I(L.pre1), *suf1 = I(L.suf1), *pre2 = I(L.pre2), *suf2 = I(L.suf2);
   int *tmin = I(L.tmin), *tmax = I(L.tmax);
-  LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, scal + S_STATUS);
-  LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W1, W2, n, L.nb, pre1, suf1, pre2, suf2, tmin,
-         tmax);
-  for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tmin, tmax, L.nb, j);
-  LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, scal + S_STATUS);
+  auto rmq_tables = [&]() {
+    LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W1, W2, n, L.nb, pre1, suf1, pre2, suf2, tmin,
+           tmax);
+    for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tmin, tmax, L.nb, j);
+  };
+  if (!tune.sampled_tags) {
+    fill_i32(c, w1, INT32_MAX, n);
+    fill_i32(c, w2, INT32_MIN, n);
+    LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
+    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, (int*)nullptr, scal + S_STATUS);
+    rmq_tables();
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_EXACT,
+           (int*)nullptr, scal + S_STATUS);
+  } else {
+    // sampled tags certify most non-fences; exact tags for the subtrees of the
+    // undecided vertices only
+    int* order = pos;     // preorder -> vertex; the tour positions are dead now
+    int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
+    fill_i32(c, cover, 0, (int64_t)n + 2);
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, first, n, w1, w2);
+    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, order, scal + S_STATUS);
+    rmq_tables();
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_CERTIFY,
+           cover, scal + S_STATUS);
+    scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
+    LAUNCH(c, k_dirty_deg, gn, BLOCK, off, order, cover, n, foff, frank);
+    scan_inplace(c, foff, n, nullptr, tmp, foff + n);
+    scan_inplace(c, frank, n, nullptr, tmp, frows);
+    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, order, frow, fstart);
+    LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
+    LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, w1, w2);
+    LAUNCH(c, k_rmq_rescatter, gn, BLOCK, frow, frows, first, w1, w2, W1, W2);
+    rmq_tables();
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_RECHECK,
+           (int*)nullptr, scal + S_STATUS);
+  }
 
   // ---- Last-CC on the implicit skeleton
   int* lab = I(L.lab);
@@ -1464,8 +1714,12 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_big_canon, 1, BLOCK, off, adj, rec, lab, head, heads, vbegin, G, scal);
   int2* vlh = (int2*)(w + L.ol);  // the list-ranking array is dead by now
   LAUNCH(c, k_vertex_lh, gn, BLOCK, lab, head, n, vlh);
-  LAUNCH(c, k_bcc_label, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits, head, scal,
-         minid, out_label);
+  if (tune.sampled_tags)
+    LAUNCH(c, k_bcc_label<false>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits, head,
+           scal, minid, out_label);
+  else
+    LAUNCH(c, k_bcc_label<true>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits, head,
+           scal, minid, out_label);
   LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, canon);
   if (A > 0) {
     if (((uintptr_t)out_label & 15) == 0) {

@@ -1,12 +1,13 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes five speed-only knobs in its flags word (they never change
+The C ABI exposes six speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
 sampling off), the First-CC union-find variant (hook by id or by hashed
 priority), an optional low-diameter decomposition in front of First-CC's
-union-find (the paper's LDD-UF-JTB shape) with its beta, and the arc-tile
-size (64-arc windows per wave, i.e. work per wave).  The tuner times candidates by
+union-find (the paper's LDD-UF-JTB shape) with its beta, exact or
+sampled-and-certified tags, and the arc-tile size (64-arc windows per wave,
+i.e. work per wave).  The tuner times candidates by
 coordinate descent on the real input and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
 """
@@ -28,7 +29,8 @@ SAMPLE = (0, 1, 2)
 TILE = (2, 3, 4, 5)
 UF = (0, 1)  # First-CC union-find: 0 = min-id hooking, 1 = hashed-priority hooking
 LDD = (0, 1, 2)  # First-CC low-diameter decomposition first: 0 = off, k = beta 2^-k
-START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0}
+TAGS = (0, 1)  # 0 = exact tag sweep over every arc, 1 = sampled-tag certification
+START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0}
 
 
 def skew_class(degrees: np.ndarray) -> str:
@@ -51,7 +53,8 @@ def cache_key(arch: str, n: int, arcs: int, graphs: int, skew: str) -> str:
 
 def encode(cfg: Dict[str, int]) -> int:
     return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"],
-                        cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)))
+                        cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)),
+                        sampled_tags=bool(cfg.get("tags", 0)))
 
 
 class Tuner:
@@ -96,7 +99,8 @@ class Tuner:
 
         for _ in range(2):
             changed = False
-            for knob, values in (("uf", UF), ("ldd", LDD), ("sample", SAMPLE), ("tile", TILE), ("ruler", RULER)):
+            for knob, values in (("tags", TAGS), ("uf", UF), ("ldd", LDD), ("sample", SAMPLE), ("tile", TILE),
+                                 ("ruler", RULER)):
                 best_v, best_t = cfg[knob], cost(cfg)
                 for v in values:
                     c = dict(cfg, **{knob: v})

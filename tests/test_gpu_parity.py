@@ -114,6 +114,8 @@ def test_multigraph_self_loops_unsorted_rows():
     N.tune_flags(sample_rounds=1), N.tune_flags(tile_shift=6), N.tune_flags(ruler_shift=7, tile_shift=3),
     N.tune_flags(cc_priority=True), N.tune_flags(cc_priority=True, sample_rounds=0),
     N.tune_flags(ldd=1), N.tune_flags(ldd=3, sample_rounds=0), N.tune_flags(ldd=2, cc_priority=True),
+    N.tune_flags(sampled_tags=True), N.tune_flags(sampled_tags=True, cc_priority=True, tile_shift=3),
+    N.tune_flags(sampled_tags=True, ldd=1, sample_rounds=0),
 ])
 @pytest.mark.parametrize("cfg", ["rmat_small", "grid_small"])
 def test_tuning_fields_never_change_results(flags, cfg):
