@@ -19,7 +19,8 @@
  * (int32 vertex ids).  Every undirected edge u-w is stored as two arcs,
  * u->w in row u and w->u in row w.  Parallel edges are allowed (they always
  * share a BCC); self-loop arcs are allowed and get label -1.  Rows need not
- * be sorted for the solve (FASTBCC_FLAG_VALIDATE requires sorted rows).
+ * be sorted for the solve (FASTBCC_FLAG_VALIDATE requires sorted rows);
+ * FASTBCC_FLAG_SORTED_ROWS lets the edge-label read-out use that they are.
  *
  * Output conventions:
  *   out_edge_label[a]  smallest arc index of the BCC that arc a belongs to
@@ -70,6 +71,12 @@ typedef enum fastbcc_status {
                                       FASTBCC_ERR_INVALID_GRAPH if it is not a
                                       symmetric CSR with sorted rows and ids in
                                       range; nothing else is launched then */
+#define FASTBCC_FLAG_SORTED_ROWS 0x2u /* the caller guarantees ascending rows:
+                                         the edge-label read-out then finds
+                                         reverse arcs by binary search instead
+                                         of gathering per arc.  Unsorted rows
+                                         with this flag give wrong labels (no
+                                         access leaves its row). */
 /* Tuning fields (0 = built-in default).  They change speed, never results.
  *   bits 8-11  log2 of the list-ranking ruler spacing, 3..10
  *   bits 12-13 union-find sampling rounds before the full sweep, 0..3 (value 3 = none)

@@ -21,6 +21,7 @@ ERR_HIP = 4
 ERR_INVALID_GRAPH = 5
 
 FLAG_VALIDATE = 0x1
+FLAG_SORTED_ROWS = 0x2
 TUNE_RULER_SHIFT = 8
 TUNE_SAMPLE_SHIFT = 12
 TUNE_TILE_SHIFT = 14

@@ -194,7 +194,7 @@ struct Tune {
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
-  const uint32_t known = FASTBCC_FLAG_VALIDATE | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
+  const uint32_t known = FASTBCC_FLAG_VALIDATE | FASTBCC_FLAG_SORTED_ROWS | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
                          FASTBCC_TUNE_SAMPLED_TAGS;
@@ -1361,14 +1361,26 @@ __global__ void __launch_bounds__(BLOCK) k_big_canon(const int* __restrict__ off
 // root); arcs of that row update minid[L].  Arcs of the largest label get
 // its final canonical label; the others get the raw label encoded as -2 - L
 // (self-loops -1), resolved by pass 2.
-template <bool DBITS>
+// How pass 1 learns l[y] in the rows of heads:
+//   LABEL_BITMAP  every arc gathers (bitmap bit, else the record of y);
+//   LABEL_DBITS   only arcs to proper descendants (bits from the tag sweep);
+//   LABEL_MIRROR  rows are sorted: only the rows marked exact gather; every
+//                 other head row writes l[x] and k_bcc_mirror then rewrites
+//                 the arcs x->y with x = head(l[y]) (the only arcs of such a
+//                 row outside l[x]: l[y] != l[x] makes x the head of l[y]).
+enum LabelMode : int { LABEL_BITMAP = 0, LABEL_DBITS = 1, LABEL_MIRROR = 2 };
+
+__device__ __forceinline__ int bcc_min_vertex(int L, int h) { return (h >= 0 && h < L) ? h : L; }
+
+template <int MODE>
 __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                            const int* __restrict__ tile_row, int tw, const int2* __restrict__ vlh,
+                            const int* __restrict__ tile_row, int tw, const int4* __restrict__ vlh,
                             const uint8_t* __restrict__ heads, const unsigned long long* __restrict__ bits,
                             const unsigned long long* __restrict__ dbits, const int* __restrict__ head,
                             const int* __restrict__ scal, int* __restrict__ minid, int* __restrict__ out) {
   const int big = scal[S_LBIG];
   const int hbig = head[big];
+  const int4 rbig = make_int4(big, hbig, bcc_min_vertex(big, hbig), 0);
   const int canon_big = scal[S_CANON_BIG];
   arc_windows(off, adj, n, A, tile_row, tw, [&](int64_t a, int x, bool ok, int y) {
     if (!ok) return;
@@ -1376,14 +1388,17 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
       __builtin_nontemporal_store(-1, out + a);
       return;
     }
-    const int2 rx = vlh[x];  // (l[x], head(l[x]))
-    const int lx = rx.x, hx = rx.y;
-    int L = lx, m = (hx >= 0 && hx < lx) ? hx : lx;
-    if (heads[x] && (!DBITS || ((dbits[a / WAVE] >> (a % WAVE)) & 1ull))) {
-      const int2 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? make_int2(big, hbig) : vlh[y];
-      if (ry.x != lx && hx != y) {
+    const int4 rx = vlh[x];  // (l[x], head(l[x]), smallest vertex of l[x]'s BCC, exact-row flag)
+    int L = rx.x, m = rx.z;
+    bool look;
+    if (MODE == LABEL_MIRROR) look = rx.w != 0;
+    else if (MODE == LABEL_DBITS) look = heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull);
+    else look = heads[x] != 0;
+    if (look) {
+      const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
+      if (ry.x != rx.x && rx.y != y) {
         L = ry.x;
-        m = (ry.y >= 0 && ry.y < ry.x) ? ry.y : ry.x;
+        m = ry.z;
       }
     }
     __builtin_nontemporal_store((L == big && canon_big >= 0) ? canon_big : -2 - L, out + a);
@@ -1391,13 +1406,41 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
   });
 }
 
-// (l[v], head(l[v])) per vertex: one 8-byte gather in the edge-label pass
-// instead of two dependent ones.
-__global__ void k_vertex_lh(const int* __restrict__ lab, const int* __restrict__ head, int n, int2* __restrict__ vlh) {
+// Per vertex: (l, head(l), smallest vertex of the BCC, exact-row flag).  A
+// head row stays exact (gathers per arc in the mirror mode) when x is a tree
+// root, heads the largest label, or is the smallest vertex of its own BCC
+// (its arcs update minid[l[x]], so none may be mislabelled there first).
+__global__ void k_vertex_lh(const int* __restrict__ lab, const int* __restrict__ head,
+                            const uint8_t* __restrict__ heads, const int4* __restrict__ rec,
+                            const int* __restrict__ scal, int n, int4* __restrict__ vlh) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int l = lab[v];
-  vlh[v] = make_int2(l, head[l]);
+  const int l = lab[v], h = head[l], m = bcc_min_vertex(l, h);
+  const bool exact = heads[v] && (rec[v].z < 0 || v == head[scal[S_LBIG]] || m == v);
+  vlh[v] = make_int4(l, h, m, exact ? 1 : 0);
+}
+
+// Mirror pass (sorted rows): vertex y whose label L is not the largest and
+// whose BCC head h is adjacent to it: the arcs h->y (found by binary search in
+// h's row) lie in L.
+__global__ void k_bcc_mirror(const int* __restrict__ off, const int* __restrict__ adj, int n,
+                             const int4* __restrict__ vlh, const int* __restrict__ scal, int* __restrict__ minid,
+                             int* __restrict__ out) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= n) return;
+  const int4 r = vlh[y];
+  const int L = r.x, h = r.y;
+  if (h < 0 || L == scal[S_LBIG]) return;
+  int lo = off[h], hi = off[h + 1];
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if (adj[mid] < y) lo = mid + 1;
+    else hi = mid;
+  }
+  const int e = off[h + 1];
+  if (lo >= e || adj[lo] != y) return;
+  if (r.z == h) atomicMin(minid + L, lo);
+  for (int a = lo; a < e && adj[a] == y; ++a) out[a] = -2 - L;
 }
 
 // canon[L] = smallest arc of BCC L, made graph-local for batches.
@@ -1524,7 +1567,7 @@ void scan_inplace(Ctx& c, int* data, int64_t max_count, const int* count_dev, in
 // The solve proper, on int32 offsets.
 fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* off, const int* adj, int G,
                           const int* vbegin, int* out_label, uint8_t* out_ap, int64_t* out_nbcc, char* w,
-                          const Tune& tune, bool validate) {
+                          const Tune& tune, bool validate, bool sorted_rows) {
   auto I = [&](size_t o) { return (int*)(w + o); };
   int* scal = I(L.scalars);
   const int tw = tune.tile_windows;
@@ -1712,14 +1755,18 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_lbig, 1, 1, lab, scal);
   LAUNCH(c, k_big_bitmap, (unsigned)cdiv((int64_t)n, BLOCK), BLOCK, lab, n, scal, bigbits);
   LAUNCH(c, k_big_canon, 1, BLOCK, off, adj, rec, lab, head, heads, vbegin, G, scal);
-  int2* vlh = (int2*)(w + L.ol);  // the list-ranking array is dead by now
-  LAUNCH(c, k_vertex_lh, gn, BLOCK, lab, head, n, vlh);
-  if (tune.sampled_tags)
-    LAUNCH(c, k_bcc_label<false>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits, head,
-           scal, minid, out_label);
+  int4* vlh = (int4*)(w + L.ol);  // the list-ranking array (16n + 8 bytes) is dead by now
+  LAUNCH(c, k_vertex_lh, gn, BLOCK, lab, head, heads, rec, scal, n, vlh);
+  if (sorted_rows)
+    LAUNCH(c, k_bcc_label<LABEL_MIRROR>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
+           head, scal, minid, out_label);
+  else if (!tune.sampled_tags)
+    LAUNCH(c, k_bcc_label<LABEL_DBITS>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
+           head, scal, minid, out_label);
   else
-    LAUNCH(c, k_bcc_label<true>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits, head,
-           scal, minid, out_label);
+    LAUNCH(c, k_bcc_label<LABEL_BITMAP>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
+           head, scal, minid, out_label);
+  if (sorted_rows) LAUNCH(c, k_bcc_mirror, gn, BLOCK, off, adj, n, vlh, scal, minid, out_label);
   LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, canon);
   if (A > 0) {
     if (((uintptr_t)out_label & 15) == 0) {
@@ -1763,6 +1810,7 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
   if (n == 0) return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
 
   const bool validate = (flags & FASTBCC_FLAG_VALIDATE) != 0;
+  const bool sorted_rows = (flags & FASTBCC_FLAG_SORTED_ROWS) != 0;
   if (validate) {
     LAUNCH(c, k_validate_rows<OffT>, grid_for(n64 + 1), BLOCK, off, n, A, scal + S_STATUS);
     int h = 0;
@@ -1781,7 +1829,7 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
   } else {
     off32 = (const int*)off;
   }
-  return solve_core(L, c, n, A, off32, adj, G, vbegin, out_label, out_ap, out_nbcc, w, tune, validate);
+  return solve_core(L, c, n, A, off32, adj, G, vbegin, out_label, out_ap, out_nbcc, w, tune, validate, sorted_rows);
 }
 
 }  // namespace

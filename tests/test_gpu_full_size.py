@@ -25,7 +25,8 @@ def test_rmat25_full_size_exact():
     off = torch.from_numpy(g.offsets).to(DEV)  # int64 offsets, as benchmarked
     adj = torch.from_numpy(g.adj).to(DEV)
     outs = []
-    for flags in (0, N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True), N.tune_flags(ldd=1), N.tune_flags(sampled_tags=True, cc_priority=True)):
+    for flags in (0, N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True), N.tune_flags(ldd=1),
+                  N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True)):
         note(f"R-MAT scale 25: GPU solve flags={flags:#x}")
         r = solve(off, adj, flags=flags)
         torch.cuda.synchronize()

@@ -57,6 +57,43 @@ def test_small_configs(name, off64):
     assert_parity(g, gpu_solve(g, off64), name)
 
 
+SORTED_FLAGS = [
+    N.FLAG_SORTED_ROWS,
+    N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True),
+    N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True, ruler_shift=7, tile_shift=4),
+    N.FLAG_SORTED_ROWS | N.tune_flags(ldd=1, sample_rounds=0),
+]
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("flags", SORTED_FLAGS)
+def test_sorted_row_read_out(name, flags):
+    """The mirror read-out (sorted rows) against the oracle, alone and with
+    the other tuning variants."""
+    note(f"{name} flags={flags:#x}")
+    g = gen.config(name)
+    assert_parity(g, gpu_solve(g, flags=flags), f"{name} {flags:#x}")
+
+
+@pytest.mark.parametrize("flags", SORTED_FLAGS[:2])
+def test_sorted_row_read_out_multigraphs(flags):
+    """Sorted multigraphs with self-loops: copies of an edge to a head are
+    mirrored together."""
+    rng = np.random.default_rng(11)
+    for t in range(40):
+        n = int(rng.integers(2, 60))
+        m = int(rng.integers(0, 3 * n))
+        edges = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(m)]
+        edges += edges[: int(rng.integers(0, 6))]
+        edges += [(i, i + 1) for i in range(0, n - 1, 3)]  # pendant paths and bridges
+        g = gen.multigraph_csr(n, edges)
+        for v in range(n):
+            row = g.adj[g.offsets[v] : g.offsets[v + 1]]
+            assert np.all(row[1:] >= row[:-1]), "generator rows must be sorted"
+        note(f"sorted multigraph #{t} n={n} arcs={g.num_arcs} flags={flags:#x}")
+        assert_parity(g, gpu_solve(g, flags=flags), f"sorted multigraph {t}")
+
+
 def cycle(n):
     return [(i, (i + 1) % n) for i in range(n)]
 
