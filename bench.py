@@ -51,10 +51,10 @@ def alg_bytes(kernel, n, A):
         # offsets + adjacency + first[y] per arc + (first, last) of the row vertex
         # + w1/w2 read-modify-write per row + one descendant bit per arc
         "k_tag_sweep": 4 * (n + 1) + 8 * A + 24 * n + A // 8,
-        # offsets + adjacency + label write per arc + (l, head) record and head
-        # flag of the row vertex + descendant bits; the gathers for descendant
-        # arcs of head rows are left out, so this is a lower bound
-        "k_bcc_label": 4 * (n + 1) + 8 * A + 9 * n + A // 8,
+        # offsets + adjacency + label write per arc + the 16-byte record of the
+        # row vertex (sorted-rows read-out: the few exact rows' gathers are
+        # left out, so this is a lower bound)
+        "k_bcc_label": 4 * (n + 1) + 8 * A + 16 * n,
         # label read + label write per arc (canonical-label lookups hit the few hot labels)
         "k_bcc_remap4": 8 * A,
     }

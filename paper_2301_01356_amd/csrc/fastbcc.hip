@@ -1382,28 +1382,32 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
   const int hbig = head[big];
   const int4 rbig = make_int4(big, hbig, bcc_min_vertex(big, hbig), 0);
   const int canon_big = scal[S_CANON_BIG];
-  arc_windows(off, adj, n, A, tile_row, tw, [&](int64_t a, int x, bool ok, int y) {
-    if (!ok) return;
-    if (y == x) {
-      __builtin_nontemporal_store(-1, out + a);
-      return;
-    }
-    const int4 rx = vlh[x];  // (l[x], head(l[x]), smallest vertex of l[x]'s BCC, exact-row flag)
-    int L = rx.x, m = rx.z;
-    bool look;
-    if (MODE == LABEL_MIRROR) look = rx.w != 0;
-    else if (MODE == LABEL_DBITS) look = heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull);
-    else look = heads[x] != 0;
-    if (look) {
-      const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
-      if (ry.x != rx.x && rx.y != y) {
-        L = ry.x;
-        m = ry.z;
-      }
-    }
-    __builtin_nontemporal_store((L == big && canon_big >= 0) ? canon_big : -2 - L, out + a);
-    if (m == x) atomicMin(minid + L, (int)a);
-  });
+  arc_windows2(
+      off, adj, n, A, tile_row, tw,
+      [&](int x, int, bool ok) { return ok ? vlh[x] : make_int4(0, -1, -1, 0); },
+      [&](int64_t a, int x, bool ok, int y, int4 rx) {
+        if (!ok) return;
+        if (y == x) {
+          __builtin_nontemporal_store(-1, out + a);
+          return;
+        }
+        // rx = (l[x], head(l[x]), smallest vertex of l[x]'s BCC, exact-row flag)
+        int L = rx.x, m = rx.z;
+        bool look;
+        if (MODE == LABEL_MIRROR) look = rx.w != 0;
+        else if (MODE == LABEL_DBITS) look = heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull);
+        else look = heads[x] != 0;
+        if (look) {
+          const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
+          if (ry.x != rx.x && rx.y != y) {
+            L = ry.x;
+            m = ry.z;
+          }
+        }
+        const bool final_big = L == big && canon_big >= 0;
+        __builtin_nontemporal_store(final_big ? canon_big : -2 - L, out + a);
+        if (m == x && !final_big) atomicMin(minid + L, (int)a);
+      });
 }
 
 // Per vertex: (l, head(l), smallest vertex of the BCC, exact-row flag).  A
@@ -1443,12 +1447,17 @@ __global__ void k_bcc_mirror(const int* __restrict__ off, const int* __restrict_
   for (int a = lo; a < e && adj[a] == y; ++a) out[a] = -2 - L;
 }
 
-// canon[L] = smallest arc of BCC L, made graph-local for batches.
+// canon[L] = smallest arc of BCC L, made graph-local for batches (the
+// largest label's was found before pass 1, which then skips its minid).
 __global__ void k_bcc_canon(const int4* __restrict__ rec, const int* __restrict__ lab,
                             const int* __restrict__ minid, int n, const int* __restrict__ vbegin, int G,
-                            const int* __restrict__ off, int* __restrict__ canon) {
+                            const int* __restrict__ off, const int* __restrict__ scal, int* __restrict__ canon) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || !is_bcc_label(rec, lab, v)) return;
+  if (v == scal[S_LBIG] && scal[S_CANON_BIG] >= 0) {
+    canon[v] = scal[S_CANON_BIG];
+    return;
+  }
   int c = minid[v];
   if (G > 1) c -= off[vbegin[graph_of(vbegin, G, v)]];
   canon[v] = c;
@@ -1767,7 +1776,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_bcc_label<LABEL_BITMAP>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
            head, scal, minid, out_label);
   if (sorted_rows) LAUNCH(c, k_bcc_mirror, gn, BLOCK, off, adj, n, vlh, scal, minid, out_label);
-  LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, canon);
+  LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, scal, canon);
   if (A > 0) {
     if (((uintptr_t)out_label & 15) == 0) {
       const int64_t n4 = A / 4;
