@@ -89,13 +89,16 @@ typedef enum fastbcc_status {
  *   bit  20    Tagging from sampled tags: fences are certified from a few
  *              sampled neighbours per vertex (the tags of Section "Tagging"
  *              computed on a subset of the edges) and exact tags are swept
- *              only for the subtrees still undecided */
+ *              only for the subtrees still undecided
+ *   bits 21-22 sampled neighbours per vertex in that mode: 0 = 4, 1 = 2,
+ *              2 = 3, 3 = 6 */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
 #define FASTBCC_TUNE_CC_PRIORITY 0x20000u
 #define FASTBCC_TUNE_LDD_SHIFT 18
 #define FASTBCC_TUNE_SAMPLED_TAGS 0x100000u
+#define FASTBCC_TUNE_TAG_SAMPLES_SHIFT 21
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -191,14 +191,17 @@ struct Tune {
   bool cc_prio = false;  // First-CC hooks by hashed priority instead of by id
   int ldd = 0;           // First-CC starts with a low-diameter decomposition, beta = 2^-ldd (0 = off)
   bool sampled_tags = false;  // fences certified from sampled tags, exact tags only where needed
+  int tag_samples = 4;        // sampled neighbours per vertex in that mode
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
   const uint32_t known = FASTBCC_FLAG_VALIDATE | FASTBCC_FLAG_SORTED_ROWS | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
-                         FASTBCC_TUNE_SAMPLED_TAGS;
+                         FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT);
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
+  static const int kSamples[4] = {4, 2, 3, 6};
+  t.tag_samples = kSamples[(flags >> FASTBCC_TUNE_TAG_SAMPLES_SHIFT) & 0x3];
   t.cc_prio = (flags & FASTBCC_TUNE_CC_PRIORITY) != 0;
   t.ldd = (int)((flags >> FASTBCC_TUNE_LDD_SHIFT) & 0x3);
   if (flags & ~known) return false;
@@ -1061,20 +1064,18 @@ __global__ void k_rmq_query(int n, int64_t nb, const int* __restrict__ W1, const
 }
 
 // ------------------------------------------------------------ sampled tags
-// Tags from a sample of each row: TAG_SAMPLES hashed neighbours, or the whole
-// row when it is no longer (then the tags are exact).  Sampled w1 can only
-// be higher and w2 only lower than the exact ones, which is what the
-// certification pass relies on.
-constexpr int TAG_SAMPLES = 4;
-
+// Tags from a sample of each row: ks hashed neighbours, or the whole row when
+// it is no longer (then the tags are exact).  Sampled w1 can only be higher
+// and w2 only lower than the exact ones, which is what the certification
+// pass relies on.
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ first,
-                             int n, int* __restrict__ w1, int* __restrict__ w2) {
+                             int n, int ks, int* __restrict__ w1, int* __restrict__ w2) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
   const int f = first[x];
   int mn = f, mx = f;
   const int b = off[x], d = off[x + 1] - b;
-  if (d <= TAG_SAMPLES) {
+  if (d <= ks) {
     for (int k = 0; k < d; ++k) {
       const int y = adj[b + k];
       if (y == x) continue;
@@ -1083,8 +1084,7 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
       mx = fy > mx ? fy : mx;
     }
   } else {
-#pragma unroll
-    for (int k = 0; k < TAG_SAMPLES; ++k) {
+    for (int k = 0; k < ks; ++k) {
       const int y = adj[b + sample_pos(x, k, d)];
       if (y == x) continue;
       const int fy = first[y];
@@ -1100,7 +1100,8 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
 // interval covers i (cover = exclusive scan of the difference array, so the
 // count at i is cover[i + 1]) and its tags were sampled.
 __global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__ order,
-                            const int* __restrict__ cover, int n, int* __restrict__ fdeg, int* __restrict__ fflag) {
+                            const int* __restrict__ cover, int n, int ks, int* __restrict__ fdeg,
+                            int* __restrict__ fflag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   bool in = false;
@@ -1108,7 +1109,7 @@ __global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__
   if (cover[i + 1] > 0) {
     const int x = order[i];
     d = off[x + 1] - off[x];
-    in = d > TAG_SAMPLES;
+    in = d > ks;
   }
   fdeg[i] = in ? d : 0;
   fflag[i] = in ? 1 : 0;
@@ -1361,14 +1362,11 @@ __global__ void __launch_bounds__(BLOCK) k_big_canon(const int* __restrict__ off
 // root); arcs of that row update minid[L].  Arcs of the largest label get
 // its final canonical label; the others get the raw label encoded as -2 - L
 // (self-loops -1), resolved by pass 2.
-// How pass 1 learns l[y] in the rows of heads:
+// How pass 1 learns l[y] in the rows of heads (unsorted rows; sorted rows
+// take the one-pass read-out below):
 //   LABEL_BITMAP  every arc gathers (bitmap bit, else the record of y);
-//   LABEL_DBITS   only arcs to proper descendants (bits from the tag sweep);
-//   LABEL_MIRROR  rows are sorted: only the rows marked exact gather; every
-//                 other head row writes l[x] and k_bcc_mirror then rewrites
-//                 the arcs x->y with x = head(l[y]) (the only arcs of such a
-//                 row outside l[x]: l[y] != l[x] makes x the head of l[y]).
-enum LabelMode : int { LABEL_BITMAP = 0, LABEL_DBITS = 1, LABEL_MIRROR = 2 };
+//   LABEL_DBITS   only arcs to proper descendants (bits from the tag sweep).
+enum LabelMode : int { LABEL_BITMAP = 0, LABEL_DBITS = 1 };
 
 __device__ __forceinline__ int bcc_min_vertex(int L, int h) { return (h >= 0 && h < L) ? h : L; }
 
@@ -1394,8 +1392,7 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
         // rx = (l[x], head(l[x]), smallest vertex of l[x]'s BCC, exact-row flag)
         int L = rx.x, m = rx.z;
         bool look;
-        if (MODE == LABEL_MIRROR) look = rx.w != 0;
-        else if (MODE == LABEL_DBITS) look = heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull);
+        if (MODE == LABEL_DBITS) look = heads[x] && ((dbits[a / WAVE] >> (a % WAVE)) & 1ull);
         else look = heads[x] != 0;
         if (look) {
           const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
@@ -1424,27 +1421,150 @@ __global__ void k_vertex_lh(const int* __restrict__ lab, const int* __restrict__
   vlh[v] = make_int4(l, h, m, exact ? 1 : 0);
 }
 
-// Mirror pass (sorted rows): vertex y whose label L is not the largest and
-// whose BCC head h is adjacent to it: the arcs h->y (found by binary search in
-// h's row) lie in L.
-__global__ void k_bcc_mirror(const int* __restrict__ off, const int* __restrict__ adj, int n,
-                             const int4* __restrict__ vlh, const int* __restrict__ scal, int* __restrict__ minid,
-                             int* __restrict__ out) {
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= n) return;
-  const int4 r = vlh[y];
-  const int L = r.x, h = r.y;
-  if (h < 0 || L == scal[S_LBIG]) return;
+// ---- final labels in one pass (sorted rows): canonical labels first
+// The smallest arc of BCC L lies in the row of its smallest vertex m(L).
+// When m(L) is the head h, that arc is h->y for the smallest member y next to
+// h: the mirror search below finds every arc h->y anyway.  Otherwise m(L) = L
+// (a member, the Last-CC root): a non-head's row lies wholly in L, so its
+// first arc that is not a self-loop; a head's row is scanned with the exact
+// rule until its first arc in L.
+
+// Binary search of y in h's row (first copy), -1 if absent.
+__device__ __forceinline__ int row_lower(const int* __restrict__ off, const int* __restrict__ adj, int h, int y) {
   int lo = off[h], hi = off[h + 1];
+  const int e = hi;
   while (lo < hi) {
     const int mid = lo + ((hi - lo) >> 1);
     if (adj[mid] < y) lo = mid + 1;
     else hi = mid;
   }
-  const int e = off[h + 1];
-  if (lo >= e || adj[lo] != y) return;
-  if (r.z == h) atomicMin(minid + L, lo);
-  for (int a = lo; a < e && adj[a] == y; ++a) out[a] = -2 - L;
+  return (lo < e && adj[lo] == y) ? lo : -1;
+}
+
+// Per vertex y of a non-largest BCC L with head h: where the arcs h->y start
+// in h's row and how many copies there are (mpos, mcnt; -1 / 0 if h and y
+// are not adjacent), and minid[L] when h is the smallest vertex of the BCC.
+__global__ void k_mirror_find(const int* __restrict__ off, const int* __restrict__ adj, int n,
+                              const int4* __restrict__ vlh, const int* __restrict__ scal, int* __restrict__ minid,
+                              int* __restrict__ mpos, int* __restrict__ mcnt) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= n) return;
+  const int4 r = vlh[y];  // (l, head(l), smallest vertex of the BCC, exact-row flag)
+  int a = -1, k = 0;
+  if (r.y >= 0 && r.x != scal[S_LBIG]) {
+    a = row_lower(off, adj, r.y, y);
+    if (a >= 0) {
+      if (r.z == r.y) atomicMin(minid + r.x, a);
+      const int e = off[r.y + 1];
+      do ++k;
+      while (a + k < e && adj[a + k] == y);
+    }
+  }
+  mpos[y] = a;
+  mcnt[y] = k;
+}
+
+// canon[L] for every BCC label, graph-local for batches.
+__global__ void k_canon_first(const int* __restrict__ off, const int* __restrict__ adj, int n,
+                              const int4* __restrict__ rec, const int* __restrict__ lab,
+                              const int4* __restrict__ vlh, const uint8_t* __restrict__ heads,
+                              const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
+                              const int* __restrict__ minid, const int* __restrict__ vbegin, int G,
+                              int* __restrict__ canon) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int big = scal[S_LBIG];
+  bool label = v < n && is_bcc_label(rec, lab, v);
+  int c = -1;
+  bool scan = false;
+  int4 r = make_int4(0, -1, 0, 0);
+  if (label) {
+    r = vlh[v];  // v is a label, so r = (v, head(v), m(v), exact)
+    if (v == big && scal[S_CANON_BIG] >= 0) {
+      canon[v] = scal[S_CANON_BIG];
+      label = false;
+    } else if (r.z == r.y) {
+      c = minid[v];
+    } else if (!heads[v]) {
+      int a = off[v];
+      const int e = off[v + 1];
+      while (a < e && adj[a] == v) ++a;
+      c = a;
+    } else {
+      scan = true;
+    }
+  }
+  // rows of heads: the wave scans each one 64 arcs at a time
+  uint64_t todo = __ballot(scan);
+  while (todo) {
+    const int j = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int x = __shfl(v, j, WAVE), hx = __shfl(r.y, j, WAVE);
+    const int b = off[x], e = off[x + 1];
+    int found = -1;
+    for (int base = b; base < e && found < 0; base += WAVE) {
+      const int a = base + lane_id();
+      bool in = false;
+      if (a < e) {
+        const int y = adj[a];
+        if (y != x) {
+          const int ly = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? big : lab[y];
+          in = ly == x || hx == y;
+        }
+      }
+      const uint64_t hit = __ballot(in);
+      if (hit) found = base + __builtin_ctzll(hit);
+    }
+    if (lane_id() == j) c = found;
+  }
+  if (label) {
+    if (G > 1 && c >= 0) c -= off[vbegin[graph_of(vbegin, G, v)]];
+    canon[v] = c;
+  }
+}
+
+// Records for the final pass: z becomes canon(l) (canon is -1 where l labels
+// no BCC).
+__global__ void k_vertex_canon(const int* __restrict__ canon, int n, int4* __restrict__ vlh) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  vlh[v].z = canon[vlh[v].x];
+}
+
+// One pass: every arc gets its final label; rows marked exact gather per arc.
+__global__ void k_bcc_final(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                            const int* __restrict__ tile_row, int tw, const int4* __restrict__ vlh,
+                            const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
+                            int* __restrict__ out) {
+  const int big = scal[S_LBIG];
+  const int4 rbig = vlh[big];
+  arc_windows2(
+      off, adj, n, A, tile_row, tw,
+      [&](int x, int, bool ok) { return ok ? vlh[x] : make_int4(0, -1, -1, 0); },
+      [&](int64_t a, int x, bool ok, int y, int4 rx) {
+        if (!ok) return;
+        if (y == x) {
+          __builtin_nontemporal_store(-1, out + a);
+          return;
+        }
+        // rx = (l[x], head(l[x]), canon(l[x]), exact-row flag)
+        int c = rx.z;
+        if (rx.w) {
+          const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
+          if (ry.x != rx.x && rx.y != y) c = ry.z;
+        }
+        __builtin_nontemporal_store(c, out + a);
+      });
+}
+
+// The arcs h->y of the mirror search get y's BCC.
+__global__ void k_mirror_write(int n, const int4* __restrict__ vlh, const int* __restrict__ mpos,
+                               const int* __restrict__ mcnt, int* __restrict__ out) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= n) return;
+  const int a0 = mpos[y];
+  if (a0 < 0) return;
+  const int c = vlh[y].z, k = mcnt[y];
+  for (int a = a0; a < a0 + k; ++a) out[a] = c;
 }
 
 // canon[L] = smallest arc of BCC L, made graph-local for batches (the
@@ -1715,13 +1835,13 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     int* order = pos;     // preorder -> vertex; the tour positions are dead now
     int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
     fill_i32(c, cover, 0, (int64_t)n + 2);
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, first, n, w1, w2);
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, first, n, tune.tag_samples, w1, w2);
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, order, scal + S_STATUS);
     rmq_tables();
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_CERTIFY,
            cover, scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
-    LAUNCH(c, k_dirty_deg, gn, BLOCK, off, order, cover, n, foff, frank);
+    LAUNCH(c, k_dirty_deg, gn, BLOCK, off, order, cover, n, tune.tag_samples, foff, frank);
     scan_inplace(c, foff, n, nullptr, tmp, foff + n);
     scan_inplace(c, frank, n, nullptr, tmp, frows);
     LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, order, frow, fstart);
@@ -1766,16 +1886,23 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_big_canon, 1, BLOCK, off, adj, rec, lab, head, heads, vbegin, G, scal);
   int4* vlh = (int4*)(w + L.ol);  // the list-ranking array (16n + 8 bytes) is dead by now
   LAUNCH(c, k_vertex_lh, gn, BLOCK, lab, head, heads, rec, scal, n, vlh);
-  if (sorted_rows)
-    LAUNCH(c, k_bcc_label<LABEL_MIRROR>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
-           head, scal, minid, out_label);
-  else if (!tune.sampled_tags)
+  if (sorted_rows) {
+    // canonical labels first, then every arc once with its final label
+    int *mpos = I(L.w1), *mcnt = I(L.w2);  // tags are done
+    LAUNCH(c, k_mirror_find, gn, BLOCK, off, adj, n, vlh, scal, minid, mpos, mcnt);
+    fill_i32(c, canon, -1, n);
+    LAUNCH(c, k_canon_first, gn, BLOCK, off, adj, n, rec, lab, vlh, heads, bigbits, scal, minid, vbegin, G, canon);
+    LAUNCH(c, k_vertex_canon, gn, BLOCK, canon, n, vlh);
+    LAUNCH(c, k_bcc_final, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
+    LAUNCH(c, k_mirror_write, gn, BLOCK, n, vlh, mpos, mcnt, out_label);
+    return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+  }
+  if (!tune.sampled_tags)
     LAUNCH(c, k_bcc_label<LABEL_DBITS>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
            head, scal, minid, out_label);
   else
     LAUNCH(c, k_bcc_label<LABEL_BITMAP>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, heads, bigbits, dbits,
            head, scal, minid, out_label);
-  if (sorted_rows) LAUNCH(c, k_bcc_mirror, gn, BLOCK, off, adj, n, vlh, scal, minid, out_label);
   LAUNCH(c, k_bcc_canon, gn, BLOCK, rec, lab, minid, n, vbegin, G, off, scal, canon);
   if (A > 0) {
     if (((uintptr_t)out_label & 15) == 0) {

@@ -30,7 +30,8 @@ TILE = (2, 3, 4, 5)
 UF = (0, 1)  # First-CC union-find: 0 = min-id hooking, 1 = hashed-priority hooking
 LDD = (0, 1, 2)  # First-CC low-diameter decomposition first: 0 = off, k = beta 2^-k
 TAGS = (0, 1)  # 0 = exact tag sweep over every arc, 1 = sampled-tag certification
-START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0}
+TAG_SAMPLES = (4, 2, 3, 6)  # sampled neighbours per vertex when certifying
+START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4}
 
 
 def skew_class(degrees: np.ndarray) -> str:
@@ -54,7 +55,7 @@ def cache_key(arch: str, n: int, arcs: int, graphs: int, skew: str) -> str:
 def encode(cfg: Dict[str, int]) -> int:
     return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"],
                         cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)),
-                        sampled_tags=bool(cfg.get("tags", 0)))
+                        sampled_tags=bool(cfg.get("tags", 0)), tag_samples=int(cfg.get("ts", 4)))
 
 
 class Tuner:
@@ -100,7 +101,9 @@ class Tuner:
         for _ in range(2):
             changed = False
             for knob, values in (("tags", TAGS), ("uf", UF), ("ldd", LDD), ("sample", SAMPLE), ("tile", TILE),
-                                 ("ruler", RULER)):
+                                 ("ruler", RULER), ("ts", TAG_SAMPLES)):
+                if knob == "ts" and not cfg["tags"]:
+                    continue
                 best_v, best_t = cfg[knob], cost(cfg)
                 for v in values:
                     c = dict(cfg, **{knob: v})
