@@ -5,28 +5,33 @@
 //
 //   First-CC   union-find over all arcs, the hooking edge of every hooked root
 //              kept as a spanning-forest edge; a few sampling rounds first,
-//              then the full sweep skips rows already in the largest set.
-//   Rooting    tree arcs grouped by source (count, scan, scatter) with twin
-//              indices; Euler circuit by "arc u->v continues with the arc
-//              after v->u in v's row" (paper: "Euler Tour Technique");
-//              all trees' tours plus one entry node per tree root are chained
-//              into ONE list in root order, so list ranking yields global
-//              positions directly; ruling-set list ranking (rulers at every
-//              K-th node index, each walks to the next ruler) and pointer
-//              jumping over the rulers.
+//              then the full sweep skips rows already in the largest set
+//              (optionally after a low-diameter decomposition, whose BFS
+//              edges are forest edges too).
+//   Rooting    forest edges numbered densely, arcs 2e and 2e + 1 (twins by
+//              a ^ 1); each vertex's out-arcs in a linked list built by
+//              atomic exchange; Euler circuit by "arc u->v continues with the
+//              arc after v->u in v's cyclic list" (paper: "Euler Tour
+//              Technique"); all trees' tours plus one entry node per root of
+//              a tree with edges are chained into ONE list, so list ranking
+//              yields global positions directly; ruling-set list ranking
+//              (rulers at every K-th node index, each walks to the next ruler)
+//              and pointer jumping over the rulers.  Trees are rooted at hubs.
 //   Tagging    down arcs (rank(u->v) < rank(v->u)) give parent and preorder
 //              number first[v] = #entries before (scan of entry flags);
 //              last[v] = first[v] + |T_v| - 1; w1/w2 = min/max of first over
-//              v and its neighbours (one arc-balanced sweep); low/high by
-//              range min/max over the preorder interval (blocked sparse
-//              table); fence bit per vertex.
+//              v and its neighbours (one arc-balanced sweep, or sampled
+//              neighbours with exact sweeps only under undecided vertices);
+//              low/high by range min/max over the preorder interval (blocked
+//              sparse table); fence bit per vertex.
 //   Last-CC    union-find on the skeleton: plain tree edges linked per
 //              vertex, non-tree arcs kept iff neither endpoint is an ancestor
 //              of the other (cross edges); fence and back edges skipped.
 //   Read-out   head(l[u]) = p(u) where l[u] != l[p(u)]; articulation points;
 //              canonical label per BCC = its smallest arc (found in the row
-//              of the BCC's smallest vertex); arc label = canonical label of
-//              the deeper endpoint's vertex label.
+//              of the BCC's smallest vertex); arc x->y lies in l[x] unless x
+//              heads l[y]; with sorted rows those arcs are found from y's side
+//              and every arc is written once with its final label.
 //
 // Every kernel is enqueued on the caller's stream; data-dependent sizes
 // (number of trees, tree arcs, rulers) stay in device memory and grids are
@@ -639,95 +644,92 @@ __global__ void k_ldd_huge(const int* __restrict__ off, const int* __restrict__ 
 }
 
 // ------------------------------------------------------------ Rooting
-// Tree degree counts and the slot each forest edge takes in both rows.
-// A vertex of graph degree >= HUB_DEG may get a huge tree degree, and one
-// counter would serialise every edge's atomic on one address: such hubs get
-// HUB_SHARDS counters, the shard picked from the edge's index h; a hub slot
-// is stored as -1 - (position within the shard), so the fill knows hub-ness
-// from the sign and the shard from h.  k_hub_finish turns shard counts into
-// in-row prefixes.
+// The forest edges (one record per hooked vertex) are numbered densely, edge
+// e = (eu[e], ev[e]); its two arcs are list nodes 2e (eu -> ev) and 2e + 1
+// (ev -> eu), so an arc's twin is a ^ 1.  Each vertex keeps its out-arcs in a
+// linked list built by atomic exchange on a list head (nxt[a] = previous
+// head); that list order is the cyclic order the Euler tour uses.  A vertex
+// of graph degree >= HUB_DEG may get a huge tree degree, and one head would
+// serialise every exchange on one address: such hubs get HUB_SHARDS lists,
+// picked by edge number, chained shard after shard.
 __device__ __forceinline__ bool is_hub(const int* __restrict__ off, int x) { return off[x + 1] - off[x] >= HUB_DEG; }
-
-__device__ __forceinline__ int tree_slot(const int* __restrict__ off, const int* __restrict__ hubidx, int* toff,
-                                         int* shard, int x, int h) {
-  if (is_hub(off, x)) return -1 - atomicAdd(shard + (size_t)hubidx[x] * HUB_SHARDS + (h & (HUB_SHARDS - 1)), 1);
-  return atomicAdd(toff + x, 1);
-}
-
-__device__ __forceinline__ int tree_pos(const int* __restrict__ toff, const int* __restrict__ hubidx,
-                                        const int* __restrict__ shard, int x, int h, int slot) {
-  if (slot >= 0) return toff[x] + slot;
-  return toff[x] + shard[(size_t)hubidx[x] * HUB_SHARDS + (h & (HUB_SHARDS - 1))] + (-1 - slot);
-}
 
 __global__ void k_hub_flags(const int* __restrict__ off, int n, int* __restrict__ hubidx) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) hubidx[v] = is_hub(off, v) ? 1 : 0;
 }
 
-__global__ void k_tree_count(const int* __restrict__ off, const int* __restrict__ hubidx, const int* __restrict__ hu,
-                             const int* __restrict__ hv, int n, int* toff, int* shard, int* __restrict__ su,
-                             int* __restrict__ sv) {
+__global__ void k_edge_flags(const int* __restrict__ hu, int n, int* __restrict__ eid) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= n) return;
-  int u = hu[h];
-  if (u < 0) return;
-  int v = hv[h];
-  su[h] = tree_slot(off, hubidx, toff, shard, u, h);
-  sv[h] = tree_slot(off, hubidx, toff, shard, v, h);
+  if (h < n) eid[h] = hu[h] >= 0 ? 1 : 0;
 }
 
-// Per hub: total tree degree into toff[x], shard counts -> exclusive prefixes.
-__global__ void k_hub_finish(const int* __restrict__ off, const int* __restrict__ hubidx, int n, int* toff,
-                             int* shard) {
+__global__ void k_edge_compact(const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ eid,
+                               int n, int* __restrict__ eu, int* __restrict__ ev) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n || hu[h] < 0) return;
+  const int e = eid[h];
+  eu[e] = hu[h];
+  ev[e] = hv[h];
+}
+
+__device__ __forceinline__ int arc_src(const int* __restrict__ eu, const int* __restrict__ ev, int a) {
+  return (a & 1) ? ev[a >> 1] : eu[a >> 1];
+}
+
+__global__ void k_tree_link(const int* __restrict__ off, const int* __restrict__ hubidx, const int* __restrict__ eid,
+                            int n, const int* __restrict__ eu, const int* __restrict__ ev, int* headp, int* shard,
+                            int* __restrict__ nxt) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= 2 * eid[n]) return;
+  const int s = arc_src(eu, ev, a);
+  int* slot = is_hub(off, s) ? shard + (size_t)hubidx[s] * HUB_SHARDS + ((a >> 1) & (HUB_SHARDS - 1)) : headp + s;
+  nxt[a] = atomicExch(slot, a);
+}
+
+// Per hub: its first arc (head of the first non-empty shard) into headp, and
+// every shard slot rewritten to the head of the next non-empty shard in
+// cyclic order, stored as -2 - head when that step wraps around.
+__global__ void k_hub_lists(const int* __restrict__ off, const int* __restrict__ hubidx, int n, int* headp,
+                            int* shard) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || !is_hub(off, v)) return;
   int* sh = shard + (size_t)hubidx[v] * HUB_SHARDS;
-  int run = 0;
-  for (int s = 0; s < HUB_SHARDS; ++s) {
-    const int c = sh[s];
-    sh[s] = run;
-    run += c;
+  int head[HUB_SHARDS];
+  int firsts = -1;
+  for (int k = 0; k < HUB_SHARDS; ++k) {
+    head[k] = sh[k];
+    if (firsts < 0 && head[k] >= 0) firsts = k;
   }
-  toff[v] = run;
-}
-
-__global__ void k_tree_fill(const int* __restrict__ hubidx, const int* __restrict__ shard,
-                            const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ su,
-                            const int* __restrict__ sv, const int* __restrict__ toff, int n, int* __restrict__ tadj,
-                            int* __restrict__ twin) {
-  int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= n) return;
-  int u = hu[h];
-  if (u < 0) return;
-  int v = hv[h];
-  int pu = tree_pos(toff, hubidx, shard, u, h, su[h]), pv = tree_pos(toff, hubidx, shard, v, h, sv[h]);
-  tadj[pu] = v;
-  tadj[pv] = u;
-  twin[pu] = pv;
-  twin[pv] = pu;
+  headp[v] = firsts >= 0 ? head[firsts] : -1;
+  if (firsts < 0) return;
+  for (int k = 0; k < HUB_SHARDS; ++k) {
+    int j = k + 1;
+    while (j < HUB_SHARDS && head[j] < 0) ++j;
+    sh[k] = j < HUB_SHARDS ? head[j] : -2 - head[firsts];
+  }
 }
 
 // Roots of trees with at least one edge get a list entry node; a one-vertex
 // tree (an isolated vertex, or one with only self-loops) stays out of the
 // Euler tour and takes a preorder number after all others.
-__global__ void k_root_flags(const int* __restrict__ cc, const int* __restrict__ toff, int n,
+__global__ void k_root_flags(const int* __restrict__ cc, const int* __restrict__ headp, int n,
                              int* __restrict__ rootidx, int* __restrict__ lone) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const bool root = cc[v] == v;
-  const bool alone = root && toff[v + 1] == toff[v];
+  const bool alone = root && headp[v] < 0;
   rootidx[v] = root && !alone ? 1 : 0;
   lone[v] = alone ? 1 : 0;
 }
 
-__global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ toff,
+__global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ headp,
                             const int* __restrict__ rootidx, const int* __restrict__ rdeg,
                             const int* __restrict__ rsel, const int* __restrict__ scal, int n,
                             int* __restrict__ roots) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  if (cc[v] != v || toff[v + 1] == toff[v]) return;
+  if (cc[v] != v || headp[v] < 0) return;
   int r = v;
   if (v == scal[S_BIG_ROOT]) {
     if (scal[S_GIANT_HUB] >= 0) r = scal[S_GIANT_HUB];
@@ -750,41 +752,62 @@ __global__ void k_lone_tags(const int* __restrict__ lone, int n, int* __restrict
 
 // List nodes: [0, C) one entry node per root of a tree with edges (root
 // order), then C + [0, 2T) the tree arcs.  The chain runs entry_0, tour_0,
-// entry_1, ...
-__global__ void k_euler_next(const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
-                             const int* __restrict__ cc, const int* __restrict__ rootidx,
-                             const int* __restrict__ roots, int n, int* __restrict__ next) {
-  const int C = rootidx[n], T2 = toff[n], NL = C + T2;
+// entry_1, ...  The successor of arc u->v is the arc after v->u in v's cyclic
+// out-list; when that step wraps around at the tour's root, the tour of this
+// tree is complete and the chain continues with the next entry node.
+__device__ __forceinline__ int node_count(const int* __restrict__ rootidx, const int* __restrict__ eid, int n) {
+  return rootidx[n] + 2 * eid[n];
+}
+
+__global__ void k_euler_next(const int* __restrict__ off, const int* __restrict__ hubidx,
+                             const int* __restrict__ eid, const int* __restrict__ eu, const int* __restrict__ ev,
+                             const int* __restrict__ headp, const int* __restrict__ shard,
+                             const int* __restrict__ nxt, const int* __restrict__ cc,
+                             const int* __restrict__ rootidx, const int* __restrict__ roots, int n,
+                             int* __restrict__ next) {
+  const int C = rootidx[n], NL = node_count(rootidx, eid, n);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NL) return;
   if (i < C) {
-    int r = roots[i];
-    next[i] = toff[r + 1] > toff[r] ? C + toff[r] : (i + 1 < C ? i + 1 : -1);
+    next[i] = C + headp[roots[i]];
     return;
   }
-  const int a = i - C;
-  const int v = tadj[a];
-  int nx = twin[a] + 1;
-  if (nx == toff[v + 1]) {
-    nx = toff[v];
+  const int t = (i - C) ^ 1;  // v -> u, the twin of this arc u -> v
+  const int nx = nxt[t];
+  if (nx >= 0) {
+    next[i] = C + nx;
+    return;
+  }
+  const int v = arc_src(eu, ev, t);
+  int head;
+  bool wrap;
+  if (is_hub(off, v)) {
+    const int q = shard[(size_t)hubidx[v] * HUB_SHARDS + ((t >> 1) & (HUB_SHARDS - 1))];
+    wrap = q < 0;
+    head = wrap ? -2 - q : q;
+  } else {
+    wrap = true;
+    head = headp[v];
+  }
+  if (wrap) {
     const int k = rootidx[cc[v]];
     if (roots[k] == v) {  // closes the tour of v's tree: continue with the next tree
       next[i] = k + 1 < C ? k + 1 : -1;
       return;
     }
   }
-  next[i] = C + nx;
+  next[i] = C + head;
 }
 
-__global__ void k_node_count(const int* __restrict__ rootidx, const int* __restrict__ toff, int n, int* out) {
-  *out = rootidx[n] + toff[n];
+__global__ void k_node_count(const int* __restrict__ rootidx, const int* __restrict__ eid, int n, int* out) {
+  *out = node_count(rootidx, eid, n);
 }
 
 // Each ruler (node index multiple of K) walks to the next ruler.
 __global__ void k_lr_walk(const int* __restrict__ next, const int* __restrict__ rootidx,
-                          const int* __restrict__ toff, int n, int shift, int2* __restrict__ ol,
+                          const int* __restrict__ eid, int n, int shift, int2* __restrict__ ol,
                           int* __restrict__ rnext, int* __restrict__ rlen) {
-  const int NL = rootidx[n] + toff[n];
+  const int NL = node_count(rootidx, eid, n);
   const int R = (NL + (1 << shift) - 1) >> shift;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
@@ -805,10 +828,10 @@ __global__ void k_lr_walk(const int* __restrict__ next, const int* __restrict__ 
 }
 
 // One pointer-jumping round over rulers: suffix sums of segment lengths.
-__global__ void k_lr_jump(const int* __restrict__ rootidx, const int* __restrict__ toff, int n, int shift,
+__global__ void k_lr_jump(const int* __restrict__ rootidx, const int* __restrict__ eid, int n, int shift,
                           const int* __restrict__ vin, const int* __restrict__ nin, int* __restrict__ vout,
                           int* __restrict__ nout) {
-  const int NL = rootidx[n] + toff[n];
+  const int NL = node_count(rootidx, eid, n);
   const int R = (NL + (1 << shift) - 1) >> shift;
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
@@ -823,23 +846,29 @@ __global__ void k_lr_jump(const int* __restrict__ rootidx, const int* __restrict
 }
 
 // Global position of every node, then its entry flag scattered by position.
-__global__ void k_lr_pos(const int* __restrict__ rootidx, const int* __restrict__ toff, const int* __restrict__ twin,
-                         int n, const int2* __restrict__ ol, const int* __restrict__ suf, int* __restrict__ pos) {
-  const int NL = rootidx[n] + toff[n];
+__global__ void k_lr_pos(const int* __restrict__ rootidx, const int* __restrict__ eid, int n, int shift,
+                         const int2* __restrict__ ol, const int* __restrict__ suf, int* __restrict__ pos,
+                         int* status) {
+  const int NL = node_count(rootidx, eid, n);
+  const int R = (NL + (1 << shift) - 1) >> shift;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NL) return;
   int2 o = ol[i];
+  if (o.x < 0 || o.x >= R) {  // a node no ruler walked over: the tour is broken
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    pos[i] = -1;
+    return;
+  }
   pos[i] = NL - suf[o.x] + o.y;
 }
 
-__global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __restrict__ toff,
-                              const int* __restrict__ twin, int n, const int* __restrict__ pos,
-                              int* __restrict__ eflag, int* status) {
-  const int C = rootidx[n], NL = C + toff[n];
+__global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __restrict__ eid, int n,
+                              const int* __restrict__ pos, int* __restrict__ eflag, int* status) {
+  const int C = rootidx[n], NL = node_count(rootidx, eid, n);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NL) return;
   int f = 1;
-  if (i >= C) f = pos[i] < pos[C + twin[i - C]] ? 1 : 0;
+  if (i >= C) f = pos[i] < pos[C + ((i - C) ^ 1)] ? 1 : 0;  // the down arc comes first
   const int p = pos[i];
   if (p < 0 || p >= NL) {
     atomicExch(status, (int)FASTBCC_ERR_HIP);
@@ -851,25 +880,34 @@ __global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __rest
 // first/last/parent from the ranked tour: one 16-byte record per vertex plus
 // a compact first[] (the array every arc sweep gathers from).
 __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ roots,
-                       const int* __restrict__ toff, const int* __restrict__ tadj, const int* __restrict__ twin,
+                       const int* __restrict__ eid, const int* __restrict__ eu, const int* __restrict__ ev,
                        const int* __restrict__ lone, int n, const int* __restrict__ pos,
                        const int* __restrict__ escan, int* __restrict__ first, int4* __restrict__ rec, int* status) {
-  const int C = rootidx[n], NL = C + toff[n];
+  const int C = rootidx[n], NL = node_count(rootidx, eid, n);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NL) return;
   int v, f, l, p;
   if (i < C) {
+    const int pi = pos[i], pn = (i + 1 < C) ? pos[i + 1] : 0;
+    if (pi < 0 || pi >= NL || pn < 0 || pn >= NL) {
+      atomicExch(status, (int)FASTBCC_ERR_HIP);
+      return;
+    }
     v = roots[i];
-    f = escan[pos[i]];
-    int nf = (i + 1 < C) ? escan[pos[i + 1]] : n - lone[n];
+    f = escan[pi];
+    int nf = (i + 1 < C) ? escan[pn] : n - lone[n];
     l = nf - 1;
     p = -1;
   } else {
-    const int a = i - C, ta = twin[a], tw = C + ta;
+    const int a = i - C, tw = C + (a ^ 1);
     const int pi = pos[i], pt = pos[tw];
+    if (pi < 0 || pi >= NL || pt < 0 || pt >= NL) {
+      atomicExch(status, (int)FASTBCC_ERR_HIP);
+      return;
+    }
     if (pi > pt) return;  // up arc
-    v = tadj[a];
-    p = tadj[ta];
+    v = arc_src(eu, ev, a ^ 1);  // the arc runs p -> v
+    p = arc_src(eu, ev, a);
     f = escan[pi];
     l = f + (pt - pi - 1) / 2;
   }
@@ -1757,19 +1795,21 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_compress, gn, BLOCK, cc, n);
 
   // ---- Rooting
-  int *toff = I(L.toff), *su = I(L.su), *sv = I(L.sv), *tadj = I(L.tadj), *twin = I(L.twin);
+  int *eid = I(L.toff), *eu = I(L.su), *ev = I(L.sv), *headp = I(L.tadj), *nxt = I(L.twin);
   int *rootidx = I(L.rootidx), *roots = I(L.roots), *next = I(L.next), *tmp = I(L.scan_tmp);
   int *hubidx = I(L.hubidx), *shard = I(L.shard);
-  fill_i32(c, toff, 0, n + 1);
-  fill_i32(c, shard, 0, L.hubs * HUB_SHARDS);
+  LAUNCH(c, k_edge_flags, gn, BLOCK, hu, n, eid);
+  scan_inplace(c, eid, n, nullptr, tmp, eid + n);
+  LAUNCH(c, k_edge_compact, gn, BLOCK, hu, hv, eid, n, eu, ev);
+  fill_i32(c, headp, -1, n);
+  fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
   LAUNCH(c, k_hub_flags, gn, BLOCK, off, n, hubidx);
   scan_inplace(c, hubidx, n, nullptr, tmp, hubidx + n);
-  LAUNCH(c, k_tree_count, gn, BLOCK, off, hubidx, hu, hv, n, toff, shard, su, sv);
-  LAUNCH(c, k_hub_finish, gn, BLOCK, off, hubidx, n, toff, shard);
-  scan_inplace(c, toff, n, nullptr, tmp, toff + n);
-  LAUNCH(c, k_tree_fill, gn, BLOCK, hubidx, shard, hu, hv, su, sv, toff, n, tadj, twin);
-  int* lone = hubidx;  // the hub numbering is dead after the tree fill
-  LAUNCH(c, k_root_flags, gn, BLOCK, cc, toff, n, rootidx, lone);
+  const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
+  LAUNCH(c, k_tree_link, grid_for(arcs_max), BLOCK, off, hubidx, eid, n, eu, ev, headp, shard, nxt);
+  LAUNCH(c, k_hub_lists, gn, BLOCK, off, hubidx, n, headp, shard);
+  int* lone = I(L.frank);  // the frontier ranks are free from here until Tagging's own frontier
+  LAUNCH(c, k_root_flags, gn, BLOCK, cc, headp, n, rootidx, lone);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   scan_inplace(c, lone, n, nullptr, tmp, lone + n);
   int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
@@ -1779,39 +1819,39 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_root_degree, gn, BLOCK, off, cc, n, scal, rdeg);
     LAUNCH(c, k_root_select, gn, BLOCK, off, cc, n, rdeg, rsel);
   }
-  LAUNCH(c, k_root_list, gn, BLOCK, cc, toff, rootidx, rdeg, rsel, scal, n, roots);
+  LAUNCH(c, k_root_list, gn, BLOCK, cc, headp, rootidx, rdeg, rsel, scal, n, roots);
   const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
   const unsigned gnode = grid_for(nodes_max);
-  LAUNCH(c, k_euler_next, gnode, BLOCK, toff, tadj, twin, cc, rootidx, roots, n, next);
+  LAUNCH(c, k_euler_next, gnode, BLOCK, off, hubidx, eid, eu, ev, headp, shard, nxt, cc, rootidx, roots, n, next);
 
   // list ranking: ruling set + pointer jumping over rulers
   const int sh = tune.ruler_shift;
   const int64_t rmax = cdiv(nodes_max, int64_t(1) << sh);
   int2* ol = (int2*)(w + L.ol);
   int *rlen = I(L.rlen), *rnext = I(L.rnext);
-  LAUNCH(c, k_lr_walk, grid_for(rmax), BLOCK, next, rootidx, toff, n, sh, ol, rnext, rlen);
+  LAUNCH(c, k_lr_walk, grid_for(rmax), BLOCK, next, rootidx, eid, n, sh, ol, rnext, rlen);
   const int* vin = rlen;
   const int* nin = rnext;
   int* bufv[2] = {I(L.rval0), I(L.rval1)};
   int* bufn[2] = {I(L.rnx0), I(L.rnx1)};
   const int rounds = ilog2_floor(rmax) + 1;  // 2^rounds > ruler count
   for (int k = 0; k < rounds; ++k) {
-    LAUNCH(c, k_lr_jump, grid_for(rmax), BLOCK, rootidx, toff, n, sh, vin, nin, bufv[k & 1], bufn[k & 1]);
+    LAUNCH(c, k_lr_jump, grid_for(rmax), BLOCK, rootidx, eid, n, sh, vin, nin, bufv[k & 1], bufn[k & 1]);
     vin = bufv[k & 1];
     nin = bufn[k & 1];
   }
   int* pos = I(L.pos);
   int* eflag = I(L.eflag);
-  LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, toff, twin, n, ol, vin, pos);
-  LAUNCH(c, k_enter_flags, gnode, BLOCK, rootidx, toff, twin, n, pos, eflag, scal + S_STATUS);
+  LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, eid, n, sh, ol, vin, pos, scal + S_STATUS);
+  LAUNCH(c, k_enter_flags, gnode, BLOCK, rootidx, eid, n, pos, eflag, scal + S_STATUS);
   int* nl_dev = scal + S_NODES;  // number of list nodes, for the scan of entry flags
-  LAUNCH(c, k_node_count, 1, 1, rootidx, toff, n, nl_dev);
+  LAUNCH(c, k_node_count, 1, 1, rootidx, eid, n, nl_dev);
   scan_inplace(c, eflag, nodes_max, nl_dev, tmp, scal + S_ENTRIES);
 
   // ---- Tagging
   int *first = I(L.first), *w1 = I(L.w1), *w2 = I(L.w2);
   int4* rec = (int4*)(w + L.rec);
-  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, toff, tadj, twin, lone, n, pos, eflag, first, rec, scal + S_STATUS);
+  LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, eid, eu, ev, lone, n, pos, eflag, first, rec, scal + S_STATUS);
   LAUNCH(c, k_lone_tags, gn, BLOCK, lone, n, first, rec);
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
   int *W1 = I(L.W1), *W2 = I(L.W2), *pre1 = I(L.pre1), *suf1 = I(L.suf1), *pre2 = I(L.pre2), *suf2 = I(L.suf2);
