@@ -52,9 +52,10 @@ def alg_bytes(kernel, n, A):
         # + w1/w2 read-modify-write per row + one descendant bit per arc
         "k_tag_sweep": 4 * (n + 1) + 8 * A + 24 * n + A // 8,
         # offsets + adjacency + label write per arc + the 16-byte record of the
-        # row vertex (sorted-rows read-out: the few exact rows' gathers are
-        # left out, so this is a lower bound)
+        # row vertex (the few exact rows' gathers are left out: a lower bound)
         "k_bcc_label": 4 * (n + 1) + 8 * A + 16 * n,
+        # one-pass final labels (sorted rows): the same stream and records
+        "k_bcc_final": 4 * (n + 1) + 8 * A + 16 * n,
         # label read + label write per arc (canonical-label lookups hit the few hot labels)
         "k_bcc_remap4": 8 * A,
     }
