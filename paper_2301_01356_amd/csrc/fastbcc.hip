@@ -90,8 +90,6 @@ enum Scalar : int {
   S_NODES = 8,      // list nodes of the Euler tour
   S_ENTRIES = 9,    // entry flags over the tour
   S_LDD_HUGE = 10,  // two slots: long rows listed by a decomposition round
-  S_GIANT_HUB = 12, // highest-degree sampled vertex of the largest component (-1: none)
-  S_BIG_ROOT = 13,  // final First-CC root of that component
   S_COUNT = 64,
 };
 
@@ -197,13 +195,16 @@ struct Tune {
   int ldd = 0;           // First-CC starts with a low-diameter decomposition, beta = 2^-ldd (0 = off)
   bool sampled_tags = false;  // fences certified from sampled tags, exact tags only where needed
   int tag_samples = 4;        // sampled neighbours per vertex in that mode
+  bool first_round_free = false;  // First-CC's first sampling round links without atomics
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
   const uint32_t known = FASTBCC_FLAG_VALIDATE | FASTBCC_FLAG_SORTED_ROWS | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
-                         FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT);
+                         FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
+                         FASTBCC_TUNE_FREE_FIRST_ROUND;
+  t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
   static const int kSamples[4] = {4, 2, 3, 6};
   t.tag_samples = kSamples[(flags >> FASTBCC_TUNE_TAG_SAMPLES_SHIFT) & 0x3];
@@ -291,78 +292,33 @@ __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __re
   }
 }
 
-// Tree roots: the largest component is rooted at its highest-degree sampled
-// vertex, every other component at a vertex of largest degree.  Any root is
-// valid; a hub almost surely lies in the component's largest BCC, and a root
-// inside the largest BCC keeps the subtrees below fence vertices small (what
-// the sampled-tag certification needs).
-__global__ void __launch_bounds__(1024) k_giant_hub(const int* __restrict__ off, const int* __restrict__ cc, int n,
-                                                    int* scal) {
-  __shared__ int bd[1024 / WAVE], bv[1024 / WAVE];
-  const int big = cc[scal[S_BIG_CC]];  // the sampled root may have been hooked since
-  int best_d = -1, best_v = -1;
-  for (int k = 0; k < 8; ++k) {
-    const int64_t i = (int64_t)k * 1024 + threadIdx.x;
-    const int v = (int)((i * n) / 8192);
-    if (v < n && cc[v] == big) {
-      const int d = off[v + 1] - off[v];
-      if (d > best_d) {
-        best_d = d;
-        best_v = v;
-      }
-    }
-  }
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    const int d2 = __shfl_down(best_d, o, WAVE), v2 = __shfl_down(best_v, o, WAVE);
-    if (d2 > best_d) {
-      best_d = d2;
-      best_v = v2;
-    }
-  }
-  if (lane_id() == 0) {
-    bd[threadIdx.x / WAVE] = best_d;
-    bv[threadIdx.x / WAVE] = best_v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 1024 / WAVE; ++w)
-      if (bd[w] > best_d) {
-        best_d = bd[w];
-        best_v = bv[w];
-      }
-    scal[S_GIANT_HUB] = best_d > 0 ? best_v : -1;
-    scal[S_BIG_ROOT] = big;
-  }
+// Tree roots: every component with a sampled vertex is rooted at its
+// highest-degree sampled vertex, the others at their union-find root.  Any
+// root is valid; a hub almost surely lies in its component's largest BCC, and
+// a root inside the largest BCC keeps the subtrees below fence vertices small
+// (what the sampled-tag certification needs).  Only the samples touch the
+// per-component slots, so even the largest component sees few atomics.
+constexpr int ROOT_SAMPLES = 65536;
+
+__device__ __forceinline__ int root_sample(int i, int n) {
+  return (int)(((int64_t)i * n) / ROOT_SAMPLES);
 }
 
-// rdeg[c] = largest degree in component c (c = union-find root), except the
-// largest component; runs of equal c in a wave are reduced first.
-__global__ void k_root_degree(const int* __restrict__ off, const int* __restrict__ cc, int n,
-                              const int* __restrict__ scal, int* rdeg) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  const int big = scal[S_BIG_ROOT];
-  int c = -1, d = -1;
-  if (v < n) {
-    c = cc[v];
-    d = off[v + 1] - off[v];
-    if (c == big) c = -1;
-  }
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int c2 = __shfl_up(c, o, WAVE), d2 = __shfl_up(d, o, WAVE);
-    if (lane >= o && c2 == c && d2 > d) d = d2;
-  }
-  const int cn = __shfl_down(c, 1, WAVE);
-  if (c >= 0 && (lane == WAVE - 1 || cn != c)) atomicMax(rdeg + c, d);
+__global__ void k_root_degree(const int* __restrict__ off, const int* __restrict__ cc, int n, int* rdeg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ROOT_SAMPLES) return;
+  const int v = root_sample(i, n);
+  if (i > 0 && v == root_sample(i - 1, n)) return;  // n < ROOT_SAMPLES: each vertex once
+  atomicMax(rdeg + cc[v], off[v + 1] - off[v]);
 }
 
 __global__ void k_root_select(const int* __restrict__ off, const int* __restrict__ cc, int n,
                               const int* __restrict__ rdeg, int* __restrict__ rsel) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ROOT_SAMPLES) return;
+  const int v = root_sample(i, n);
   const int c = cc[v];
-  if (off[v + 1] - off[v] == rdeg[c]) rsel[c] = v;  // any vertex of largest degree
+  if (off[v + 1] - off[v] == rdeg[c]) rsel[c] = v;  // any sampled vertex of largest degree
 }
 
 // Most frequent value of p[] over a stratified sample of vertices (one block).
@@ -501,6 +457,26 @@ __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__
     int w = adj[b + sample_pos(v, r, e - b)];
     if (w != v) cc_link<PRIO>(cc, v, w, hu, hv);
   }
+}
+
+// First sampling round from all-singleton sets, without atomics: v points to
+// its sampled neighbour w when w ranks above it (smaller id, or higher hashed
+// priority), which keeps the pointers acyclic; the edge is recorded at v as
+// a hooked root's edge would be.  Only about half the samples link; the next
+// rounds link the rest with the full union-find.
+template <bool PRIO>
+__global__ void k_cc_first_round(const int* __restrict__ off, const int* __restrict__ adj, int n, int* cc,
+                                 int* __restrict__ hu, int* __restrict__ hv) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t b = off[v], e = off[v + 1];
+  if (e == b) return;
+  const int w = adj[b + sample_pos(v, 0, e - b)];
+  const bool up = PRIO ? uf_prio(w) > uf_prio(v) : w < v;
+  if (w == v || !up) return;
+  cc[v] = w;
+  hu[v] = v;
+  hv[v] = w;
 }
 
 // Full sweep over the frontier: rows whose set is the sampled largest one
@@ -730,13 +706,7 @@ __global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ 
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   if (cc[v] != v || headp[v] < 0) return;
-  int r = v;
-  if (v == scal[S_BIG_ROOT]) {
-    if (scal[S_GIANT_HUB] >= 0) r = scal[S_GIANT_HUB];
-  } else if (rdeg[v] >= 0) {
-    r = rsel[v];
-  }
-  roots[rootidx[v]] = r;
+  roots[rootidx[v]] = rdeg[v] >= 0 ? rsel[v] : v;
 }
 
 // first = last = n - S + (rank among one-vertex trees), S of them in all.
@@ -1783,8 +1753,14 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   }
   // compress after every round: the next round's finds then take one hop
   for (int r = 0; r < tune.sample_rounds; ++r) {
-    if (tune.cc_prio) LAUNCH(c, k_cc_sample<true>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
-    else LAUNCH(c, k_cc_sample<false>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+    if (r == 0 && tune.first_round_free && !tune.ldd) {
+      if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gn, BLOCK, off, adj, n, cc, hu, hv);
+      else LAUNCH(c, k_cc_first_round<false>, gn, BLOCK, off, adj, n, cc, hu, hv);
+    } else if (tune.cc_prio) {
+      LAUNCH(c, k_cc_sample<true>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+    } else {
+      LAUNCH(c, k_cc_sample<false>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+    }
     LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   }
   if (tune.sample_rounds == 0) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
@@ -1813,12 +1789,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   scan_inplace(c, lone, n, nullptr, tmp, lone + n);
   int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
-  if (n > 0) {
-    fill_i32(c, rdeg, -1, n);
-    LAUNCH(c, k_giant_hub, 1, 1024, off, cc, n, scal);
-    LAUNCH(c, k_root_degree, gn, BLOCK, off, cc, n, scal, rdeg);
-    LAUNCH(c, k_root_select, gn, BLOCK, off, cc, n, rdeg, rsel);
-  }
+  fill_i32(c, rdeg, -1, n);
+  LAUNCH(c, k_root_degree, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg);
+  LAUNCH(c, k_root_select, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg, rsel);
   LAUNCH(c, k_root_list, gn, BLOCK, cc, headp, rootidx, rdeg, rsel, scal, n, roots);
   const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
   const unsigned gnode = grid_for(nodes_max);

@@ -1,12 +1,13 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes six speed-only knobs in its flags word (they never change
+The C ABI exposes seven speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
 sampling off), the First-CC union-find variant (hook by id or by hashed
 priority), an optional low-diameter decomposition in front of First-CC's
 union-find (the paper's LDD-UF-JTB shape) with its beta, exact or
-sampled-and-certified tags, and the arc-tile size (64-arc windows per wave,
+sampled-and-certified tags (and how many samples), an atomic-free first
+sampling round, and the arc-tile size (64-arc windows per wave,
 i.e. work per wave).  The tuner times candidates by
 coordinate descent on the real input and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
@@ -31,7 +32,8 @@ UF = (0, 1)  # First-CC union-find: 0 = min-id hooking, 1 = hashed-priority hook
 LDD = (0, 1, 2)  # First-CC low-diameter decomposition first: 0 = off, k = beta 2^-k
 TAGS = (0, 1)  # 0 = exact tag sweep over every arc, 1 = sampled-tag certification
 TAG_SAMPLES = (4, 2, 3, 6)  # sampled neighbours per vertex when certifying
-START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4}
+FREE = (0, 1)  # First-CC's first sampling round without atomics
+START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0}
 
 
 def skew_class(degrees: np.ndarray) -> str:
@@ -55,7 +57,8 @@ def cache_key(arch: str, n: int, arcs: int, graphs: int, skew: str) -> str:
 def encode(cfg: Dict[str, int]) -> int:
     return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"],
                         cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)),
-                        sampled_tags=bool(cfg.get("tags", 0)), tag_samples=int(cfg.get("ts", 4)))
+                        sampled_tags=bool(cfg.get("tags", 0)), tag_samples=int(cfg.get("ts", 4)),
+                        free_first_round=bool(cfg.get("free", 0)))
 
 
 class Tuner:
@@ -100,8 +103,8 @@ class Tuner:
 
         for _ in range(2):
             changed = False
-            for knob, values in (("tags", TAGS), ("uf", UF), ("ldd", LDD), ("sample", SAMPLE), ("tile", TILE),
-                                 ("ruler", RULER), ("ts", TAG_SAMPLES)):
+            for knob, values in (("tags", TAGS), ("uf", UF), ("free", FREE), ("ldd", LDD), ("sample", SAMPLE),
+                                 ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES)):
                 if knob == "ts" and not cfg["tags"]:
                     continue
                 best_v, best_t = cfg[knob], cost(cfg)

@@ -154,6 +154,7 @@ def test_multigraph_self_loops_unsorted_rows():
     N.tune_flags(sampled_tags=True), N.tune_flags(sampled_tags=True, cc_priority=True, tile_shift=3),
     N.tune_flags(sampled_tags=True, ldd=1, sample_rounds=0),
     N.tune_flags(sampled_tags=True, tag_samples=2), N.tune_flags(sampled_tags=True, tag_samples=6),
+    N.tune_flags(free_first_round=True), N.tune_flags(free_first_round=True, cc_priority=True, sample_rounds=1),
 ])
 @pytest.mark.parametrize("cfg", ["rmat_small", "grid_small"])
 def test_tuning_fields_never_change_results(flags, cfg):
