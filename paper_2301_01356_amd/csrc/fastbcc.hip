@@ -1390,7 +1390,7 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
   const int canon_big = scal[S_CANON_BIG];
   arc_windows2(
       off, adj, n, A, tile_row, tw,
-      [&](int x, int, bool ok) { return ok ? vlh[x] : make_int4(0, -1, -1, 0); },
+      [&](int x, int, bool) { return vlh[x]; },
       [&](int64_t a, int x, bool ok, int y, int4 rx) {
         if (!ok) return;
         if (y == x) {
@@ -1547,7 +1547,7 @@ __global__ void k_bcc_final(const int* __restrict__ off, const int* __restrict__
   const int4 rbig = vlh[big];
   arc_windows2(
       off, adj, n, A, tile_row, tw,
-      [&](int x, int, bool ok) { return ok ? vlh[x] : make_int4(0, -1, -1, 0); },
+      [&](int x, int, bool) { return vlh[x]; },
       [&](int64_t a, int x, bool ok, int y, int4 rx) {
         if (!ok) return;
         if (y == x) {

@@ -336,37 +336,45 @@ __device__ __forceinline__ void arc_windows(const int* __restrict__ off, const i
 }
 
 // Row of every arc of one window, from the 64 row ends starting at `row`
-// (held in `e`, loaded by the caller); extra blocks of row ends are loaded
-// only when the window spans more than 64 rows.
+// (held in `e`, loaded by the caller).  Only a window spanning more than 64
+// rows takes the branch that loads further blocks of row ends.
+__device__ __forceinline__ int window_pos(int ev, int64_t a) {
+  // number of the 64 row ends in ev that are <= a (0..64)
+  const int64_t e_last = __shfl(ev, WAVE - 1, WAVE);
+  int pos = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1) {
+    const int64_t ej = __shfl(ev, pos + step - 1, WAVE);
+    if (ej <= a) pos += step;
+  }
+  if (pos == WAVE - 1 && e_last <= a) pos = WAVE;
+  return pos;
+}
+
 __device__ __forceinline__ int window_row(const int* __restrict__ off, int n, int64_t a, int64_t tend, int row,
                                           int e) {
-  const int lane = lane_id();
-  int my_row = -1;
-  int lo = row;
-  int ev = e;
-  while (lo < n) {
-    const int64_t e_last = __shfl(ev, WAVE - 1, WAVE);
-    int pos = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-      const int64_t ej = __shfl(ev, pos + step - 1, WAVE);
-      if (ej <= a) pos += step;
+  const int pos = window_pos(e, a);
+  int my_row = pos < WAVE ? row + pos : -1;
+  if (__any(a < tend && my_row < 0)) {
+    const int lane = lane_id();
+    for (int lo = row + WAVE; lo < n; lo += WAVE) {
+      const int ev = off[lo + 1 + lane < n ? lo + 1 + lane : n];
+      const int p = window_pos(ev, a);
+      if (my_row < 0 && p < WAVE) my_row = lo + p;
+      if (!__any(a < tend && my_row < 0)) break;
     }
-    if (pos == WAVE - 1 && e_last <= a) pos = WAVE;
-    if (my_row < 0 && pos < WAVE) my_row = lo + pos;
-    const bool need = (a < tend) && my_row < 0;
-    if (!__any(need)) break;
-    lo += WAVE;
-    if (lo < n) ev = off[lo + 1 + lane < n ? lo + 1 + lane : n];
   }
   return my_row;
 }
 
 // arc_windows pipelined two windows deep: while window k's body waits for
 // its per-row gathers (`fetch(x, y, ok)`, issued one window earlier), window
-// k+1's rows are already found and its gathers are in flight.  Loads are
-// issued in the order their results are waited for, since a wave's vector
-// loads complete in issue order.  body(a, x, ok, y, fetched).
+// k+1's rows are already found and its gathers are in flight.  A wave's vector
+// loads complete in issue order and the compiler can only wait for them by
+// count, so every load here is unconditional (out-of-range lanes read a
+// clamped address and ignore the value) and the loop is unrolled twice with
+// one register set per parity: no branch and no register copy of a value in
+// flight forces a wait for all loads.  body(a, x, ok, y, fetched).
 template <typename Fetch, typename Body>
 __device__ __forceinline__ void arc_windows2(const int* __restrict__ off, const int* __restrict__ adj, int n,
                                              int64_t A, const int* __restrict__ tile_row, int tile_windows,
@@ -377,39 +385,44 @@ __device__ __forceinline__ void arc_windows2(const int* __restrict__ off, const 
   const int64_t tbeg = wave * tile_arcs;
   if (tbeg >= A) return;
   const int64_t tend = tbeg + tile_arcs < A ? tbeg + tile_arcs : A;
-  auto row_ends = [&](int r) { return r < n ? off[r + 1 + lane < n ? r + 1 + lane : n] : 0; };
-  auto target = [&](int64_t a) { return a < tend ? __builtin_nontemporal_load(adj + a) : -1; };
-  // window 0: rows, then window 1's loads, then window 0's gathers
-  int64_t a = tbeg + lane;
+  auto row_ends = [&](int r) {  // r < n
+    const int idx = r + 1 + lane;
+    return off[idx < n ? idx : n];
+  };
+  auto target = [&](int64_t a) { return __builtin_nontemporal_load(adj + (a < tend ? a : tend - 1)); };
+  using F = decltype(fetch(0, 0, false));
   int row = tile_row[wave];
-  int y = target(a);
-  int x = window_row(off, n, a, tend, row, row_ends(row));
-  bool ok = a < tend && x >= 0 && x < n;
-  int last = __shfl(x, WAVE - 1, WAVE);
+  int eA = row_ends(row);
+  int yA = target(tbeg + lane);
+  int xA = window_row(off, n, tbeg + lane, tend, row, eA);
+  bool okA = tbeg + lane < tend && xA >= 0 && xA < n;
+  int last = __shfl(xA, WAVE - 1, WAVE);
   row = last >= 0 ? last : row;
-  int y1 = target(a + WAVE);
-  int e1 = (tbeg + WAVE < tend) ? row_ends(row) : 0;
-  auto f = fetch(ok ? x : -1, y, ok);
-  for (int64_t base = tbeg; base < tend; base += WAVE) {
-    const int64_t a1 = base + WAVE + lane;
-    decltype(f) f1 = f;
-    int x1 = -1;
-    bool ok1 = false;
-    int yy1 = y1;
-    if (base + WAVE < tend) {
-      x1 = window_row(off, n, a1, tend, row, e1);
-      ok1 = a1 < tend && x1 >= 0 && x1 < n;
-      last = __shfl(x1, WAVE - 1, WAVE);
-      row = last >= 0 ? last : row;
-      y1 = target(a1 + WAVE);
-      e1 = (base + 2 * WAVE < tend) ? row_ends(row) : 0;
-      f1 = fetch(ok1 ? x1 : -1, yy1, ok1);
-    }
-    body(base + lane, ok ? x : -1, ok, y, f);
-    x = x1;
-    ok = ok1;
-    y = yy1;
-    f = f1;
+  int eB = row_ends(row);
+  int yB = target(tbeg + WAVE + lane);
+  F fA = fetch(okA ? xA : 0, yA, okA), fB;
+  int xB = -1;
+  bool okB = false;
+  int64_t base = tbeg;
+  // one window: find the next window's rows, load the window after next,
+  // fetch for the next window, then run this window's body
+  auto step = [&](int& xc, bool& okc, int& yc, F& fc, int& ec, int& xn, bool& okn, int& yn, F& fn, int& en) {
+    const int64_t an = base + WAVE + lane;
+    xn = window_row(off, n, an, tend, row, en);
+    okn = an < tend && xn >= 0 && xn < n;
+    last = __shfl(xn, WAVE - 1, WAVE);
+    row = last >= 0 ? last : row;
+    ec = row_ends(row);
+    fn = fetch(okn ? xn : 0, yn, okn);
+    body(base + lane, okc ? xc : -1, okc, yc, fc);
+    yc = target(base + 2 * WAVE + lane);
+    base += WAVE;
+  };
+  for (;;) {
+    step(xA, okA, yA, fA, eA, xB, okB, yB, fB, eB);
+    if (base >= tend) break;
+    step(xB, okB, yB, fB, eB, xA, okA, yA, fA, eA);
+    if (base >= tend) break;
   }
 }
 
