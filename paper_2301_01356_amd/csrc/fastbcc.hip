@@ -104,7 +104,7 @@ inline int ilog2_floor(int64_t x) {
 struct Layout {
   size_t total = 0;
   size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
-      rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, lab, head,
+      rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W, pre, suf, tab, rec, lab, head,
       rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, hubidx, shard, bigbits, dbits, tile_row, scan_tmp;
   int64_t nb = 0;      // rmq blocks of 64
   int levels = 0;      // sparse-table levels
@@ -155,14 +155,10 @@ Layout make_layout(int64_t n, int64_t A) {
   L.first = take(c, n * I);
   L.w1 = take(c, n * I);
   L.w2 = take(c, n * I);
-  L.W1 = take(c, n * I);
-  L.W2 = take(c, n * I);
-  L.pre1 = take(c, n * I);
-  L.suf1 = take(c, n * I);
-  L.pre2 = take(c, n * I);
-  L.suf2 = take(c, n * I);
-  L.tmin = take(c, (size_t)L.levels * L.nb * I);
-  L.tmax = take(c, (size_t)L.levels * L.nb * I);
+  L.W = take(c, n * 2 * I);
+  L.pre = take(c, n * 2 * I);
+  L.suf = take(c, n * 2 * I);
+  L.tab = take(c, (size_t)L.levels * L.nb * 2 * I);
   L.rec = take(c, n * sizeof(int4));
   L.lab = take(c, n * I);
   L.head = take(c, n * I);
@@ -306,10 +302,23 @@ __device__ __forceinline__ int root_sample(int i, int n) {
 
 __global__ void k_root_degree(const int* __restrict__ off, const int* __restrict__ cc, int n, int* rdeg) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ROOT_SAMPLES) return;
-  const int v = root_sample(i, n);
-  if (i > 0 && v == root_sample(i - 1, n)) return;  // n < ROOT_SAMPLES: each vertex once
-  atomicMax(rdeg + cc[v], off[v + 1] - off[v]);
+  int c = -1, d = -1;
+  if (i < ROOT_SAMPLES) {
+    const int v = root_sample(i, n);
+    if (i == 0 || v != root_sample(i - 1, n)) {  // n < ROOT_SAMPLES: each vertex once
+      c = cc[v];
+      d = off[v + 1] - off[v];
+    }
+  }
+  // runs of equal components within the wave reduce to one atomic
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int c2 = __shfl_up(c, o, WAVE), d2 = __shfl_up(d, o, WAVE);
+    if (lane >= o && c2 == c && d2 > d) d = d2;
+  }
+  const int cn = __shfl_down(c, 1, WAVE);
+  if (c >= 0 && (lane == WAVE - 1 || cn != c)) atomicMax(rdeg + c, d);
 }
 
 __global__ void k_root_select(const int* __restrict__ off, const int* __restrict__ cc, int n,
@@ -900,41 +909,46 @@ __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__
                             const int* __restrict__ tile_row, int tw, const int* __restrict__ first,
                             const int4* __restrict__ rec, int* __restrict__ w1, int* __restrict__ w2,
                             unsigned long long* __restrict__ dbits) {
-  arc_windows(off, adj, n, A, tile_row, tw, [&](int64_t a, int x, bool ok, int y) {
-    int mn = INT32_MAX, mx = INT32_MIN;
-    bool desc = false;
-    const int key = ok ? x : -1;
-    if (ok && y != x) {
-      const int fy = first[y];
-      mn = mx = fy;
-      const int2 fl = reinterpret_cast<const int2*>(rec)[2 * (int64_t)x];  // (first[x], last[x])
-      desc = fy > fl.x && fy <= fl.y;
-    }
-    const int lane = lane_id();
-    const uint64_t dm = __ballot(desc);
-    if (lane == 0) dbits[a / WAVE] = dm;  // lane 0 holds the window's first arc, a multiple of 64
+  arc_windows2(
+      off, adj, n, A, tile_row, tw,
+      [&](int x, int y, bool) {
+        const int2 fl = reinterpret_cast<const int2*>(rec)[2 * (int64_t)x];  // (first[x], last[x])
+        return make_int3(first[y], fl.x, fl.y);
+      },
+      [&](int64_t a, int x, bool ok, int y, int3 g) {
+        int mn = INT32_MAX, mx = INT32_MIN;
+        bool desc = false;
+        const int key = ok ? x : -1;
+        if (ok && y != x) {
+          mn = mx = g.x;
+          desc = g.x > g.y && g.x <= g.z;
+        }
+        const int lane = lane_id();
+        const uint64_t dm = __ballot(desc);
+        if (lane == 0) dbits[a / WAVE] = dm;  // lane 0 holds the window's first arc, a multiple of 64
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      int k2 = __shfl_up(key, o, WAVE);
-      int m2 = __shfl_up(mn, o, WAVE);
-      int x2 = __shfl_up(mx, o, WAVE);
-      if (lane >= o && k2 == key) {
-        mn = m2 < mn ? m2 : mn;
-        mx = x2 > mx ? x2 : mx;
-      }
-    }
-    const int knext = __shfl_down(key, 1, WAVE);
-    const bool tail = (lane == WAVE - 1) || knext != key;
-    if (tail && key >= 0 && mn != INT32_MAX) {
-      atomicMin(w1 + key, mn);
-      atomicMax(w2 + key, mx);
-    }
-  });
+        for (int o = 1; o < WAVE; o <<= 1) {
+          int k2 = __shfl_up(key, o, WAVE);
+          int m2 = __shfl_up(mn, o, WAVE);
+          int x2 = __shfl_up(mx, o, WAVE);
+          if (lane >= o && k2 == key) {
+            mn = m2 < mn ? m2 : mn;
+            mx = x2 > mx ? x2 : mx;
+          }
+        }
+        const int knext = __shfl_down(key, 1, WAVE);
+        const bool tail = (lane == WAVE - 1) || knext != key;
+        if (tail && key >= 0 && mn != INT32_MAX) {
+          atomicMin(w1 + key, mn);
+          atomicMax(w2 + key, mx);
+        }
+      });
 }
 
+// Per preorder slot f: (min, max) of the tags, one 8-byte pair so a range
+// query gathers both at once.
 __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restrict__ w1, const int* __restrict__ w2,
-                              int n, int* __restrict__ W1, int* __restrict__ W2, int* __restrict__ order,
-                              int* status) {
+                              int n, int2* __restrict__ W, int* __restrict__ order, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int f = first[v];
@@ -943,62 +957,46 @@ __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restri
     return;
   }
   int a = w1[v], b = w2[v];
-  W1[f] = a < f ? a : f;
-  W2[f] = b > f ? b : f;
+  W[f] = make_int2(a < f ? a : f, b > f ? b : f);
   if (order) order[f] = v;
 }
 
-// In-block prefix/suffix min and max (block = 64 consecutive preorder slots
-// = one wave), block minima/maxima into sparse-table level 0.
-__global__ void k_rmq_block(const int* __restrict__ W1, const int* __restrict__ W2, int n, int64_t nb,
-                            int* __restrict__ pre1, int* __restrict__ suf1, int* __restrict__ pre2,
-                            int* __restrict__ suf2, int* __restrict__ tmin, int* __restrict__ tmax) {
+__device__ __forceinline__ int2 mm(int2 p, int2 q) {
+  return make_int2(q.x < p.x ? q.x : p.x, q.y > p.y ? q.y : p.y);
+}
+
+// In-block prefix/suffix (min, max) (block = 64 consecutive preorder slots
+// = one wave), block (min, max) into sparse-table level 0.
+__global__ void k_rmq_block(const int2* __restrict__ W, int n, int64_t nb, int2* __restrict__ pre,
+                            int2* __restrict__ suf, int2* __restrict__ tab) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = lane_id();
   const bool in = i < n;
-  const int a = in ? W1[i] : INT32_MAX;
-  const int b = in ? W2[i] : INT32_MIN;
-  int pa = a, pb = b, sa = a, sb = b;
+  const int2 w = in ? W[i] : make_int2(INT32_MAX, INT32_MIN);
+  int2 p = w, q = w;
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
-    int ta = __shfl_up(pa, o, WAVE), tb = __shfl_up(pb, o, WAVE);
-    int ua = __shfl_down(sa, o, WAVE), ub = __shfl_down(sb, o, WAVE);
-    if (lane >= o) {
-      pa = ta < pa ? ta : pa;
-      pb = tb > pb ? tb : pb;
-    }
-    if (lane + o < WAVE) {
-      sa = ua < sa ? ua : sa;
-      sb = ub > sb ? ub : sb;
-    }
+    const int2 t = make_int2(__shfl_up(p.x, o, WAVE), __shfl_up(p.y, o, WAVE));
+    const int2 u = make_int2(__shfl_down(q.x, o, WAVE), __shfl_down(q.y, o, WAVE));
+    if (lane >= o) p = mm(p, t);
+    if (lane + o < WAVE) q = mm(q, u);
   }
   if (in) {
-    pre1[i] = pa;
-    suf1[i] = sa;
-    pre2[i] = pb;
-    suf2[i] = sb;
+    pre[i] = p;
+    suf[i] = q;
   }
   const int64_t blk = i / WAVE;
-  if (lane == 0 && blk < nb) {
-    tmin[blk] = sa;
-    tmax[blk] = sb;
-  }
+  if (lane == 0 && blk < nb) tab[blk] = q;
 }
 
-__global__ void k_rmq_level(int* __restrict__ tmin, int* __restrict__ tmax, int64_t nb, int j) {
+__global__ void k_rmq_level(int2* __restrict__ tab, int64_t nb, int j) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   const int64_t h = int64_t(1) << (j - 1);
-  const int* pm = tmin + (size_t)(j - 1) * nb;
-  const int* px = tmax + (size_t)(j - 1) * nb;
-  int m = pm[b], x = px[b];
-  if (b + h < nb) {
-    int m2 = pm[b + h], x2 = px[b + h];
-    m = m2 < m ? m2 : m;
-    x = x2 > x ? x2 : x;
-  }
-  tmin[(size_t)j * nb + b] = m;
-  tmax[(size_t)j * nb + b] = x;
+  const int2* pt = tab + (size_t)(j - 1) * nb;
+  int2 m = pt[b];
+  if (b + h < nb) m = mm(m, pt[b + h]);
+  tab[(size_t)j * nb + b] = m;
 }
 
 // low/high over [first, last]; fence(p(v), v) = first[p] <= low[v] and
@@ -1013,10 +1011,9 @@ __global__ void k_rmq_level(int* __restrict__ tmin, int* __restrict__ tmax, int6
 //   QUERY_RECHECK  exact test for the undecided vertices only.
 enum QueryMode : int { QUERY_EXACT = 0, QUERY_CERTIFY = 1, QUERY_RECHECK = 2 };
 
-__global__ void k_rmq_query(int n, int64_t nb, const int* __restrict__ W1, const int* __restrict__ W2,
-                            const int* __restrict__ pre1, const int* __restrict__ suf1, const int* __restrict__ pre2,
-                            const int* __restrict__ suf2, const int* __restrict__ tmin, const int* __restrict__ tmax,
-                            int4* rec, int mode, int* __restrict__ cover, int* status) {
+__global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const int2* __restrict__ pre,
+                            const int2* __restrict__ suf, const int2* __restrict__ tab, int4* rec, int mode,
+                            int* __restrict__ cover, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int4 me = rec[v];
@@ -1035,31 +1032,20 @@ __global__ void k_rmq_query(int n, int64_t nb, const int* __restrict__ W1, const
     return;
   }
   const int bl = l / WAVE, br = r / WAVE;
-  int lo, hi;
+  int2 m;
   if (bl == br) {
-    lo = INT32_MAX;
-    hi = INT32_MIN;
-    for (int k = l; k <= r; ++k) {
-      int a = W1[k], b = W2[k];
-      lo = a < lo ? a : lo;
-      hi = b > hi ? b : hi;
-    }
+    m = W[l];
+    for (int k = l + 1; k <= r; ++k) m = mm(m, W[k]);
   } else {
-    lo = suf1[l] < pre1[r] ? suf1[l] : pre1[r];
-    hi = suf2[l] > pre2[r] ? suf2[l] : pre2[r];
+    m = mm(suf[l], pre[r]);
     const int len = br - bl - 1;
     if (len > 0) {
       const int j = 31 - __clz(len);
       const size_t lv = (size_t)j * nb;
-      int m1 = tmin[lv + bl + 1], m2 = tmin[lv + br - (1 << j)];
-      int x1 = tmax[lv + bl + 1], x2 = tmax[lv + br - (1 << j)];
-      lo = m1 < lo ? m1 : lo;
-      lo = m2 < lo ? m2 : lo;
-      hi = x1 > hi ? x1 : hi;
-      hi = x2 > hi ? x2 : hi;
+      m = mm(m, mm(tab[lv + bl + 1], tab[lv + br - (1 << j)]));
     }
   }
-  const bool fence = pr.x <= lo && pr.y >= hi;
+  const bool fence = pr.x <= m.x && pr.y >= m.y;
   if (mode == QUERY_CERTIFY) {
     if (fence) {
       rec[v].w = 2;
@@ -1160,13 +1146,12 @@ __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__
 
 __global__ void k_rmq_rescatter(const int* __restrict__ frow, const int* __restrict__ frows,
                                 const int* __restrict__ first, const int* __restrict__ w1,
-                                const int* __restrict__ w2, int* __restrict__ W1, int* __restrict__ W2) {
+                                const int* __restrict__ w2, int2* __restrict__ W) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= *frows) return;
   const int x = frow[r], f = first[x];
   const int a = w1[x], b = w2[x];
-  W1[f] = a < f ? a : f;
-  W2[f] = b > f ? b : f;
+  W[f] = make_int2(a < f ? a : f, b > f ? b : f);
 }
 
 // ------------------------------------------------------------ Last-CC
@@ -1827,21 +1812,19 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, eid, eu, ev, lone, n, pos, eflag, first, rec, scal + S_STATUS);
   LAUNCH(c, k_lone_tags, gn, BLOCK, lone, n, first, rec);
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
-  int *W1 = I(L.W1), *W2 = I(L.W2), *pre1 = I(L.pre1), *suf1 = I(L.suf1), *pre2 = I(L.pre2), *suf2 = I(L.suf2);
-  int *tmin = I(L.tmin), *tmax = I(L.tmax);
+  int2 *W = (int2*)(w + L.W), *pre = (int2*)(w + L.pre), *suf = (int2*)(w + L.suf), *tab = (int2*)(w + L.tab);
   auto rmq_tables = [&]() {
-    LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W1, W2, n, L.nb, pre1, suf1, pre2, suf2, tmin,
-           tmax);
-    for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tmin, tmax, L.nb, j);
+    LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W, n, L.nb, pre, suf, tab);
+    for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j);
   };
   if (!tune.sampled_tags) {
     fill_i32(c, w1, INT32_MAX, n);
     fill_i32(c, w2, INT32_MIN, n);
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
-    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, (int*)nullptr, scal + S_STATUS);
+    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, (int*)nullptr, scal + S_STATUS);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_EXACT,
-           (int*)nullptr, scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, (int*)nullptr,
+           scal + S_STATUS);
   } else {
     // sampled tags certify most non-fences; exact tags for the subtrees of the
     // undecided vertices only
@@ -1849,10 +1832,10 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
     fill_i32(c, cover, 0, (int64_t)n + 2);
     LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, first, n, tune.tag_samples, w1, w2);
-    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W1, W2, order, scal + S_STATUS);
+    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_CERTIFY,
-           cover, scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, cover,
+           scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
     LAUNCH(c, k_dirty_deg, gn, BLOCK, off, order, cover, n, tune.tag_samples, foff, frank);
     scan_inplace(c, foff, n, nullptr, tmp, foff + n);
@@ -1860,10 +1843,10 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, order, frow, fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
     LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, w1, w2);
-    LAUNCH(c, k_rmq_rescatter, gn, BLOCK, frow, frows, first, w1, w2, W1, W2);
+    LAUNCH(c, k_rmq_rescatter, gn, BLOCK, frow, frows, first, w1, w2, W);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W1, W2, pre1, suf1, pre2, suf2, tmin, tmax, rec, (int)QUERY_RECHECK,
-           (int*)nullptr, scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, (int*)nullptr,
+           scal + S_STATUS);
   }
 
   // ---- Last-CC on the implicit skeleton
