@@ -93,7 +93,9 @@ typedef enum fastbcc_status {
  *   bits 21-22 sampled neighbours per vertex in that mode: 0 = 4, 1 = 2,
  *              2 = 3, 3 = 6
  *   bit  23    First-CC's first sampling round links each vertex to its
- *              sample only when the sample ranks above it, without atomics */
+ *              sample only when the sample ranks above it, without atomics
+ *   bit  24    Last-CC hooks by hashed priority, then relabels every set to
+ *              its smallest member */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
@@ -102,6 +104,7 @@ typedef enum fastbcc_status {
 #define FASTBCC_TUNE_SAMPLED_TAGS 0x100000u
 #define FASTBCC_TUNE_TAG_SAMPLES_SHIFT 21
 #define FASTBCC_TUNE_FREE_FIRST_ROUND 0x800000u
+#define FASTBCC_TUNE_LCC_PRIORITY 0x1000000u
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -90,6 +90,8 @@ enum Scalar : int {
   S_NODES = 8,      // list nodes of the Euler tour
   S_ENTRIES = 9,    // entry flags over the tour
   S_LDD_HUGE = 10,  // two slots: long rows listed by a decomposition round
+  S_BIG_ROOT = 12,  // Last-CC root of the sampled largest set (priority hooking)
+  S_BIG_MIN = 13,   // its smallest member
   S_COUNT = 64,
 };
 
@@ -192,6 +194,7 @@ struct Tune {
   bool sampled_tags = false;  // fences certified from sampled tags, exact tags only where needed
   int tag_samples = 4;        // sampled neighbours per vertex in that mode
   bool first_round_free = false;  // First-CC's first sampling round links without atomics
+  bool lcc_prio = false;          // Last-CC hooks by hashed priority, then relabels to smallest members
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
@@ -199,8 +202,9 @@ bool decode_flags(uint32_t flags, Tune& t) {
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
                          FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
-                         FASTBCC_TUNE_FREE_FIRST_ROUND;
+                         FASTBCC_TUNE_FREE_FIRST_ROUND | FASTBCC_TUNE_LCC_PRIORITY;
   t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
+  t.lcc_prio = (flags & FASTBCC_TUNE_LCC_PRIORITY) != 0;
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
   static const int kSamples[4] = {4, 2, 3, 6};
   t.tag_samples = kSamples[(flags >> FASTBCC_TUNE_TAG_SAMPLES_SHIFT) & 0x3];
@@ -1160,12 +1164,24 @@ __global__ void k_lcc_init(int* __restrict__ lab, int n) {
   if (v < n) lab[v] = v;
 }
 
+// Last-CC hooks by id (a set's root is its smallest member, which the
+// read-out relies on) or, as a tuning variant, by hashed priority (shallower
+// trees on lattices and long paths) followed by a relabelling to the smallest
+// member.  One rule per solve: mixing rules could hook two roots under each
+// other.
+template <bool PRIO>
+__device__ __forceinline__ void lcc_link(int* lab, int u, int v) {
+  if (PRIO) uf_link_prio(lab, u, v);
+  else uf_link(lab, u, v);
+}
+
 // Plain (non-fence) tree edges are skeleton edges.
+template <bool PRIO>
 __global__ void k_lcc_tree(const int4* __restrict__ rec, int n, int* lab) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int4 r = rec[v];
-  if (r.z >= 0 && r.w == 0) uf_link(lab, v, r.z);
+  if (r.z >= 0 && r.w == 0) lcc_link<PRIO>(lab, v, r.z);
 }
 
 // Non-tree arc x-y is a skeleton edge iff neither endpoint is an ancestor of
@@ -1178,6 +1194,7 @@ __device__ __forceinline__ bool cross_edge(int x, int4 rx, int y, int4 ry) {
   return !y_under_x && !x_under_y;
 }
 
+template <bool PRIO>
 __global__ void k_lcc_sample(const int* __restrict__ off, const int* __restrict__ adj, const int4* __restrict__ rec,
                              int n, int r, int* lab) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1185,10 +1202,11 @@ __global__ void k_lcc_sample(const int* __restrict__ off, const int* __restrict_
   const int64_t b = off[v], e = off[v + 1];
   if (e > b) {
     int y = adj[b + sample_pos(v, r, e - b)];
-    if (y != v && cross_edge(v, rec[v], y, rec[y])) uf_link(lab, v, y);
+    if (y != v && cross_edge(v, rec[v], y, rec[y])) lcc_link<PRIO>(lab, v, y);
   }
 }
 
+template <bool PRIO>
 __global__ void k_lcc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                             const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
                             int tw, const int4* __restrict__ rec, int* lab) {
@@ -1199,8 +1217,71 @@ __global__ void k_lcc_sweep(const int* __restrict__ off, const int* __restrict__
     const int x = frow[i];
     const int64_t a = (int64_t)off[x] + (k - (int64_t)fstart[i]);
     const int y = adj[a];
-    if (y != x && cross_edge(x, rec[x], y, rec[y])) uf_link(lab, x, y);
+    if (y != x && cross_edge(x, rec[x], y, rec[y])) lcc_link<PRIO>(lab, x, y);
   });
+}
+
+// After priority hooking: every label becomes the smallest member of its set.
+// The largest set (sampled label big) takes a two-level reduction (block
+// minima, then one block over them); the others take the minimum of their
+// members with one atomic per run of equal labels in a wave.
+__global__ void k_big_min_part(const int* __restrict__ lab, int n, const int* __restrict__ scal,
+                               int* __restrict__ part) {
+  __shared__ int wmin[BLOCK / WAVE];
+  const int big = lab[scal[S_BIG_LAB]];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int m = (v < n && lab[v] == big) ? v : INT32_MAX;
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int m2 = __shfl_down(m, o, WAVE);
+    m = m2 < m ? m2 : m;
+  }
+  if (lane_id() == 0) wmin[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BLOCK / WAVE; ++w) m = wmin[w] < m ? wmin[w] : m;
+    part[blockIdx.x] = m;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_big_min(const int* __restrict__ lab, const int* __restrict__ part,
+                                                  int parts, int* scal) {
+  __shared__ int wmin[1024 / WAVE];
+  int m = INT32_MAX;
+  for (int i = threadIdx.x; i < parts; i += blockDim.x) m = part[i] < m ? part[i] : m;
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int m2 = __shfl_down(m, o, WAVE);
+    m = m2 < m ? m2 : m;
+  }
+  if (lane_id() == 0) wmin[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 1024 / WAVE; ++w) m = wmin[w] < m ? wmin[w] : m;
+    scal[S_BIG_ROOT] = lab[scal[S_BIG_LAB]];
+    scal[S_BIG_MIN] = m;
+  }
+}
+
+__global__ void k_label_min(const int* __restrict__ lab, int n, const int* __restrict__ scal, int* minv) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int L = -1;
+  if (v < n) L = lab[v];
+  if (L == scal[S_BIG_ROOT]) L = -1;
+  int m = v;
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int l2 = __shfl_up(L, o, WAVE), m2 = __shfl_up(m, o, WAVE);
+    if (lane >= o && l2 == L && m2 < m) m = m2;
+  }
+  const int ln = __shfl_down(L, 1, WAVE);
+  if (L >= 0 && (lane == WAVE - 1 || ln != L)) atomicMin(minv + L, m);
+}
+
+__global__ void k_relabel(int* lab, int n, const int* __restrict__ scal, const int* __restrict__ minv) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int L = lab[v];
+  lab[v] = L == scal[S_BIG_ROOT] ? scal[S_BIG_MIN] : minv[L];
 }
 
 // ------------------------------------------------------------ read-out
@@ -1852,16 +1933,28 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   // ---- Last-CC on the implicit skeleton
   int* lab = I(L.lab);
   LAUNCH(c, k_lcc_init, gn, BLOCK, lab, n);
-  LAUNCH(c, k_lcc_tree, gn, BLOCK, rec, n, lab);
+  if (tune.lcc_prio) LAUNCH(c, k_lcc_tree<true>, gn, BLOCK, rec, n, lab);
+  else LAUNCH(c, k_lcc_tree<false>, gn, BLOCK, rec, n, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
   for (int r = 0; r < tune.sample_rounds; ++r) {
-    LAUNCH(c, k_lcc_sample, gn, BLOCK, off, adj, rec, n, r, lab);
+    if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gn, BLOCK, off, adj, rec, n, r, lab);
+    else LAUNCH(c, k_lcc_sample<false>, gn, BLOCK, off, adj, rec, n, r, lab);
     LAUNCH(c, k_compress, gn, BLOCK, lab, n);
   }
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
   frontier(lab, S_BIG_LAB);
-  LAUNCH(c, k_lcc_sweep, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
+  if (tune.lcc_prio) LAUNCH(c, k_lcc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
+  else LAUNCH(c, k_lcc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+  if (tune.lcc_prio) {
+    int* minv = I(L.minid);  // refilled by the read-out
+    fill_i32(c, minv, INT32_MAX, n);
+    int* part = I(L.bsum);  // cdiv(n, BLOCK) + 1 slots, used again by the BCC count
+    LAUNCH(c, k_big_min_part, gn, BLOCK, lab, n, scal, part);
+    LAUNCH(c, k_big_min, 1, 1024, lab, part, (int)gn, scal);
+    LAUNCH(c, k_label_min, gn, BLOCK, lab, n, scal, minv);
+    LAUNCH(c, k_relabel, gn, BLOCK, lab, n, scal, minv);
+  }
 
   // ---- heads, articulation points, canonical labels
   int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid), *canon = I(L.canon), *bsum = I(L.bsum);

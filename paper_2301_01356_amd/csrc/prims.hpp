@@ -222,6 +222,18 @@ __device__ __forceinline__ uint32_t uf_prio(int x) {
   return h;
 }
 
+__device__ __forceinline__ void uf_link_prio(int* p, int u, int v) {
+  if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
+  int ru = uf_find(p, u), rv = uf_find(p, v);
+  while (ru != rv) {
+    const bool u_low = uf_prio(ru) < uf_prio(rv);
+    const int lo = u_low ? ru : rv, hi = u_low ? rv : ru;
+    if (ld_relaxed(p + lo) == lo && atomicCAS(p + lo, lo, hi) == lo) return;
+    ru = uf_find(p, ru);
+    rv = uf_find(p, rv);
+  }
+}
+
 __device__ __forceinline__ void uf_link_record_prio(int* p, int u, int v, int* hook_u, int* hook_v) {
   if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
   int ru = uf_find(p, u), rv = uf_find(p, v);

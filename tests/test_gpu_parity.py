@@ -59,6 +59,7 @@ def test_small_configs(name, off64):
 
 SORTED_FLAGS = [
     N.FLAG_SORTED_ROWS,
+    N.FLAG_SORTED_ROWS | N.tune_flags(lcc_priority=True, sampled_tags=True),
     N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True),
     N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True, ruler_shift=7, tile_shift=4),
     N.FLAG_SORTED_ROWS | N.tune_flags(ldd=1, sample_rounds=0),
@@ -155,6 +156,7 @@ def test_multigraph_self_loops_unsorted_rows():
     N.tune_flags(sampled_tags=True, ldd=1, sample_rounds=0),
     N.tune_flags(sampled_tags=True, tag_samples=2), N.tune_flags(sampled_tags=True, tag_samples=6),
     N.tune_flags(free_first_round=True), N.tune_flags(free_first_round=True, cc_priority=True, sample_rounds=1),
+    N.tune_flags(lcc_priority=True), N.tune_flags(lcc_priority=True, sampled_tags=True, sample_rounds=0),
 ])
 @pytest.mark.parametrize("cfg", ["rmat_small", "grid_small"])
 def test_tuning_fields_never_change_results(flags, cfg):
