@@ -67,10 +67,10 @@ def alg_bytes(kernel, n, A):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources they were taken on (hash below); otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "0ef8113c16453e17",
+    "src_sha": "97d485c80a770bcd",
     "workload": "rmat25",
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_tag_sweep": {"fetch_kib": 58015006.0, "write_kib": 1895020.2},
+    "k_bcc_final": {"fetch_kib": 2489051.6, "write_kib": 4090617.8},
 }
 
 
