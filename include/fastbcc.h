@@ -95,7 +95,8 @@ typedef enum fastbcc_status {
  *   bit  23    First-CC's first sampling round links each vertex to its
  *              sample only when the sample ranks above it, without atomics
  *   bit  24    Last-CC hooks by hashed priority, then relabels every set to
- *              its smallest member */
+ *              its smallest member
+ *   bits 25-26 Last-CC sampling rounds: 0 = as First-CC, k = k - 1 rounds */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
@@ -105,6 +106,7 @@ typedef enum fastbcc_status {
 #define FASTBCC_TUNE_TAG_SAMPLES_SHIFT 21
 #define FASTBCC_TUNE_FREE_FIRST_ROUND 0x800000u
 #define FASTBCC_TUNE_LCC_PRIORITY 0x1000000u
+#define FASTBCC_TUNE_LCC_ROUNDS_SHIFT 25
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -32,6 +32,7 @@ TUNE_TAG_SAMPLES_SHIFT = 21
 TAG_SAMPLE_CODES = {4: 0, 2: 1, 3: 2, 6: 3}
 TUNE_FREE_FIRST_ROUND = 0x800000
 TUNE_LCC_PRIORITY = 0x1000000
+TUNE_LCC_ROUNDS_SHIFT = 25
 
 EXPORTED = (
     "fastbcc_workspace_size",
@@ -126,7 +127,7 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
 
 def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False,
                ldd: int = 0, sampled_tags: bool = False, tag_samples: int = 4,
-               free_first_round: bool = False, lcc_priority: bool = False) -> int:
+               free_first_round: bool = False, lcc_priority: bool = False, lcc_rounds=None) -> int:
     """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
     the low-diameter decomposition before First-CC's union-find, beta = 2^-k;
     ``sampled_tags`` certifies fences from ``tag_samples`` (2, 3, 4 or 6)
@@ -136,6 +137,8 @@ def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc
     f |= TAG_SAMPLE_CODES[tag_samples] << TUNE_TAG_SAMPLES_SHIFT
     f |= TUNE_FREE_FIRST_ROUND if free_first_round else 0
     f |= TUNE_LCC_PRIORITY if lcc_priority else 0
+    if lcc_rounds is not None:
+        f |= (int(lcc_rounds) + 1) << TUNE_LCC_ROUNDS_SHIFT
     f |= (ldd & 0x3) << TUNE_LDD_SHIFT
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT

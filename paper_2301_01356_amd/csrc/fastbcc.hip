@@ -195,6 +195,7 @@ struct Tune {
   int tag_samples = 4;        // sampled neighbours per vertex in that mode
   bool first_round_free = false;  // First-CC's first sampling round links without atomics
   bool lcc_prio = false;          // Last-CC hooks by hashed priority, then relabels to smallest members
+  int lcc_rounds = -1;            // Last-CC sampling rounds (-1: as First-CC)
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
@@ -202,7 +203,12 @@ bool decode_flags(uint32_t flags, Tune& t) {
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
                          FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
-                         FASTBCC_TUNE_FREE_FIRST_ROUND | FASTBCC_TUNE_LCC_PRIORITY;
+                         FASTBCC_TUNE_FREE_FIRST_ROUND | FASTBCC_TUNE_LCC_PRIORITY |
+                         (0x3u << FASTBCC_TUNE_LCC_ROUNDS_SHIFT);
+  {
+    const uint32_t lr = (flags >> FASTBCC_TUNE_LCC_ROUNDS_SHIFT) & 0x3;
+    t.lcc_rounds = lr == 0 ? -1 : (int)lr - 1;
+  }
   t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
   t.lcc_prio = (flags & FASTBCC_TUNE_LCC_PRIORITY) != 0;
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
@@ -1015,11 +1021,19 @@ __global__ void k_rmq_level(int2* __restrict__ tab, int64_t nb, int j) {
 //   QUERY_RECHECK  exact test for the undecided vertices only.
 enum QueryMode : int { QUERY_EXACT = 0, QUERY_CERTIFY = 1, QUERY_RECHECK = 2 };
 
+//   Thread t handles vertex order[t] (the vertex at preorder slot t), or
+//   vertex t without an order: in preorder the range reads of neighbouring
+//   threads fall on neighbouring slots, since most subtrees are small.
 __global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const int2* __restrict__ pre,
                             const int2* __restrict__ suf, const int2* __restrict__ tab, int4* rec, int mode,
-                            int* __restrict__ cover, int* status) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+                            const int* __restrict__ order, int* __restrict__ cover, int* status) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int v = order ? order[t] : t;
+  if (v < 0 || v >= n) {  // only if first[] was no permutation (already reported)
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    return;
+  }
   const int4 me = rec[v];
   if (mode == QUERY_RECHECK && me.w != 2) return;
   const int l = me.x, r = me.y;
@@ -1902,10 +1916,11 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     fill_i32(c, w1, INT32_MAX, n);
     fill_i32(c, w2, INT32_MIN, n);
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
-    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, (int*)nullptr, scal + S_STATUS);
+    int* order = pos;  // preorder -> vertex; the tour positions are dead now
+    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, (int*)nullptr,
-           scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, (const int*)order,
+           (int*)nullptr, scal + S_STATUS);
   } else {
     // sampled tags certify most non-fences; exact tags for the subtrees of the
     // undecided vertices only
@@ -1915,8 +1930,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, first, n, tune.tag_samples, w1, w2);
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, cover,
-           scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, (const int*)order,
+           cover, scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
     LAUNCH(c, k_dirty_deg, gn, BLOCK, off, order, cover, n, tune.tag_samples, foff, frank);
     scan_inplace(c, foff, n, nullptr, tmp, foff + n);
@@ -1926,8 +1941,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, w1, w2);
     LAUNCH(c, k_rmq_rescatter, gn, BLOCK, frow, frows, first, w1, w2, W);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, (int*)nullptr,
-           scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, (const int*)nullptr,
+           (int*)nullptr, scal + S_STATUS);
   }
 
   // ---- Last-CC on the implicit skeleton
@@ -1936,7 +1951,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   if (tune.lcc_prio) LAUNCH(c, k_lcc_tree<true>, gn, BLOCK, rec, n, lab);
   else LAUNCH(c, k_lcc_tree<false>, gn, BLOCK, rec, n, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
-  for (int r = 0; r < tune.sample_rounds; ++r) {
+  const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
+  for (int r = 0; r < lcc_rounds; ++r) {
     if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gn, BLOCK, off, adj, rec, n, r, lab);
     else LAUNCH(c, k_lcc_sample<false>, gn, BLOCK, off, adj, rec, n, r, lab);
     LAUNCH(c, k_compress, gn, BLOCK, lab, n);

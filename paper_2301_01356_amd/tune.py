@@ -1,13 +1,14 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes eight speed-only knobs in its flags word (they never change
+The C ABI exposes nine speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
 sampling off), the First-CC union-find variant (hook by id or by hashed
 priority), an optional low-diameter decomposition in front of First-CC's
 union-find (the paper's LDD-UF-JTB shape) with its beta, exact or
 sampled-and-certified tags (and how many samples), an atomic-free first
-sampling round, Last-CC's hooking rule, and the arc-tile size (64-arc windows per wave,
+sampling round, Last-CC's hooking rule and sampling rounds, and the arc-tile
+size (64-arc windows per wave,
 i.e. work per wave).  The tuner times candidates by
 coordinate descent on the real input and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
@@ -34,7 +35,8 @@ TAGS = (0, 1)  # 0 = exact tag sweep over every arc, 1 = sampled-tag certificati
 TAG_SAMPLES = (4, 2, 3, 6)  # sampled neighbours per vertex when certifying
 FREE = (0, 1)  # First-CC's first sampling round without atomics
 LCC = (0, 1)  # Last-CC hooking: 0 = by id, 1 = by hashed priority + relabelling
-START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0}
+LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)
+START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1}
 
 
 def skew_class(degrees: np.ndarray) -> str:
@@ -59,7 +61,8 @@ def encode(cfg: Dict[str, int]) -> int:
     return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"],
                         cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)),
                         sampled_tags=bool(cfg.get("tags", 0)), tag_samples=int(cfg.get("ts", 4)),
-                        free_first_round=bool(cfg.get("free", 0)), lcc_priority=bool(cfg.get("lcc", 0)))
+                        free_first_round=bool(cfg.get("free", 0)), lcc_priority=bool(cfg.get("lcc", 0)),
+                        lcc_rounds=None if cfg.get("lr", -1) < 0 else int(cfg["lr"]))
 
 
 class Tuner:
@@ -105,7 +108,7 @@ class Tuner:
         for _ in range(2):
             changed = False
             for knob, values in (("tags", TAGS), ("uf", UF), ("free", FREE), ("lcc", LCC), ("ldd", LDD), ("sample", SAMPLE),
-                                 ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES)):
+                                 ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES), ("lr", LCC_ROUNDS)):
                 if knob == "ts" and not cfg["tags"]:
                     continue
                 best_v, best_t = cfg[knob], cost(cfg)

@@ -97,4 +97,4 @@ def test_tune_flag_encoding():
     assert N.tune_flags(ldd=2) == 2 << N.TUNE_LDD_SHIFT
     assert N.tune_flags(sampled_tags=True) == N.TUNE_SAMPLED_TAGS
     assert (N.tune_flags(tag_samples=2) >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3 == 1
-    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 25) == N.ERR_INVALID_ARGUMENT
+    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 27) == N.ERR_INVALID_ARGUMENT
