@@ -1840,7 +1840,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   }
   // compress after every round: the next round's finds then take one hop
   for (int r = 0; r < tune.sample_rounds; ++r) {
-    if (r == 0 && tune.first_round_free && !tune.ldd) {
+    const bool free_round = r == 0 && tune.first_round_free && !tune.ldd;
+    if (free_round) {
       if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gn, BLOCK, off, adj, n, cc, hu, hv);
       else LAUNCH(c, k_cc_first_round<false>, gn, BLOCK, off, adj, n, cc, hu, hv);
     } else if (tune.cc_prio) {
@@ -1848,7 +1849,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     } else {
       LAUNCH(c, k_cc_sample<false>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
     }
-    LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+    // the atomic-free round leaves short chains that the next round's finds
+    // walk anyway; every other round is flattened for the next one
+    if (!free_round || r + 1 == tune.sample_rounds) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   }
   if (tune.sample_rounds == 0) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
