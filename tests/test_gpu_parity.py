@@ -314,3 +314,69 @@ def test_vertex_labels_batched_are_graph_local():
         v0, v1 = u.vbegin[i], u.vbegin[i + 1]
         lab, _, _, _, _ = oracle.ht_bcc(g.offsets, g.adj)
         check_bc_labeling(g.n, g.offsets, g.adj, lab, home[v0:v1], head[v0:v1], f"graph {i}")
+
+
+def hub_graph(seed=21):
+    """Two hubs above every degree threshold of the solve (hub shards, long
+    decomposition rows, long mirror searches): hub 0 with 12,000 pendant
+    leaves and 1,500 triangles, hub 1 with 5,000 leaves, the hubs joined by
+    three disjoint paths, a long pendant path, and random chords."""
+    rng = np.random.default_rng(seed)
+    edges = []
+    nxt = 2
+    for _ in range(12000):
+        edges.append((0, nxt)); nxt += 1
+    for _ in range(1500):
+        a, b = nxt, nxt + 1; nxt += 2
+        edges += [(0, a), (a, b), (b, 0)]
+    for _ in range(5000):
+        edges.append((1, nxt)); nxt += 1
+    for _ in range(3):
+        prev = 0
+        for _ in range(50):
+            edges.append((prev, nxt)); prev = nxt; nxt += 1
+        edges.append((prev, 1))
+    prev = 1
+    for _ in range(3000):
+        edges.append((prev, nxt)); prev = nxt; nxt += 1
+    n = nxt
+    for _ in range(400):
+        u, v = int(rng.integers(2, n)), int(rng.integers(2, n))
+        edges.append((u, v))
+    return gen.from_edges(n, edges)
+
+
+HUB_FLAGS = [
+    0,
+    N.FLAG_SORTED_ROWS,
+    N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True),
+    N.tune_flags(sampled_tags=True, cc_priority=True, tag_samples=2),
+    N.tune_flags(ldd=1),
+    N.FLAG_SORTED_ROWS | N.tune_flags(ldd=2, sample_rounds=0),
+    N.FLAG_SORTED_ROWS | N.tune_flags(lcc_priority=True, free_first_round=True, lcc_rounds=0),
+    N.FLAG_SORTED_ROWS | N.tune_flags(free_first_round=True, cc_priority=True, sampled_tags=True, tile_shift=5),
+]
+
+
+@pytest.mark.parametrize("flags", HUB_FLAGS)
+def test_hubs_above_every_degree_threshold(flags):
+    g = hub_graph()
+    note(f"hub graph n={g.n} arcs={g.num_arcs} max degree={int(np.diff(g.offsets).max())} flags={flags:#x}")
+    assert_parity(g, gpu_solve(g, flags=flags), f"hub graph {flags:#x}")
+
+
+@pytest.mark.parametrize("flags", HUB_FLAGS[:3])
+def test_hub_graphs_batched(flags):
+    graphs = [hub_graph(21), gen.from_edges(5, cycle(5)), hub_graph(22)]
+    u = gen.unite(graphs)
+    note(f"batched hub graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off = torch.from_numpy(u.offsets32()).to(DEV)
+    adj = torch.from_numpy(u.adj).to(DEV)
+    r = solve_batched(vb, off, adj, flags=flags)
+    torch.cuda.synchronize()
+    lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for i, gi in enumerate(graphs):
+        v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
+        a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
+        assert_parity(gi, (lab[a0:a1], ap[v0:v1], int(nb[i])), f"batched hub graph {i}")
