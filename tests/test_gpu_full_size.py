@@ -25,8 +25,16 @@ def test_rmat25_full_size_exact():
     off = torch.from_numpy(g.offsets).to(DEV)  # int64 offsets, as benchmarked
     adj = torch.from_numpy(g.adj).to(DEV)
     outs = []
+    # the defaults, the variants, and the configurations the autotuner picks for
+    # this graph in the benchmark (sorted rows, certified tags, free first round,
+    # no Last-CC sampling rounds)
     for flags in (0, N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True), N.tune_flags(ldd=1),
-                  N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True)):
+                  N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True),
+                  N.FLAG_SORTED_ROWS | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, sampled_tags=True,
+                                                    tag_samples=4, free_first_round=True, lcc_rounds=0),
+                  N.FLAG_SORTED_ROWS | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True,
+                                                    sampled_tags=True, tag_samples=3, free_first_round=True,
+                                                    lcc_priority=True)):
         note(f"R-MAT scale 25: GPU solve flags={flags:#x}")
         r = solve(off, adj, flags=flags)
         torch.cuda.synchronize()
@@ -49,20 +57,22 @@ def test_batch4096_full_size_exact():
     vb = torch.from_numpy(u.vbegin).to(DEV)
     off = torch.from_numpy(u.offsets32()).to(DEV)
     adj = torch.from_numpy(u.adj).to(DEV)
-    note("batch of 4096: GPU batched solve")
-    r = solve_batched(vb, off, adj)
-    torch.cuda.synchronize()
-    lab = r.edge_label.cpu().numpy()
-    ap = r.is_ap.cpu().numpy()
-    nb = r.num_bcc.cpu().numpy()
+    outs = []
+    for flags in (0, N.FLAG_SORTED_ROWS | N.tune_flags(cc_priority=True, free_first_round=True, lcc_priority=True)):
+        note(f"batch of 4096: GPU batched solve flags={flags:#x}")
+        r = solve_batched(vb, off, adj, flags=flags)
+        torch.cuda.synchronize()
+        outs.append((r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()))
+        del r
     note("batch of 4096: oracle per graph")
     for i in range(len(u.vbegin) - 1):
         v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
         a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
         olab, oap, onb, _, _ = oracle.ht_bcc(u.offsets[v0 : v1 + 1] - a0, u.adj[a0:a1] - v0)
-        assert int(nb[i]) == onb, f"graph {i}"
-        assert np.array_equal(ap[v0:v1], oap), f"graph {i}"
-        assert np.array_equal(lab[a0:a1], olab), f"graph {i}"
+        for lab, ap, nb in outs:
+            assert int(nb[i]) == onb, f"graph {i}"
+            assert np.array_equal(ap[v0:v1], oap), f"graph {i}"
+            assert np.array_equal(lab[a0:a1], olab), f"graph {i}"
 
 
 @pytest.mark.parametrize("k", [2, 20])
