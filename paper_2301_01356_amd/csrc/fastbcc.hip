@@ -270,14 +270,18 @@ __global__ void k_tile_rows(const int* __restrict__ off, int n, int64_t A, const
 // finds).  fdeg -> scan gives each
 // row's first virtual arc; the non-empty rows are then compacted (row id +
 // start) so the virtual CSR has no empty rows for a wave to walk over.
-__global__ void k_frontier_deg(const int* __restrict__ off, const int* __restrict__ comp,
-                               const int* __restrict__ scal, int slot, int n, int* __restrict__ fdeg,
-                               int* __restrict__ fflag) {
+// Frontier rows: those outside the sampled largest set.  Flattens the
+// parent array on the way (every parent becomes its root), so the pass
+// before it need not.
+__global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int* __restrict__ scal, int slot, int n,
+                               int* __restrict__ fdeg, int* __restrict__ fflag) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int big = scal[slot];
+  const int r = uf_find(comp, v);
+  if (ld_relaxed(comp + v) != r) st_relaxed(comp + v, r);
   const int d = off[v + 1] - off[v];
-  const bool in = d > 0 && comp[v] != big;
+  const bool in = d > 0 && r != big;
   fdeg[v] = in ? d : 0;
   fflag[v] = in ? 1 : 0;
 }
@@ -341,7 +345,7 @@ __global__ void k_root_select(const int* __restrict__ off, const int* __restrict
 }
 
 // Most frequent value of p[] over a stratified sample of vertices (one block).
-__global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(const int* __restrict__ p, int n, int* out) {
+__global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(int* p, int n, int* out) {
   __shared__ int s[MODE_SAMPLES];
   __shared__ int best_len[MODE_SAMPLES / WAVE];
   __shared__ int best_val[MODE_SAMPLES / WAVE];
@@ -353,7 +357,7 @@ __global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(const int* __restric
   h *= 0x2c1b3c6du;
   h ^= h >> 12;
   int64_t v = ((int64_t)i * stride + (int64_t)(h % (uint32_t)stride)) % n;
-  s[i] = p[v];
+  s[i] = uf_find(p, (int)v);  // the sets need not be flattened yet
   __syncthreads();
   // bitonic sort of MODE_SAMPLES values
   for (int k = 2; k <= MODE_SAMPLES; k <<= 1) {
@@ -735,15 +739,26 @@ __global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ 
   roots[rootidx[v]] = rdeg[v] >= 0 ? rsel[v] : v;
 }
 
-// first = last = n - S + (rank among one-vertex trees), S of them in all.
-__global__ void k_lone_tags(const int* __restrict__ lone, int n, int* __restrict__ first, int4* __restrict__ rec) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+// One-vertex trees: first = last = n - S + (rank among them), S of them in
+// all.  Done by the per-vertex pass that starts Tagging.
+__device__ __forceinline__ bool lone_tags(const int* __restrict__ lone, int n, int v, int* __restrict__ first,
+                                          int4* __restrict__ rec) {
   const int k = lone[v];
-  if (lone[v + 1] == k) return;
+  if (lone[v + 1] == k) return false;
   const int f = n - lone[n] + k;
   first[v] = f;
   rec[v] = make_int4(f, f, -1, 0);
+  return true;
+}
+
+// Exact tags: w1/w2 start empty for the sweep's atomics.
+__global__ void k_tag_init(const int* __restrict__ lone, int n, int* __restrict__ first, int4* __restrict__ rec,
+                           int* __restrict__ w1, int* __restrict__ w2) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  lone_tags(lone, n, v, first, rec);
+  w1[v] = INT32_MAX;
+  w2[v] = INT32_MIN;
 }
 
 // List nodes: [0, C) one entry node per root of a tree with edges (root
@@ -1087,10 +1102,17 @@ __global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const
 // it is no longer (then the tags are exact).  Sampled w1 can only be higher
 // and w2 only lower than the exact ones, which is what the certification
 // pass relies on.
-__global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ first,
-                             int n, int ks, int* __restrict__ w1, int* __restrict__ w2) {
+__global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
+                             int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int* __restrict__ w1,
+                             int* __restrict__ w2) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n) return;
+  if (lone_tags(lone, n, x, first, rec)) {  // no neighbour but itself: its tags are its own
+    const int f = first[x];
+    w1[x] = f;
+    w2[x] = f;
+    return;
+  }
   const int f = first[x];
   int mn = f, mx = f;
   const int b = off[x], d = off[x + 1] - b;
@@ -1803,7 +1825,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *foff = I(L.foff), *frank = I(L.frank), *frow = I(L.frow), *fstart = I(L.fstart), *ftile = I(L.ftile);
   int* frows = frank + n;  // number of compacted frontier rows (scan total)
   // frontier virtual CSR of the rows a sweep still has to visit
-  auto frontier = [&](const int* comp, int slot) {
+  auto frontier = [&](int* comp, int slot) {
     LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, foff, frank);
     scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
     scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
@@ -1849,11 +1871,11 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     } else {
       LAUNCH(c, k_cc_sample<false>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
     }
-    // the atomic-free round leaves short chains that the next round's finds
-    // walk anyway; every other round is flattened for the next one
-    if (!free_round || r + 1 == tune.sample_rounds) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+    // flattened for the next round, except after the atomic-free round (its
+    // chains are short and the next round's finds walk them anyway) and
+    // after the last one (the frontier pass flattens)
+    if (!free_round && r + 1 < tune.sample_rounds) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   }
-  if (tune.sample_rounds == 0) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
   frontier(cc, S_BIG_CC);
   if (tune.cc_prio) LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
@@ -1915,7 +1937,6 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *first = I(L.first), *w1 = I(L.w1), *w2 = I(L.w2);
   int4* rec = (int4*)(w + L.rec);
   LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, eid, eu, ev, lone, n, pos, eflag, first, rec, scal + S_STATUS);
-  LAUNCH(c, k_lone_tags, gn, BLOCK, lone, n, first, rec);
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
   int2 *W = (int2*)(w + L.W), *pre = (int2*)(w + L.pre), *suf = (int2*)(w + L.suf), *tab = (int2*)(w + L.tab);
   auto rmq_tables = [&]() {
@@ -1923,8 +1944,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j);
   };
   if (!tune.sampled_tags) {
-    fill_i32(c, w1, INT32_MAX, n);
-    fill_i32(c, w2, INT32_MIN, n);
+    LAUNCH(c, k_tag_init, gn, BLOCK, lone, n, first, rec, w1, w2);
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
     int* order = pos;  // preorder -> vertex; the tour positions are dead now
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
@@ -1937,7 +1957,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     int* order = pos;     // preorder -> vertex; the tour positions are dead now
     int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
     fill_i32(c, cover, 0, (int64_t)n + 2);
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, first, n, tune.tag_samples, w1, w2);
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, w1, w2);
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
     rmq_tables();
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, (const int*)order,
@@ -1960,12 +1980,12 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_lcc_init, gn, BLOCK, lab, n);
   if (tune.lcc_prio) LAUNCH(c, k_lcc_tree<true>, gn, BLOCK, rec, n, lab);
   else LAUNCH(c, k_lcc_tree<false>, gn, BLOCK, rec, n, lab);
-  LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+  // flattened before each sampling round; the frontier pass flattens the last state
   const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
   for (int r = 0; r < lcc_rounds; ++r) {
+    LAUNCH(c, k_compress, gn, BLOCK, lab, n);
     if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gn, BLOCK, off, adj, rec, n, r, lab);
     else LAUNCH(c, k_lcc_sample<false>, gn, BLOCK, off, adj, rec, n, r, lab);
-    LAUNCH(c, k_compress, gn, BLOCK, lab, n);
   }
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
   frontier(lab, S_BIG_LAB);
