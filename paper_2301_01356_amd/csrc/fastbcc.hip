@@ -92,6 +92,7 @@ enum Scalar : int {
   S_LDD_HUGE = 10,  // two slots: long rows listed by a decomposition round
   S_BIG_ROOT = 12,  // Last-CC root of the sampled largest set (priority hooking)
   S_BIG_MIN = 13,   // its smallest member
+  S_HUBS = 14,      // hubs numbered so far
   S_COUNT = 64,
 };
 
@@ -234,10 +235,6 @@ bool decode_flags(uint32_t flags, Tune& t) {
 
 // ------------------------------------------------------------ small kernels
 __global__ void k_fill_i32(int* p, int v, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
@@ -499,13 +496,16 @@ __global__ void k_cc_first_round(const int* __restrict__ off, const int* __restr
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
-  if (e == b) return;
-  const int w1 = adj[b + sample_pos(v, 0, e - b)];
-  const int w2 = adj[b + sample_pos(v, 16, e - b)];
-  const int w = ranks_above<PRIO>(w2, w1) ? w2 : w1;
-  if (w == v || !ranks_above<PRIO>(w, v)) return;
+  int w = v;
+  if (e > b) {
+    const int w1 = adj[b + sample_pos(v, 0, e - b)];
+    const int w2 = adj[b + sample_pos(v, 16, e - b)];
+    w = ranks_above<PRIO>(w2, w1) ? w2 : w1;
+    if (!ranks_above<PRIO>(w, v)) w = v;
+  }
+  // this pass also initialises every set (cc[v] = v, no hook edge)
   cc[v] = w;
-  hu[v] = v;
+  hu[v] = w == v ? -1 : v;
   hv[v] = w;
 }
 
@@ -660,14 +660,18 @@ __global__ void k_ldd_huge(const int* __restrict__ off, const int* __restrict__ 
 // picked by edge number, chained shard after shard.
 __device__ __forceinline__ bool is_hub(const int* __restrict__ off, int x) { return off[x + 1] - off[x] >= HUB_DEG; }
 
-__global__ void k_hub_flags(const int* __restrict__ off, int n, int* __restrict__ hubidx) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) hubidx[v] = is_hub(off, v) ? 1 : 0;
-}
-
-__global__ void k_edge_flags(const int* __restrict__ hu, int n, int* __restrict__ eid) {
+// Per vertex, first pass of Rooting: edge flag for the dense numbering,
+// First-CC's sets flattened, the out-list head cleared, hubs numbered (in any
+// order: the number only picks the hub's counters).
+__global__ void k_edge_flags(const int* __restrict__ off, const int* __restrict__ hu, int n, int* cc,
+                             int* __restrict__ eid, int* __restrict__ headp, int* __restrict__ hubidx, int* scal) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < n) eid[h] = hu[h] >= 0 ? 1 : 0;
+  if (h >= n) return;
+  eid[h] = hu[h] >= 0 ? 1 : 0;
+  const int r = uf_find(cc, h);
+  if (ld_relaxed(cc + h) != r) st_relaxed(cc + h, r);
+  headp[h] = -1;
+  if (is_hub(off, h)) hubidx[h] = atomicAdd(scal + S_HUBS, 1);
 }
 
 __global__ void k_edge_compact(const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ eid,
@@ -695,36 +699,38 @@ __global__ void k_tree_link(const int* __restrict__ off, const int* __restrict__
 
 // Per hub: its first arc (head of the first non-empty shard) into headp, and
 // every shard slot rewritten to the head of the next non-empty shard in
-// cyclic order, stored as -2 - head when that step wraps around.
-__global__ void k_hub_lists(const int* __restrict__ off, const int* __restrict__ hubidx, int n, int* headp,
-                            int* shard) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || !is_hub(off, v)) return;
-  int* sh = shard + (size_t)hubidx[v] * HUB_SHARDS;
-  int head[HUB_SHARDS];
-  int firsts = -1;
-  for (int k = 0; k < HUB_SHARDS; ++k) {
-    head[k] = sh[k];
-    if (firsts < 0 && head[k] >= 0) firsts = k;
-  }
-  headp[v] = firsts >= 0 ? head[firsts] : -1;
-  if (firsts < 0) return;
-  for (int k = 0; k < HUB_SHARDS; ++k) {
-    int j = k + 1;
-    while (j < HUB_SHARDS && head[j] < 0) ++j;
-    sh[k] = j < HUB_SHARDS ? head[j] : -2 - head[firsts];
-  }
-}
-
-// Roots of trees with at least one edge get a list entry node; a one-vertex
-// tree (an isolated vertex, or one with only self-loops) stays out of the
-// Euler tour and takes a preorder number after all others.
-__global__ void k_root_flags(const int* __restrict__ cc, const int* __restrict__ headp, int n,
-                             int* __restrict__ rootidx, int* __restrict__ lone) {
+// cyclic order, stored as -2 - head when that step wraps around.  Then, for
+// every vertex, the root flags: roots of trees with at least one edge get a
+// list entry node; a one-vertex tree (an isolated vertex, or one with only
+// self-loops) stays out of the Euler tour and takes a preorder number after
+// all others.  rdeg is cleared for the root choice.
+__global__ void k_hub_lists(const int* __restrict__ off, const int* __restrict__ hubidx,
+                            const int* __restrict__ cc, int n, int* headp, int* shard, int* __restrict__ rootidx,
+                            int* __restrict__ lone, int* __restrict__ rdeg) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
+  rdeg[v] = -1;
+  int hv = headp[v];
+  if (is_hub(off, v)) {
+    int* sh = shard + (size_t)hubidx[v] * HUB_SHARDS;
+    int head[HUB_SHARDS];
+    int firsts = -1;
+    for (int k = 0; k < HUB_SHARDS; ++k) {
+      head[k] = sh[k];
+      if (firsts < 0 && head[k] >= 0) firsts = k;
+    }
+    hv = firsts >= 0 ? head[firsts] : -1;
+    headp[v] = hv;
+    if (firsts >= 0) {
+      for (int k = 0; k < HUB_SHARDS; ++k) {
+        int j = k + 1;
+        while (j < HUB_SHARDS && head[j] < 0) ++j;
+        sh[k] = j < HUB_SHARDS ? head[j] : -2 - head[firsts];
+      }
+    }
+  }
   const bool root = cc[v] == v;
-  const bool alone = root && headp[v] < 0;
+  const bool alone = root && hv < 0;
   rootidx[v] = root && !alone ? 1 : 0;
   lone[v] = alone ? 1 : 0;
 }
@@ -1104,9 +1110,11 @@ __global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const
 // pass relies on.
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
                              int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int* __restrict__ w1,
-                             int* __restrict__ w2) {
+                             int* __restrict__ w2, int* __restrict__ cover) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < 2) cover[n + x] = 0;  // the certification's difference array (n + 2 slots) starts at zero
   if (x >= n) return;
+  cover[x] = 0;
   if (lone_tags(lone, n, x, first, rec)) {  // no neighbour but itself: its tags are its own
     const int f = first[x];
     w1[x] = f;
@@ -1328,6 +1336,17 @@ __global__ void k_relabel(int* lab, int n, const int* __restrict__ scal, const i
 }
 
 // ------------------------------------------------------------ read-out
+__global__ void k_readout_init(int n, int* __restrict__ head, uint8_t* __restrict__ heads, int* __restrict__ rootlab,
+                               int* __restrict__ minid, uint8_t* __restrict__ ap) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  head[v] = -1;
+  heads[v] = 0;
+  rootlab[v] = -1;
+  minid[v] = INT32_MAX;
+  if (ap) ap[v] = 0;
+}
+
 // head(l[u]) = p(u) when l[u] != l[p(u)] (paper: Algorithm 1, component
 // heads).  A non-root head is an articulation point; a tree root is one iff
 // it heads two different labels.
@@ -1793,12 +1812,6 @@ void fill_i32(Ctx& c, int* p, int v, int64_t count) {
   LAUNCH(c, k_fill_i32, g, BLOCK, p, v, count);
 }
 
-void fill_u8(Ctx& c, uint8_t* p, uint8_t v, int64_t count) {
-  if (count <= 0) return;
-  unsigned g = grid_for(count);
-  if (g > 65536) g = 65536;
-  LAUNCH(c, k_fill_u8, g, BLOCK, p, v, count);
-}
 
 // Exclusive scan in place over max_count ints (count from device if given);
 // the total goes to data[count] when total_out is null, else to *total_out.
@@ -1857,8 +1870,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
       LAUNCH(c, k_ldd_round, gn, BLOCK, off, adj, n, r, T0, 1.0f / beta, cc, rnd, hu, hv, queue, scal);
       LAUNCH(c, k_ldd_huge, LDD_HUGE_GRID, BLOCK, off, adj, r, queue, scal, cc, rnd, hu, hv);
     }
-  } else {
-    LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);
+  } else if (!(tune.first_round_free && tune.sample_rounds > 0)) {
+    LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);  // else the atomic-free round initialises
   }
   // compress after every round: the next round's finds then take one hop
   for (int r = 0; r < tune.sample_rounds; ++r) {
@@ -1880,28 +1893,23 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   frontier(cc, S_BIG_CC);
   if (tune.cc_prio) LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
   else LAUNCH(c, k_cc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
-  LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+  // (Rooting's first pass flattens the sets)
 
   // ---- Rooting
   int *eid = I(L.toff), *eu = I(L.su), *ev = I(L.sv), *headp = I(L.tadj), *nxt = I(L.twin);
   int *rootidx = I(L.rootidx), *roots = I(L.roots), *next = I(L.next), *tmp = I(L.scan_tmp);
   int *hubidx = I(L.hubidx), *shard = I(L.shard);
-  LAUNCH(c, k_edge_flags, gn, BLOCK, hu, n, eid);
+  fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
+  LAUNCH(c, k_edge_flags, gn, BLOCK, off, hu, n, cc, eid, headp, hubidx, scal);
   scan_inplace(c, eid, n, nullptr, tmp, eid + n);
   LAUNCH(c, k_edge_compact, gn, BLOCK, hu, hv, eid, n, eu, ev);
-  fill_i32(c, headp, -1, n);
-  fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
-  LAUNCH(c, k_hub_flags, gn, BLOCK, off, n, hubidx);
-  scan_inplace(c, hubidx, n, nullptr, tmp, hubidx + n);
   const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
   LAUNCH(c, k_tree_link, grid_for(arcs_max), BLOCK, off, hubidx, eid, n, eu, ev, headp, shard, nxt);
-  LAUNCH(c, k_hub_lists, gn, BLOCK, off, hubidx, n, headp, shard);
   int* lone = I(L.frank);  // the frontier ranks are free from here until Tagging's own frontier
-  LAUNCH(c, k_root_flags, gn, BLOCK, cc, headp, n, rootidx, lone);
+  int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
+  LAUNCH(c, k_hub_lists, gn, BLOCK, off, hubidx, cc, n, headp, shard, rootidx, lone, rdeg);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   scan_inplace(c, lone, n, nullptr, tmp, lone + n);
-  int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
-  fill_i32(c, rdeg, -1, n);
   LAUNCH(c, k_root_degree, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg);
   LAUNCH(c, k_root_select, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg, rsel);
   LAUNCH(c, k_root_list, gn, BLOCK, cc, headp, rootidx, rdeg, rsel, scal, n, roots);
@@ -1956,8 +1964,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     // undecided vertices only
     int* order = pos;     // preorder -> vertex; the tour positions are dead now
     int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
-    fill_i32(c, cover, 0, (int64_t)n + 2);
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, w1, w2);
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, w1, w2, cover);
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
     rmq_tables();
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, (const int*)order,
@@ -2005,11 +2012,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   // ---- heads, articulation points, canonical labels
   int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid), *canon = I(L.canon), *bsum = I(L.bsum);
   uint8_t* heads = (uint8_t*)(w + L.heads);
-  fill_i32(c, head, -1, n);
-  fill_u8(c, heads, 0, n);
-  fill_i32(c, rootlab, -1, n);
-  fill_i32(c, minid, INT32_MAX, n);
-  if (out_ap) fill_u8(c, out_ap, 0, n);
+  LAUNCH(c, k_readout_init, gn, BLOCK, n, head, heads, rootlab, minid, out_ap);
   LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, heads, rootlab, out_ap);
   if (out_nbcc) {
     LAUNCH(c, k_bcc_count, gn, BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
