@@ -106,12 +106,13 @@ def cpu_baseline(sample_scale):
     }
 
 
-# Every generated input has ascending rows; the solve is told so (the
-# edge-label read-out then finds reverse arcs by binary search).
+# Every generated input has ascending rows and no self-loops; the solve is
+# told so (the edge-label read-out then finds reverse arcs by binary search
+# and writes labels without re-reading the adjacency).
 def _input_flags():
     from paper_2301_01356_amd import _native as N
 
-    return N.FLAG_SORTED_ROWS
+    return N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
 
 
 INPUT_FLAGS = _input_flags()

@@ -77,6 +77,15 @@ typedef enum fastbcc_status {
                                          of gathering per arc.  Unsorted rows
                                          with this flag give wrong labels (no
                                          access leaves its row). */
+#define FASTBCC_FLAG_NO_SELF_LOOPS 0x4u /* the caller guarantees no arc v->v:
+                                           with FASTBCC_FLAG_SORTED_ROWS the
+                                           edge-label pass then writes labels
+                                           without reading the adjacency (rows
+                                           that need per-arc care still read
+                                           it).  A self-loop with this flag
+                                           gets a BCC label instead of -1;
+                                           with FASTBCC_FLAG_VALIDATE it is
+                                           reported as an invalid graph. */
 /* Tuning fields (0 = built-in default).  They change speed, never results.
  *   bits 8-11  log2 of the list-ranking ruler spacing, 3..10
  *   bits 12-13 union-find sampling rounds before the full sweep, 0..3 (value 3 = none)

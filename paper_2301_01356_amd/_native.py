@@ -22,6 +22,7 @@ ERR_INVALID_GRAPH = 5
 
 FLAG_VALIDATE = 0x1
 FLAG_SORTED_ROWS = 0x2
+FLAG_NO_SELF_LOOPS = 0x4
 TUNE_RULER_SHIFT = 8
 TUNE_SAMPLE_SHIFT = 12
 TUNE_TILE_SHIFT = 14

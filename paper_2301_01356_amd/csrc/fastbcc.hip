@@ -200,7 +200,8 @@ struct Tune {
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
-  const uint32_t known = FASTBCC_FLAG_VALIDATE | FASTBCC_FLAG_SORTED_ROWS | (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
+  const uint32_t known = FASTBCC_FLAG_VALIDATE | FASTBCC_FLAG_SORTED_ROWS | FASTBCC_FLAG_NO_SELF_LOOPS |
+                         (0xFu << FASTBCC_TUNE_RULER_SHIFT) |
                          (0x3u << FASTBCC_TUNE_SAMPLE_SHIFT) | (0x7u << FASTBCC_TUNE_TILE_SHIFT) |
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
                          FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
@@ -421,11 +422,11 @@ __global__ void k_validate_rows(const OffT* __restrict__ off, int n, int64_t A, 
 }
 
 __global__ void k_validate_arcs(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                                const int* __restrict__ tile_row, int tw, int* status) {
+                                const int* __restrict__ tile_row, int tw, bool no_loops, int* status) {
   arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
     if (!ok) return;
     const int y = adj[a];
-    bool bad = (y < 0 || y >= n);
+    bool bad = (y < 0 || y >= n) || (no_loops && y == x);
     if (!bad && a > (int64_t)off[x] && adj[a - 1] > y) bad = true;  // rows sorted
     if (!bad) {
       // x must occur in row y (binary search; rows sorted)
@@ -1667,24 +1668,27 @@ __global__ void k_vertex_canon(const int* __restrict__ canon, int n, int4* __res
 }
 
 // One pass: every arc gets its final label; rows marked exact gather per arc.
+// NOLOOPS (no arc v->v): only exact rows read the adjacency.
+template <bool NOLOOPS>
 __global__ void k_bcc_final(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                             const int* __restrict__ tile_row, int tw, const int4* __restrict__ vlh,
                             const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
                             int* __restrict__ out) {
   const int big = scal[S_LBIG];
   const int4 rbig = vlh[big];
-  arc_windows2(
+  arc_windows2<!NOLOOPS>(
       off, adj, n, A, tile_row, tw,
       [&](int x, int, bool) { return vlh[x]; },
       [&](int64_t a, int x, bool ok, int y, int4 rx) {
         if (!ok) return;
-        if (y == x) {
+        if (!NOLOOPS && y == x) {
           __builtin_nontemporal_store(-1, out + a);
           return;
         }
         // rx = (l[x], head(l[x]), canon(l[x]), exact-row flag)
         int c = rx.z;
         if (rx.w) {
+          if (NOLOOPS) y = adj[a];
           const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
           if (ry.x != rx.x && rx.y != y) c = ry.z;
         }
@@ -1826,7 +1830,7 @@ void scan_inplace(Ctx& c, int* data, int64_t max_count, const int* count_dev, in
 // The solve proper, on int32 offsets.
 fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* off, const int* adj, int G,
                           const int* vbegin, int* out_label, uint8_t* out_ap, int64_t* out_nbcc, char* w,
-                          const Tune& tune, bool validate, bool sorted_rows) {
+                          const Tune& tune, bool validate, bool sorted_rows, bool no_loops) {
   auto I = [&](size_t o) { return (int*)(w + o); };
   int* scal = I(L.scalars);
   const int tw = tune.tile_windows;
@@ -1849,7 +1853,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
 
   if (validate) {
     int h = 0;
-    LAUNCH(c, k_validate_arcs, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, scal + S_STATUS);
+    LAUNCH(c, k_validate_arcs, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, no_loops, scal + S_STATUS);
     if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, c.st) != hipSuccess ||
         hipStreamSynchronize(c.st) != hipSuccess)
       return FASTBCC_ERR_HIP;
@@ -2031,7 +2035,10 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     fill_i32(c, canon, -1, n);
     LAUNCH(c, k_canon_first, gn, BLOCK, off, adj, n, rec, lab, vlh, heads, bigbits, scal, minid, vbegin, G, canon);
     LAUNCH(c, k_vertex_canon, gn, BLOCK, canon, n, vlh);
-    LAUNCH(c, k_bcc_final, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
+    if (no_loops)
+      LAUNCH(c, k_bcc_final<true>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
+    else
+      LAUNCH(c, k_bcc_final<false>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
     LAUNCH(c, k_mirror_write, gn, BLOCK, n, vlh, mpos, mcnt, out_label);
     return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
   }
@@ -2085,6 +2092,7 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
 
   const bool validate = (flags & FASTBCC_FLAG_VALIDATE) != 0;
   const bool sorted_rows = (flags & FASTBCC_FLAG_SORTED_ROWS) != 0;
+  const bool no_loops = (flags & FASTBCC_FLAG_NO_SELF_LOOPS) != 0;
   if (validate) {
     LAUNCH(c, k_validate_rows<OffT>, grid_for(n64 + 1), BLOCK, off, n, A, scal + S_STATUS);
     int h = 0;
@@ -2103,7 +2111,8 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
   } else {
     off32 = (const int*)off;
   }
-  return solve_core(L, c, n, A, off32, adj, G, vbegin, out_label, out_ap, out_nbcc, w, tune, validate, sorted_rows);
+  return solve_core(L, c, n, A, off32, adj, G, vbegin, out_label, out_ap, out_nbcc, w, tune, validate, sorted_rows,
+                    no_loops);
 }
 
 }  // namespace

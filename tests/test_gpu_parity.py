@@ -59,6 +59,7 @@ def test_small_configs(name, off64):
 
 SORTED_FLAGS = [
     N.FLAG_SORTED_ROWS,
+    N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True, lcc_rounds=0),
     N.FLAG_SORTED_ROWS | N.tune_flags(lcc_priority=True, sampled_tags=True),
     N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True),
     N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True, ruler_shift=7, tile_shift=4),
@@ -76,7 +77,7 @@ def test_sorted_row_read_out(name, flags):
     assert_parity(g, gpu_solve(g, flags=flags), f"{name} {flags:#x}")
 
 
-@pytest.mark.parametrize("flags", SORTED_FLAGS[:2])
+@pytest.mark.parametrize("flags", SORTED_FLAGS[:1] + SORTED_FLAGS[2:3])
 def test_sorted_row_read_out_multigraphs(flags):
     """Sorted multigraphs with self-loops: copies of an edge to a head are
     mirrored together."""
@@ -217,6 +218,23 @@ def test_validate_flag():
     assert ei.value.status == N.ERR_INVALID_GRAPH
 
 
+def test_validate_loop_free_promise():
+    """A self-loop is a valid input, but not under the loop-free flag: with
+    validation on, breaking that promise is reported as an invalid graph."""
+    loopy = gen.multigraph_csr(4, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 3)])
+    note("validate self-loop without the loop-free flag")
+    assert_parity(loopy, gpu_solve(loopy, flags=N.FLAG_VALIDATE | N.FLAG_SORTED_ROWS), "self-loop")
+    note("validate self-loop with the loop-free flag")
+    off, adj = to_dev(loopy)
+    with pytest.raises(N.FastBccError) as ei:
+        solve(off, adj, flags=N.FLAG_VALIDATE | N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS)
+    assert ei.value.status == N.ERR_INVALID_GRAPH
+    g = gen.config("rmat_small")
+    note("validate loop-free rmat_small with the loop-free flag")
+    flags = N.FLAG_VALIDATE | N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
+    assert_parity(g, gpu_solve(g, flags=flags), "validated loop-free")
+
+
 @pytest.mark.parametrize("name", ["plain", "grid"])
 def test_full_size_configs(name):
     note(f"full {name}")
@@ -355,6 +373,8 @@ HUB_FLAGS = [
     N.FLAG_SORTED_ROWS | N.tune_flags(ldd=2, sample_rounds=0),
     N.FLAG_SORTED_ROWS | N.tune_flags(lcc_priority=True, free_first_round=True, lcc_rounds=0),
     N.FLAG_SORTED_ROWS | N.tune_flags(free_first_round=True, cc_priority=True, sampled_tags=True, tile_shift=5),
+    N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True),
+    N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS,
 ]
 
 
