@@ -77,6 +77,7 @@ constexpr int DEF_SAMPLE_ROUNDS = 2;
 constexpr int MIN_TILE_ARCS = 256;  // workspace is sized for this tile size
 constexpr int DEF_TILE_SHIFT = 2;   // 4 windows of 64 arcs
 constexpr int MAX_TILE_SHIFT = 6;
+constexpr int ROWS_TILE_WINDOWS = 64;  // windows per wave in the row-wise label fill
 constexpr int HUB_DEG = 4096;    // graph degree from which tree-degree counters are sharded
 constexpr int HUB_SHARDS = 32;   // counters per hub (power of two, <= 32: 5 bits of a slot)
 
@@ -1668,32 +1669,145 @@ __global__ void k_vertex_canon(const int* __restrict__ canon, int n, int4* __res
 }
 
 // One pass: every arc gets its final label; rows marked exact gather per arc.
-// NOLOOPS (no arc v->v): only exact rows read the adjacency.
-template <bool NOLOOPS>
 __global__ void k_bcc_final(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                             const int* __restrict__ tile_row, int tw, const int4* __restrict__ vlh,
                             const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
                             int* __restrict__ out) {
   const int big = scal[S_LBIG];
   const int4 rbig = vlh[big];
-  arc_windows2<!NOLOOPS>(
+  arc_windows2(
       off, adj, n, A, tile_row, tw,
       [&](int x, int, bool) { return vlh[x]; },
       [&](int64_t a, int x, bool ok, int y, int4 rx) {
         if (!ok) return;
-        if (!NOLOOPS && y == x) {
+        if (y == x) {
           __builtin_nontemporal_store(-1, out + a);
           return;
         }
         // rx = (l[x], head(l[x]), canon(l[x]), exact-row flag)
         int c = rx.z;
         if (rx.w) {
-          if (NOLOOPS) y = adj[a];
           const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
           if (ry.x != rx.x && rx.y != y) c = ry.z;
         }
         __builtin_nontemporal_store(c, out + a);
       });
+}
+
+// Number of the 64 row ends held in `e` (ascending over the lanes) that are
+// <= a: a binary search over the lanes.
+__device__ __forceinline__ int block_count(int e, int a) {
+  int pos = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1)
+    if (__shfl(e, pos + step - 1, WAVE) <= a) pos += step;
+  if (pos == WAVE - 1 && __builtin_amdgcn_readlane(e, WAVE - 1) <= a) pos = WAVE;
+  return pos;
+}
+
+// The same pass for inputs without self-loops (sorted rows): only exact rows
+// read their targets; every other arc takes its row's label, so the pass is
+// a row-wise fill.  A wave walks its tile's 64-arc windows holding a block of
+// 64 consecutive rows in registers, per lane the end of one row and that
+// row's label with the exact-row flag in bit 31.  Most arcs lie in windows
+// inside one row (high-degree rows hold most arcs): such a window costs one
+// compare.  The few row ends inside other windows are counted from a ballot,
+// lane by lane.  Loads happen only when the walk leaves the block (the block
+// then restarts at the window's first row), for exact rows, and for windows
+// spanning more than 64 rows; waits for them also wait for the stores in
+// flight, so the windows between them run without any wait.
+__global__ void k_bcc_rows(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                           const int* __restrict__ tile_row, int tw, int stride, const int4* __restrict__ vlh,
+                           const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
+                           int* __restrict__ out) {
+  const int lane = lane_id();
+  const int64_t wave =
+      __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE));
+  const int64_t tile_arcs = (int64_t)WAVE * tw * stride;
+  const int64_t tbeg = wave * tile_arcs;
+  if (tbeg >= A) return;
+  const int64_t tend = tbeg + tile_arcs < A ? tbeg + tile_arcs : A;
+  const int4 rbig = vlh[scal[S_LBIG]];
+  auto pack = [](int4 q) { return (q.z & 0x7fffffff) | (q.w ? (int)0x80000000 : 0); };
+  // Every load below is used on its own path before paths join, so no load
+  // is in flight where a window begins: the compiler waits only on paths
+  // that load (a wait for a load also waits for the stores in flight).
+  int rb = tile_row[wave * stride];  // the row holding arc tbeg
+  int e = 0, p = 0;                  // rows rb .. rb+63 (rows past n end at A)
+  bool stale = true;                 // the block must be loaded at rb
+  auto block = [&]() {
+    const int v = rb + lane;
+    e = off[v < n ? v + 1 : n];
+    p = pack(vlh[v < n ? v : n - 1]);
+  };
+  for (int64_t base = tbeg; base < tend; base += WAVE) {
+    const int64_t a64 = base + lane;
+    const bool ok = a64 < tend;
+    const int a = (int)(ok ? a64 : tend - 1);
+    const int b = (int)base;
+    const int wend = (int)(base + WAVE < tend ? base + WAVE : tend);
+    unsigned long long live = __ballot(e > b);  // rows of the block ending after b
+    if (stale) {
+      block();
+      live = __ballot(e > b);
+      stale = false;
+    }
+    if (live == 0 || __builtin_amdgcn_readlane(e, WAVE - 1) < wend) {
+      // restart the block at the row holding arc b
+      while (live == 0) {
+        rb += WAVE;
+        block();
+        live = __ballot(e > b);
+      }
+      rb += __builtin_ctzll(live);
+      block();
+      live = __ballot(e > b);
+    }
+    const int rp = __builtin_ctzll(live);  // block row holding arc b
+    int pos, q, x;
+    if (__builtin_amdgcn_readlane(e, rp) >= wend) {  // one row holds the whole window
+      q = __builtin_amdgcn_readlane(p, rp);
+      x = rb + rp;
+    } else {
+      const unsigned long long m = __ballot(e < wend) & (~0ull << rp);  // row ends inside
+      if (__builtin_popcountll(m) > 8) {
+        pos = block_count(e, a);
+      } else {
+        pos = rp;
+        for (unsigned long long k = m; k; k &= k - 1)
+          pos += a >= __builtin_amdgcn_readlane(e, __builtin_ctzll(k)) ? 1 : 0;
+      }
+      q = __shfl(p, pos & (WAVE - 1), WAVE);
+      x = rb + pos;
+      if (m >> (WAVE - 1)) {
+        // more than 64 rows in the window: the rest from the offsets, then
+        // the block restarts at the row of the window's last arc
+        bool far = pos >= WAVE;  // every lane, so the last lane's row is known
+        for (int lo = rb + WAVE; __any(far) && lo < n; lo += WAVE) {
+          const int ev = off[lo + 1 + lane < n ? lo + 1 + lane : n];
+          const int k = block_count(ev, a);
+          if (far && k < WAVE) {
+            x = lo + k;
+            q = pack(vlh[x]);
+            far = false;
+          }
+        }
+        rb = __builtin_amdgcn_readlane(x, WAVE - 1);
+        stale = true;
+      }
+    }
+    int c = q & 0x7fffffff;
+    if (__any(ok && q < 0)) {
+      if (ok && q < 0) {
+        // exact row: rx = (l[x], head(l[x]), canon(l[x]), 1)
+        const int4 rx = vlh[x];
+        const int y = adj[a];
+        const int4 ry = ((bits[y / WAVE] >> (y % WAVE)) & 1ull) ? rbig : vlh[y];
+        if (ry.x != rx.x && rx.y != y) c = ry.z;
+      }
+    }
+    if (ok) __builtin_nontemporal_store(c, out + a64);
+  }
 }
 
 // The arcs h->y of the mirror search get y's BCC.
@@ -2035,10 +2149,13 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     fill_i32(c, canon, -1, n);
     LAUNCH(c, k_canon_first, gn, BLOCK, off, adj, n, rec, lab, vlh, heads, bigbits, scal, minid, vbegin, G, canon);
     LAUNCH(c, k_vertex_canon, gn, BLOCK, canon, n, vlh);
-    if (no_loops)
-      LAUNCH(c, k_bcc_final<true>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
-    else
-      LAUNCH(c, k_bcc_final<false>, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
+    if (no_loops) {
+      const int stride = tw >= ROWS_TILE_WINDOWS ? 1 : ROWS_TILE_WINDOWS / tw;
+      const unsigned rows_grid = (unsigned)cdiv(cdiv(ntiles, stride) * WAVE, BLOCK);
+      LAUNCH(c, k_bcc_rows, rows_grid, BLOCK, off, adj, n, A, tile_row, tw, stride, vlh, bigbits, scal, out_label);
+    } else {
+      LAUNCH(c, k_bcc_final, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
+    }
     LAUNCH(c, k_mirror_write, gn, BLOCK, n, vlh, mpos, mcnt, out_label);
     return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
   }

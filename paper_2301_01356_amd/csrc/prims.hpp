@@ -386,9 +386,8 @@ __device__ __forceinline__ int window_row(const int* __restrict__ off, int n, in
 // count, so every load here is unconditional (out-of-range lanes read a
 // clamped address and ignore the value) and the loop is unrolled twice with
 // one register set per parity: no branch and no register copy of a value in
-// flight forces a wait for all loads.  body(a, x, ok, y, fetched).  Without
-// TARGETS the adjacency is not read (y = -1 everywhere).
-template <bool TARGETS = true, typename Fetch, typename Body>
+// flight forces a wait for all loads.  body(a, x, ok, y, fetched).
+template <typename Fetch, typename Body>
 __device__ __forceinline__ void arc_windows2(const int* __restrict__ off, const int* __restrict__ adj, int n,
                                              int64_t A, const int* __restrict__ tile_row, int tile_windows,
                                              Fetch&& fetch, Body&& body) {
@@ -403,7 +402,7 @@ __device__ __forceinline__ void arc_windows2(const int* __restrict__ off, const 
     return off[idx < n ? idx : n];
   };
   auto target = [&](int64_t a) {
-    return TARGETS ? __builtin_nontemporal_load(adj + (a < tend ? a : tend - 1)) : -1;
+    return __builtin_nontemporal_load(adj + (a < tend ? a : tend - 1));
   };
   using F = decltype(fetch(0, 0, false));
   int row = tile_row[wave];

@@ -26,13 +26,15 @@ def test_rmat25_full_size_exact():
     adj = torch.from_numpy(g.adj).to(DEV)
     outs = []
     # the defaults, the variants, and the configurations the autotuner picks for
-    # this graph in the benchmark (sorted rows, certified tags, free first round,
-    # no Last-CC sampling rounds)
+    # this graph in the benchmark (sorted loop-free rows, certified tags, free
+    # first round, no Last-CC sampling rounds)
     for flags in (0, N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True), N.tune_flags(ldd=1),
                   N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True),
-                  N.FLAG_SORTED_ROWS | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, sampled_tags=True,
-                                                    tag_samples=4, free_first_round=True, lcc_rounds=0),
-                  N.FLAG_SORTED_ROWS | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True,
+                  N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
+                  | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, sampled_tags=True, tag_samples=3,
+                                 free_first_round=True, lcc_rounds=0),
+                  N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
+                  | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True,
                                                     sampled_tags=True, tag_samples=3, free_first_round=True,
                                                     lcc_priority=True)):
         note(f"R-MAT scale 25: GPU solve flags={flags:#x}")
@@ -58,7 +60,8 @@ def test_batch4096_full_size_exact():
     off = torch.from_numpy(u.offsets32()).to(DEV)
     adj = torch.from_numpy(u.adj).to(DEV)
     outs = []
-    for flags in (0, N.FLAG_SORTED_ROWS | N.tune_flags(cc_priority=True, free_first_round=True, lcc_priority=True)):
+    for flags in (0, N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
+                  | N.tune_flags(cc_priority=True, free_first_round=True, lcc_priority=True)):
         note(f"batch of 4096: GPU batched solve flags={flags:#x}")
         r = solve_batched(vb, off, adj, flags=flags)
         torch.cuda.synchronize()

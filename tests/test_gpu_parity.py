@@ -96,6 +96,43 @@ def test_sorted_row_read_out_multigraphs(flags):
         assert_parity(g, gpu_solve(g, flags=flags), f"sorted multigraph {t}")
 
 
+def sparse_rows_graph(seed, n, isolated, hubs):
+    """Loop-free graph whose rows are mostly empty or short, with runs of
+    more than 64 empty rows and a few hubs: 64-arc windows then span from
+    one row to well over 64 rows."""
+    rng = np.random.default_rng(seed)
+    live = np.flatnonzero(rng.random(n) >= isolated)
+    live = live[(live < n // 3) | (live > n // 3 + 300)]  # a run of empty rows
+    edges = []
+    for i in range(0, len(live) - 1, 2):  # a matching: rows of degree 1
+        edges.append((int(live[i]), int(live[i + 1])))
+    for i in range(0, len(live) - 2, 7):  # short paths and triangles
+        edges.append((int(live[i]), int(live[i + 2])))
+    for h in live[rng.choice(len(live), size=hubs, replace=False)]:
+        for v in rng.choice(live, size=min(len(live), 700), replace=False):
+            if int(v) != int(h):
+                edges.append((int(h), int(v)))
+    return gen.from_edges(n, edges)
+
+
+ROW_FILL_FLAGS = [
+    N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(tile_shift=t)
+    for t in (2, 4, 6)
+] + [N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True)]
+
+
+@pytest.mark.parametrize("flags", ROW_FILL_FLAGS)
+@pytest.mark.parametrize("shape", [(1, 3000, 0.9, 0), (2, 20000, 0.6, 3), (3, 50000, 0.97, 2), (4, 777, 0.0, 1)])
+def test_loop_free_row_fill(flags, shape):
+    """The row-wise label fill for loop-free sorted rows: windows inside one
+    row, windows over a few rows, windows over more than 64 rows and runs of
+    empty rows between windows, at several tile sizes."""
+    seed, n, isolated, hubs = shape
+    g = sparse_rows_graph(seed, n, isolated, hubs)
+    note(f"sparse rows seed={seed} n={n} arcs={g.num_arcs} flags={flags:#x}")
+    assert_parity(g, gpu_solve(g, flags=flags), f"sparse rows {shape} {flags:#x}")
+
+
 def cycle(n):
     return [(i, (i + 1) % n) for i in range(n)]
 
