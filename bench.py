@@ -56,6 +56,9 @@ def alg_bytes(kernel, n, A):
         "k_bcc_label": 4 * (n + 1) + 8 * A + 16 * n,
         # one-pass final labels (sorted rows): the same stream and records
         "k_bcc_final": 4 * (n + 1) + 8 * A + 16 * n,
+        # row-wise label fill (sorted loop-free rows): offsets + label write per
+        # arc + (label, exact flag) of every row; exact rows' gathers left out
+        "k_bcc_rows": 4 * (n + 1) + 4 * A + 8 * n,
         # label read + label write per arc (canonical-label lookups hit the few hot labels)
         "k_bcc_remap4": 8 * A,
     }

@@ -73,6 +73,8 @@ constexpr int MODE_SAMPLES = 1024;
 constexpr int MIN_RULER_SHIFT = 3;
 constexpr int MAX_RULER_SHIFT = 10;
 constexpr int DEF_RULER_SHIFT = 5;
+constexpr int LR2_SHIFT = 4;             // second ruling level: every 16th ruler
+constexpr int LR2_MIN_RULERS = 1 << 16;  // below this, pointer jumping over all rulers
 constexpr int DEF_SAMPLE_ROUNDS = 2;
 constexpr int MIN_TILE_ARCS = 256;  // workspace is sized for this tile size
 constexpr int DEF_TILE_SHIFT = 2;   // 4 windows of 64 arcs
@@ -107,12 +109,14 @@ inline int ilog2_floor(int64_t x) {
 // ------------------------------------------------------------ workspace
 struct Layout {
   size_t total = 0;
-  size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, rlen, rnext, rval0,
+  size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, ol2, rnext2, rlen2, rlen,
+      rnext, rval0,
       rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W, pre, suf, tab, rec, lab, head,
       rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, hubidx, shard, bigbits, dbits, tile_row, scan_tmp;
   int64_t nb = 0;      // rmq blocks of 64
   int levels = 0;      // sparse-table levels
   int64_t rmax = 0;    // ruler capacity
+  int64_t rmax2 = 0;   // second-level ruler capacity
   int64_t tiles = 0;   // tile capacity
   int64_t scan_blocks = 0;
   int64_t hubs = 0;    // hub capacity (sharded tree-degree counters)
@@ -131,6 +135,7 @@ Layout make_layout(int64_t n, int64_t A) {
   L.nb = cdiv(n > 0 ? n : 1, 64);
   L.levels = ilog2_floor(L.nb) + 1;
   L.rmax = cdiv(n2, int64_t(1) << MIN_RULER_SHIFT) + 1;
+  L.rmax2 = cdiv(L.rmax, int64_t(1) << LR2_SHIFT) + 1;
   L.tiles = cdiv(A > 0 ? A : 1, MIN_TILE_ARCS) + 1;
   L.scan_blocks = cdiv(n2, SCAN_TILE) + 1;
   const size_t I = sizeof(int);
@@ -154,6 +159,9 @@ Layout make_layout(int64_t n, int64_t A) {
   L.rval1 = take(c, L.rmax * I);
   L.rnx0 = take(c, L.rmax * I);
   L.rnx1 = take(c, L.rmax * I);
+  L.ol2 = take(c, L.rmax * 2 * I);
+  L.rnext2 = take(c, L.rmax2 * I);
+  L.rlen2 = take(c, L.rmax2 * I);
   L.pos = take(c, n2 * I);
   L.eflag = take(c, n2 * I);
   L.first = take(c, n * I);
@@ -844,6 +852,54 @@ __global__ void k_lr_walk(const int* __restrict__ next, const int* __restrict__ 
   }
   rnext[r] = nr;
   rlen[r] = cnt;
+}
+
+// Second level of the ruling set, over the rulers' own list (weighted by
+// segment lengths): every 2^shift2-th ruler walks it to the next such ruler,
+// recording for each ruler it passes the weight before it.  Pointer jumping
+// then runs over 2^shift2 times fewer elements.
+__global__ void k_lr_walk2(const int* __restrict__ rootidx, const int* __restrict__ eid, int n, int shift,
+                           int shift2, const int* __restrict__ rnext, const int* __restrict__ rlen,
+                           int2* __restrict__ ol2, int* __restrict__ rnext2, int* __restrict__ rlen2) {
+  const int NL = node_count(rootidx, eid, n);
+  const int R = (NL + (1 << shift) - 1) >> shift;
+  const int R2 = (R + (1 << shift2) - 1) >> shift2;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= R2) return;
+  const int mask = (1 << shift2) - 1;
+  int r = q << shift2, acc = 0, nq = -1;
+  for (int steps = 0; steps < R; ++steps) {
+    ol2[r] = make_int2(q, acc);
+    acc += rlen[r];
+    const int j = rnext[r];
+    if (j < 0) break;
+    if ((j & mask) == 0) {
+      nq = j >> shift2;
+      break;
+    }
+    r = j;
+  }
+  rnext2[q] = nq;
+  rlen2[q] = acc;
+}
+
+// Rulers' suffix sums from the second level's: suf[r] = suf2[q] - (weight
+// between q's first ruler and r).  Written over rlen.
+__global__ void k_lr_suf(const int* __restrict__ rootidx, const int* __restrict__ eid, int n, int shift,
+                         int shift2, const int2* __restrict__ ol2, const int* __restrict__ suf2,
+                         int* __restrict__ suf, int* status) {
+  const int NL = node_count(rootidx, eid, n);
+  const int R = (NL + (1 << shift) - 1) >> shift;
+  const int R2 = (R + (1 << shift2) - 1) >> shift2;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int2 o = ol2[r];
+  if (o.x < 0 || o.x >= R2) {  // a ruler no second-level walk passed: the tour is broken
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
+    suf[r] = 0;
+    return;
+  }
+  suf[r] = suf2[o.x] - o.y;
 }
 
 // One pointer-jumping round over rulers: suffix sums of segment lengths.
@@ -2041,19 +2097,34 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int2* ol = (int2*)(w + L.ol);
   int *rlen = I(L.rlen), *rnext = I(L.rnext);
   LAUNCH(c, k_lr_walk, grid_for(rmax), BLOCK, next, rootidx, eid, n, sh, ol, rnext, rlen);
-  const int* vin = rlen;
-  const int* nin = rnext;
   int* bufv[2] = {I(L.rval0), I(L.rval1)};
   int* bufn[2] = {I(L.rnx0), I(L.rnx1)};
-  const int rounds = ilog2_floor(rmax) + 1;  // 2^rounds > ruler count
-  for (int k = 0; k < rounds; ++k) {
-    LAUNCH(c, k_lr_jump, grid_for(rmax), BLOCK, rootidx, eid, n, sh, vin, nin, bufv[k & 1], bufn[k & 1]);
-    vin = bufv[k & 1];
-    nin = bufn[k & 1];
+  auto jump = [&](const int* vin, const int* nin, int shift, int64_t count) {  // suffix sums
+    const int rounds = ilog2_floor(count) + 1;  // 2^rounds > ruler count
+    for (int k = 0; k < rounds; ++k) {
+      LAUNCH(c, k_lr_jump, grid_for(count), BLOCK, rootidx, eid, n, shift, vin, nin, bufv[k & 1], bufn[k & 1]);
+      vin = bufv[k & 1];
+      nin = bufn[k & 1];
+    }
+    return vin;
+  };
+  const int* rsuf;  // suffix sums of the rulers' segment lengths
+  if (rmax >= LR2_MIN_RULERS) {
+    // a second ruling level over the rulers, then pointer jumping over its rulers
+    const int sh2 = LR2_SHIFT;
+    const int64_t rmax2 = cdiv(rmax, int64_t(1) << sh2);
+    int2* ol2 = (int2*)(w + L.ol2);
+    int *rnext2 = I(L.rnext2), *rlen2 = I(L.rlen2);
+    LAUNCH(c, k_lr_walk2, grid_for(rmax2), BLOCK, rootidx, eid, n, sh, sh2, rnext, rlen, ol2, rnext2, rlen2);
+    const int* suf2 = jump(rlen2, rnext2, sh + sh2, rmax2);
+    LAUNCH(c, k_lr_suf, grid_for(rmax), BLOCK, rootidx, eid, n, sh, sh2, ol2, suf2, rlen, scal + S_STATUS);
+    rsuf = rlen;
+  } else {
+    rsuf = jump(rlen, rnext, sh, rmax);
   }
   int* pos = I(L.pos);
   int* eflag = I(L.eflag);
-  LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, eid, n, sh, ol, vin, pos, scal + S_STATUS);
+  LAUNCH(c, k_lr_pos, gnode, BLOCK, rootidx, eid, n, sh, ol, rsuf, pos, scal + S_STATUS);
   LAUNCH(c, k_enter_flags, gnode, BLOCK, rootidx, eid, n, pos, eflag, scal + S_STATUS);
   int* nl_dev = scal + S_NODES;  // number of list nodes, for the scan of entry flags
   LAUNCH(c, k_node_count, 1, 1, rootidx, eid, n, nl_dev);

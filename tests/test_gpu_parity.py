@@ -168,6 +168,23 @@ def test_open_grid_and_long_path():
     assert_parity(g, gpu_solve(g), "grid+path")
 
 
+@pytest.mark.parametrize("ruler_shift", [3, 4])
+@pytest.mark.parametrize("what", ["rmat19", "path", "forest"])
+def test_two_level_list_ranking(what, ruler_shift):
+    """Euler tours long enough for the second ruling level (at least 2^16
+    rulers): a power-law graph, one long path, and many path trees."""
+    if what == "rmat19":
+        g = gen.rmat(seed=7, scale=19, edge_factor=4)
+    elif what == "path":
+        g = gen.from_edges(600_000, path(600_000))
+    else:
+        edges = [(i, i + 1) for i in range(700_000) if i % 997 != 996]
+        g = gen.from_edges(700_001, edges)
+    flags = N.tune_flags(ruler_shift=ruler_shift)
+    note(f"two-level list ranking {what} n={g.n} arcs={g.num_arcs} flags={flags:#x}")
+    assert_parity(g, gpu_solve(g, flags=flags), f"{what} ruler {ruler_shift}")
+
+
 def test_multigraph_self_loops_unsorted_rows():
     rng = np.random.default_rng(3)
     for t in range(60):
