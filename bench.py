@@ -394,6 +394,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--no-systems", action="store_true", help="skip the batched and serving legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
@@ -484,6 +485,39 @@ def main():
     num_bcc = int(out.num_bcc.item())
     log(f"[bench] {args.steps} steps: {ms:.3f} ms/step, {A / ms / 1e6:.2f} G arcs/s, #BCC={num_bcc}")
 
+    # the same solve captured once into a HIP graph (the solve enqueues
+    # kernels only) and replayed K times: the launch gaps between its kernels
+    # go away; the labels must equal the eager ones
+    ms_graph = None
+    if not args.no_graph:
+        ref_label = out.edge_label.clone()
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        with torch.cuda.stream(gs):
+            hg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(hg, stream=gs):
+                solve(off, adj, out=out, workspace=ws, flags=args.flags, stream=gs)
+            for _ in range(args.warmup):
+                hg.replay()
+            out.edge_label.fill_(-7)
+            hg.replay()
+        gs.synchronize()
+        if not torch.equal(out.edge_label, ref_label) or int(out.num_bcc.item()) != num_bcc:
+            raise SystemExit("[bench] graph replay disagrees with the eager solve")
+        del ref_label
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(gs):
+            g0.record(gs)
+            for _ in range(args.steps):
+                hg.replay()
+            g1.record(gs)
+        gs.synchronize()
+        ms_graph = g0.elapsed_time(g1) / args.steps
+        log(f"[bench] {args.steps} graph replays: {ms_graph:.3f} ms/step, {A / ms_graph / 1e6:.2f} G arcs/s")
+        stream.wait_stream(gs)
+        torch.cuda.synchronize()
+
     # per-kernel durations: the same K steps with an event pair per launch
     tr = N.Trace(max_launches=256 * args.steps + 256)
     for _ in range(args.steps):
@@ -493,7 +527,7 @@ def main():
     rows = sorted(tot.items(), key=lambda kv: -kv[1][0])
     traced_ms = sum(v[0] for v in tot.values()) / args.steps
     log(f"[bench] traced: kernel time per step {traced_ms:.3f} ms")
-    for name, (t, cnt) in rows[:25]:
+    for name, (t, cnt) in rows:
         log(f"  {t / args.steps:9.3f} ms/step  {cnt // args.steps:4d} launches/step  {name}")
     dom_name, (dom_ms, dom_cnt) = rows[0]
     roofline = None
@@ -550,7 +584,9 @@ def main():
         "data": "synthetic",
         "config": {**cfg, "arcs": A, "vertices": n, "num_bcc": num_bcc, "flags": args.flags, "tuned": tuned,
                    "edge_convention": "directed arcs (paper Table 1 m)",
-                   "undirected_edges_per_s": value / 2, "parallelism": "single GPU"},
+                   "undirected_edges_per_s": value / 2, "parallelism": "single GPU",
+                   "hip_graph_ms_per_step": ms_graph,
+                   "hip_graph_edges_per_s": A / (ms_graph * 1e-3) if ms_graph else None},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

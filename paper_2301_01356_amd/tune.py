@@ -26,7 +26,7 @@ from . import _native as N
 
 DEFAULT_CACHE = os.environ.get("FASTBCC_TUNE_CACHE", os.path.expanduser("~/.cache/fastbcc_tune.json"))
 
-RULER = (4, 5, 6, 7, 8)
+RULER = (3, 4, 5, 6, 7)
 SAMPLE = (0, 1, 2)
 TILE = (2, 3, 4, 5)
 UF = (0, 1)  # First-CC union-find: 0 = min-id hooking, 1 = hashed-priority hooking
@@ -36,7 +36,7 @@ TAG_SAMPLES = (4, 2, 3, 6)  # sampled neighbours per vertex when certifying
 FREE = (0, 1)  # First-CC's first sampling round without atomics
 LCC = (0, 1)  # Last-CC hooking: 0 = by id, 1 = by hashed priority + relabelling
 LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)
-START = {"ruler": 5, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1}
+START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1}
 
 
 def skew_class(degrees: np.ndarray) -> str:
