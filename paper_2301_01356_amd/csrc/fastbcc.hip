@@ -321,17 +321,41 @@ __device__ __forceinline__ int root_sample(int i, int n) {
   return (int)(((int64_t)i * n) / ROOT_SAMPLES);
 }
 
-__global__ void k_root_degree(const int* __restrict__ off, const int* __restrict__ cc, int n, int* rdeg) {
+// Largest sampled degree per component.  Samples without edges are skipped
+// (their trees have no tour).  Most samples fall in one component, whose
+// counter would serialise one atomic per wave: each block first folds the
+// samples of its first sampled component in LDS, then the rest reduce runs of
+// equal components per wave.  Launched with ROOT_BLOCK threads per block.
+constexpr int ROOT_BLOCK = 1024;
+__global__ void __launch_bounds__(ROOT_BLOCK) k_root_degree(const int* __restrict__ off, const int* __restrict__ cc,
+                                                          int n, int* rdeg) {
+  __shared__ int first_t, key, kmax;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int c = -1, d = -1;
   if (i < ROOT_SAMPLES) {
     const int v = root_sample(i, n);
     if (i == 0 || v != root_sample(i - 1, n)) {  // n < ROOT_SAMPLES: each vertex once
-      c = cc[v];
       d = off[v + 1] - off[v];
+      if (d > 0) c = cc[v];
     }
   }
-  // runs of equal components within the wave reduce to one atomic
+  if (threadIdx.x == 0) {
+    first_t = INT32_MAX;
+    key = -1;
+    kmax = -1;
+  }
+  __syncthreads();
+  if (c >= 0) atomicMin(&first_t, (int)threadIdx.x);
+  __syncthreads();
+  if ((int)threadIdx.x == first_t) key = c;
+  __syncthreads();
+  if (c >= 0 && c == key) {
+    atomicMax(&kmax, d);
+    c = -1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && key >= 0) atomicMax(rdeg + key, kmax);
+  // the other components: runs of equal components within the wave, one atomic each
   const int lane = lane_id();
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
@@ -345,10 +369,15 @@ __global__ void k_root_degree(const int* __restrict__ off, const int* __restrict
 __global__ void k_root_select(const int* __restrict__ off, const int* __restrict__ cc, int n,
                               const int* __restrict__ rdeg, int* __restrict__ rsel) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ROOT_SAMPLES) return;
-  const int v = root_sample(i, n);
-  const int c = cc[v];
-  if (off[v + 1] - off[v] == rdeg[c]) rsel[c] = v;  // any sampled vertex of largest degree
+  int v = -1, c = -1;
+  if (i < ROOT_SAMPLES) {
+    v = root_sample(i, n);
+    c = cc[v];
+    if (off[v + 1] - off[v] != rdeg[c]) c = -1;  // not of largest degree
+  }
+  // any sampled vertex of largest degree: one store per run of equal components in the wave
+  const int cn = __shfl_down(c, 1, WAVE);
+  if (c >= 0 && (lane_id() == WAVE - 1 || cn != c)) rsel[c] = v;
 }
 
 // Most frequent value of p[] over a stratified sample of vertices (one block).
@@ -1167,40 +1196,43 @@ __global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const
 // and w2 only lower than the exact ones, which is what the certification
 // pass relies on.
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
-                             int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int* __restrict__ w1,
-                             int* __restrict__ w2, int* __restrict__ cover) {
+                             int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int2* __restrict__ W,
+                             int* __restrict__ order, int* __restrict__ cover, int* status) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x < 2) cover[n + x] = 0;  // the certification's difference array (n + 2 slots) starts at zero
   if (x >= n) return;
   cover[x] = 0;
+  int f, mn, mx;
   if (lone_tags(lone, n, x, first, rec)) {  // no neighbour but itself: its tags are its own
-    const int f = first[x];
-    w1[x] = f;
-    w2[x] = f;
+    f = mn = mx = first[x];
+  } else {
+    f = mn = mx = first[x];
+    const int b = off[x], d = off[x + 1] - b;
+    if (d <= ks) {
+      for (int k = 0; k < d; ++k) {
+        const int y = adj[b + k];
+        if (y == x) continue;
+        const int fy = first[y];
+        mn = fy < mn ? fy : mn;
+        mx = fy > mx ? fy : mx;
+      }
+    } else {
+      for (int k = 0; k < ks; ++k) {
+        const int y = adj[b + sample_pos(x, k, d)];
+        if (y == x) continue;
+        const int fy = first[y];
+        mn = fy < mn ? fy : mn;
+        mx = fy > mx ? fy : mx;
+      }
+    }
+  }
+  if (f < 0 || f >= n) {  // preorder numbers must be a permutation of [0, n)
+    atomicExch(status, (int)FASTBCC_ERR_HIP);
     return;
   }
-  const int f = first[x];
-  int mn = f, mx = f;
-  const int b = off[x], d = off[x + 1] - b;
-  if (d <= ks) {
-    for (int k = 0; k < d; ++k) {
-      const int y = adj[b + k];
-      if (y == x) continue;
-      const int fy = first[y];
-      mn = fy < mn ? fy : mn;
-      mx = fy > mx ? fy : mx;
-    }
-  } else {
-    for (int k = 0; k < ks; ++k) {
-      const int y = adj[b + sample_pos(x, k, d)];
-      if (y == x) continue;
-      const int fy = first[y];
-      mn = fy < mn ? fy : mn;
-      mx = fy > mx ? fy : mx;
-    }
-  }
-  w1[x] = mn;
-  w2[x] = mx;
+  // straight into the RMQ input, by preorder slot
+  W[f] = make_int2(mn, mx);
+  order[f] = x;
 }
 
 // Slot i of the preorder: the row order[i] needs exact tags when an undecided
@@ -1225,7 +1257,7 @@ __global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__
 // Exact w1/w2 for the listed rows (all their arcs), then their preorder slots.
 __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                             const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                            int tw, const int* __restrict__ first, int* __restrict__ w1, int* __restrict__ w2) {
+                            int tw, const int* __restrict__ first, int2* __restrict__ W) {
   const int R = *frows;
   const int64_t F = fstart[R];
   arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
@@ -1250,21 +1282,12 @@ __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__
     }
     const int knext = __shfl_down(key, 1, WAVE);
     const bool tail = (lane == WAVE - 1) || knext != key;
-    if (tail && key >= 0 && mn != INT32_MAX) {
-      atomicMin(w1 + x, mn);
-      atomicMax(w2 + x, mx);
+    if (tail && key >= 0 && mn != INT32_MAX) {  // onto the sampled tags, in place
+      int* wx = (int*)(W + first[x]);
+      atomicMin(wx, mn);
+      atomicMax(wx + 1, mx);
     }
   });
-}
-
-__global__ void k_rmq_rescatter(const int* __restrict__ frow, const int* __restrict__ frows,
-                                const int* __restrict__ first, const int* __restrict__ w1,
-                                const int* __restrict__ w2, int2* __restrict__ W) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= *frows) return;
-  const int x = frow[r], f = first[x];
-  const int a = w1[x], b = w2[x];
-  W[f] = make_int2(a < f ? a : f, b > f ? b : f);
 }
 
 // ------------------------------------------------------------ Last-CC
@@ -2084,7 +2107,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_hub_lists, gn, BLOCK, off, hubidx, cc, n, headp, shard, rootidx, lone, rdeg);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   scan_inplace(c, lone, n, nullptr, tmp, lone + n);
-  LAUNCH(c, k_root_degree, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg);
+  LAUNCH(c, k_root_degree, grid_for(ROOT_SAMPLES, ROOT_BLOCK), ROOT_BLOCK, off, cc, n, rdeg);
   LAUNCH(c, k_root_select, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg, rsel);
   LAUNCH(c, k_root_list, gn, BLOCK, cc, headp, rootidx, rdeg, rsel, scal, n, roots);
   const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
@@ -2153,8 +2176,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     // undecided vertices only
     int* order = pos;     // preorder -> vertex; the tour positions are dead now
     int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, w1, w2, cover);
-    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, order, cover,
+           scal + S_STATUS);
     rmq_tables();
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, (const int*)order,
            cover, scal + S_STATUS);
@@ -2164,8 +2187,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     scan_inplace(c, frank, n, nullptr, tmp, frows);
     LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, order, frow, fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
-    LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, w1, w2);
-    LAUNCH(c, k_rmq_rescatter, gn, BLOCK, frow, frows, first, w1, w2, W);
+    LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, W);
     rmq_tables();
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, (const int*)nullptr,
            (int*)nullptr, scal + S_STATUS);
