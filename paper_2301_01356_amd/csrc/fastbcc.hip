@@ -1291,10 +1291,6 @@ __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__
 }
 
 // ------------------------------------------------------------ Last-CC
-__global__ void k_lcc_init(int* __restrict__ lab, int n) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) lab[v] = v;
-}
 
 // Last-CC hooks by id (a set's root is its smallest member, which the
 // read-out relies on) or, as a tuning variant, by hashed priority (shallower
@@ -1307,13 +1303,25 @@ __device__ __forceinline__ void lcc_link(int* lab, int u, int v) {
   else uf_link(lab, u, v);
 }
 
-// Plain (non-fence) tree edges are skeleton edges.
+// Plain (non-fence) tree edges are skeleton edges.  First without atomics,
+// from all-singleton sets: v points to its parent when the parent ranks
+// above it (the hooking rule's order, so the pointers are acyclic and every
+// set's root is still the member the rule would leave on top); this pass also
+// initialises every set.  Then the other plain tree edges by union-find.
+template <bool PRIO>
+__global__ void k_lcc_tree_free(const int4* __restrict__ rec, int n, int* __restrict__ lab) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int4 r = rec[v];
+  lab[v] = (r.z >= 0 && r.w == 0 && ranks_above<PRIO>(r.z, v)) ? r.z : v;
+}
+
 template <bool PRIO>
 __global__ void k_lcc_tree(const int4* __restrict__ rec, int n, int* lab) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int4 r = rec[v];
-  if (r.z >= 0 && r.w == 0) lcc_link<PRIO>(lab, v, r.z);
+  if (r.z >= 0 && r.w == 0 && !ranks_above<PRIO>(r.z, v)) lcc_link<PRIO>(lab, v, r.z);
 }
 
 // Non-tree arc x-y is a skeleton edge iff neither endpoint is an ancestor of
@@ -2195,9 +2203,13 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
 
   // ---- Last-CC on the implicit skeleton
   int* lab = I(L.lab);
-  LAUNCH(c, k_lcc_init, gn, BLOCK, lab, n);
-  if (tune.lcc_prio) LAUNCH(c, k_lcc_tree<true>, gn, BLOCK, rec, n, lab);
-  else LAUNCH(c, k_lcc_tree<false>, gn, BLOCK, rec, n, lab);
+  if (tune.lcc_prio) {
+    LAUNCH(c, k_lcc_tree_free<true>, gn, BLOCK, rec, n, lab);
+    LAUNCH(c, k_lcc_tree<true>, gn, BLOCK, rec, n, lab);
+  } else {
+    LAUNCH(c, k_lcc_tree_free<false>, gn, BLOCK, rec, n, lab);
+    LAUNCH(c, k_lcc_tree<false>, gn, BLOCK, rec, n, lab);
+  }
   // flattened before each sampling round; the frontier pass flattens the last state
   const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
   for (int r = 0; r < lcc_rounds; ++r) {
