@@ -100,7 +100,7 @@ typedef enum fastbcc_status {
  *              computed on a subset of the edges) and exact tags are swept
  *              only for the subtrees still undecided
  *   bits 21-22 sampled neighbours per vertex in that mode: 0 = 4, 1 = 2,
- *              2 = 3, 3 = 6
+ *              2 = 3, 3 = 1
  *   bit  23    First-CC's first sampling round links each vertex to its
  *              sample only when the sample ranks above it, without atomics
  *   bit  24    Last-CC hooks by hashed priority, then relabels every set to

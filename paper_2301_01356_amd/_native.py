@@ -30,7 +30,7 @@ TUNE_CC_PRIORITY = 0x20000
 TUNE_LDD_SHIFT = 18
 TUNE_SAMPLED_TAGS = 0x100000
 TUNE_TAG_SAMPLES_SHIFT = 21
-TAG_SAMPLE_CODES = {4: 0, 2: 1, 3: 2, 6: 3}
+TAG_SAMPLE_CODES = {4: 0, 2: 1, 3: 2, 1: 3}
 TUNE_FREE_FIRST_ROUND = 0x800000
 TUNE_LCC_PRIORITY = 0x1000000
 TUNE_LCC_ROUNDS_SHIFT = 25
@@ -131,7 +131,7 @@ def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc
                free_first_round: bool = False, lcc_priority: bool = False, lcc_rounds=None) -> int:
     """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
     the low-diameter decomposition before First-CC's union-find, beta = 2^-k;
-    ``sampled_tags`` certifies fences from ``tag_samples`` (2, 3, 4 or 6)
+    ``sampled_tags`` certifies fences from ``tag_samples`` (1, 2, 3 or 4)
     sampled neighbours per vertex first."""
     f = TUNE_CC_PRIORITY if cc_priority else 0
     f |= TUNE_SAMPLED_TAGS if sampled_tags else 0

@@ -223,7 +223,7 @@ bool decode_flags(uint32_t flags, Tune& t) {
   t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
   t.lcc_prio = (flags & FASTBCC_TUNE_LCC_PRIORITY) != 0;
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
-  static const int kSamples[4] = {4, 2, 3, 6};
+  static const int kSamples[4] = {4, 2, 3, 1};
   t.tag_samples = kSamples[(flags >> FASTBCC_TUNE_TAG_SAMPLES_SHIFT) & 0x3];
   t.cc_prio = (flags & FASTBCC_TUNE_CC_PRIORITY) != 0;
   t.ldd = (int)((flags >> FASTBCC_TUNE_LDD_SHIFT) & 0x3);
@@ -1217,8 +1217,11 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
         mx = fy > mx ? fy : mx;
       }
     } else {
+      // ks consecutive arcs from a hashed start: one adjacency line instead
+      // of ks (any subset of the row keeps the sampled tags sound)
+      const int s0 = b + sample_pos(x, 0, d - ks + 1);
       for (int k = 0; k < ks; ++k) {
-        const int y = adj[b + sample_pos(x, k, d)];
+        const int y = adj[s0 + k];
         if (y == x) continue;
         const int fy = first[y];
         mn = fy < mn ? fy : mn;

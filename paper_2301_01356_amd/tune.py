@@ -32,7 +32,7 @@ TILE = (2, 3, 4, 5)
 UF = (0, 1)  # First-CC union-find: 0 = min-id hooking, 1 = hashed-priority hooking
 LDD = (0, 1, 2)  # First-CC low-diameter decomposition first: 0 = off, k = beta 2^-k
 TAGS = (0, 1)  # 0 = exact tag sweep over every arc, 1 = sampled-tag certification
-TAG_SAMPLES = (4, 2, 3, 6)  # sampled neighbours per vertex when certifying
+TAG_SAMPLES = (4, 3, 2, 1)  # sampled neighbours per vertex when certifying
 FREE = (0, 1)  # First-CC's first sampling round without atomics
 LCC = (0, 1)  # Last-CC hooking: 0 = by id, 1 = by hashed priority + relabelling
 LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)

@@ -31,7 +31,7 @@ def test_rmat25_full_size_exact():
     for flags in (0, N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True), N.tune_flags(ldd=1),
                   N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True),
                   N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
-                  | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, sampled_tags=True, tag_samples=3,
+                  | N.tune_flags(ruler_shift=4, sample_rounds=2, tile_shift=4, sampled_tags=True, tag_samples=2,
                                  free_first_round=True, lcc_rounds=0),
                   N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
                   | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True,

@@ -209,7 +209,7 @@ def test_multigraph_self_loops_unsorted_rows():
     N.tune_flags(ldd=1), N.tune_flags(ldd=3, sample_rounds=0), N.tune_flags(ldd=2, cc_priority=True),
     N.tune_flags(sampled_tags=True), N.tune_flags(sampled_tags=True, cc_priority=True, tile_shift=3),
     N.tune_flags(sampled_tags=True, ldd=1, sample_rounds=0),
-    N.tune_flags(sampled_tags=True, tag_samples=2), N.tune_flags(sampled_tags=True, tag_samples=6),
+    N.tune_flags(sampled_tags=True, tag_samples=2), N.tune_flags(sampled_tags=True, tag_samples=1),
     N.tune_flags(free_first_round=True), N.tune_flags(free_first_round=True, cc_priority=True, sample_rounds=1),
     N.tune_flags(lcc_priority=True), N.tune_flags(lcc_priority=True, sampled_tags=True, sample_rounds=0),
     N.tune_flags(lcc_rounds=0), N.tune_flags(lcc_rounds=1, lcc_priority=True, sampled_tags=True),
@@ -428,6 +428,7 @@ HUB_FLAGS = [
     N.FLAG_SORTED_ROWS | N.tune_flags(lcc_priority=True, free_first_round=True, lcc_rounds=0),
     N.FLAG_SORTED_ROWS | N.tune_flags(free_first_round=True, cc_priority=True, sampled_tags=True, tile_shift=5),
     N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True),
+    N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, tag_samples=1),
     N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS,
 ]
 
