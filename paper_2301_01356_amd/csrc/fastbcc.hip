@@ -1806,10 +1806,12 @@ __device__ __forceinline__ int block_count(int e, int a) {
 // then restarts at the window's first row), for exact rows, and for windows
 // spanning more than 64 rows; waits for them also wait for the stores in
 // flight, so the windows between them run without any wait.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 __global__ void k_bcc_rows(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
                            const int* __restrict__ tile_row, int tw, int stride, const int4* __restrict__ vlh,
                            const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
-                           int* __restrict__ out) {
+                           bool out16, int* __restrict__ out) {
   const int lane = lane_id();
   const int64_t wave =
       __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE));
@@ -1854,6 +1856,17 @@ __global__ void k_bcc_rows(const int* __restrict__ off, const int* __restrict__ 
       live = __ballot(e > b);
     }
     const int rp = __builtin_ctzll(live);  // block row holding arc b
+    // four windows inside one row that is not exact: a 16-byte store per lane
+    // (out16: the labels are 16-byte aligned; windows start at multiples of 64)
+    if (out16 && base + 4 * WAVE <= tend && (int64_t)__builtin_amdgcn_readlane(e, rp) >= base + 4 * WAVE) {
+      const int q4 = __builtin_amdgcn_readlane(p, rp);
+      if (q4 >= 0) {
+        const v4i c4 = {q4, q4, q4, q4};
+        __builtin_nontemporal_store(c4, reinterpret_cast<v4i*>(out + base) + lane);
+        base += 3 * WAVE;  // and the loop's own step
+        continue;
+      }
+    }
     int pos, q, x;
     if (__builtin_amdgcn_readlane(e, rp) >= wend) {  // one row holds the whole window
       q = __builtin_amdgcn_readlane(p, rp);
@@ -2260,7 +2273,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     if (no_loops) {
       const int stride = tw >= ROWS_TILE_WINDOWS ? 1 : ROWS_TILE_WINDOWS / tw;
       const unsigned rows_grid = (unsigned)cdiv(cdiv(ntiles, stride) * WAVE, BLOCK);
-      LAUNCH(c, k_bcc_rows, rows_grid, BLOCK, off, adj, n, A, tile_row, tw, stride, vlh, bigbits, scal, out_label);
+      const bool out16 = ((uintptr_t)out_label & 15) == 0;
+      LAUNCH(c, k_bcc_rows, rows_grid, BLOCK, off, adj, n, A, tile_row, tw, stride, vlh, bigbits, scal, out16,
+             out_label);
     } else {
       LAUNCH(c, k_bcc_final, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
     }

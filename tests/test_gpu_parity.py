@@ -12,6 +12,7 @@ import torch
 import oracle
 from paper_2301_01356_amd import _native as N
 from paper_2301_01356_amd import gen, solve, solve_batched
+from paper_2301_01356_amd.api import BccResult
 
 pytestmark = pytest.mark.gpu
 
@@ -131,6 +132,27 @@ def test_loop_free_row_fill(flags, shape):
     g = sparse_rows_graph(seed, n, isolated, hubs)
     note(f"sparse rows seed={seed} n={n} arcs={g.num_arcs} flags={flags:#x}")
     assert_parity(g, gpu_solve(g, flags=flags), f"sparse rows {shape} {flags:#x}")
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2, 3])
+def test_loop_free_row_fill_label_alignment(shift):
+    """The fill stores four labels at once where the label buffer is 16-byte
+    aligned; a buffer at 4, 8 or 12 bytes past that takes the one-label
+    stores.  Both give the oracle's labels."""
+    g = gen.config("rmat_small")
+    off, adj = to_dev(g)
+    A, n = g.num_arcs, g.n
+    buf = torch.full((A + 4,), -9, dtype=torch.int32, device=DEV)
+    out = BccResult(buf[shift : shift + A], torch.empty(n, dtype=torch.uint8, device=DEV),
+                    torch.empty(1, dtype=torch.int64, device=DEV))
+    note(f"rmat_small label buffer offset {4 * shift} bytes")
+    flags = N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True)
+    solve(off, adj, out=out, flags=flags)
+    torch.cuda.synchronize()
+    got = (out.edge_label.cpu().numpy(), out.is_ap.cpu().numpy(), int(out.num_bcc.item()))
+    assert_parity(g, got, f"label offset {shift}")
+    rest = torch.cat([buf[:shift], buf[shift + A :]]).cpu().numpy()
+    assert np.all(rest == -9), "the solve wrote outside the label buffer"
 
 
 def cycle(n):
