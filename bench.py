@@ -45,8 +45,9 @@ def workload_graph(name):
 # Algorithmic bytes per launch: each array touched the minimal number of
 # times the kernel's definition needs, 4 bytes per gathered word (no cache
 # lines).  Offsets are read as int32 inside the solve (int64 input offsets are
-# narrowed once).  A = arcs, n = vertices.
-def alg_bytes(kernel, n, A):
+# narrowed once).  A = arcs, n = vertices, deg = row lengths, flags = the
+# solve's flags (for the tag sample count).
+def alg_bytes(kernel, n, A, deg=None, flags=0):
     models = {
         # offsets + adjacency + first[y] per arc + (first, last) of the row vertex
         # + w1/w2 read-modify-write per row + one descendant bit per arc
@@ -62,6 +63,22 @@ def alg_bytes(kernel, n, A):
         # label read + label write per arc (canonical-label lookups hit the few hot labels)
         "k_bcc_remap4": 8 * A,
     }
+    if deg is not None:
+        import numpy as np
+
+        from paper_2301_01356_amd import _native as N
+
+        codes = {c: k for k, c in N.TAG_SAMPLE_CODES.items()}
+        ks = codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3]
+        live = int((deg > 0).sum())
+        # sampled tags: per vertex its one-vertex-tree rank, first[x], offsets,
+        # the cleared difference-array slot, the (min, max) pair and the
+        # preorder map written by slot; per sampled arc the target and its first[]
+        models["k_tag_sample"] = 28 * n + 8 * int(np.minimum(deg, ks).sum())
+        # one union-find sampling round: offsets per vertex; per vertex with
+        # arcs the sampled target, both sets' parents and the hooking write
+        # (finds longer than one hop left out: a lower bound)
+        models["k_cc_sample"] = 4 * (n + 1) + 16 * live
     return models.get(kernel)
 
 
@@ -439,6 +456,7 @@ def main():
     off = torch.from_numpy(g.offsets if off64 else g.offsets32()).to(dev)
     adj = torch.from_numpy(g.adj).to(dev)
     n, A = g.n, g.num_arcs
+    deg = (g.offsets[1:] - g.offsets[:-1]).astype("int64")  # row lengths, for the byte models
     ws = alloc_workspace(n, A, 1, dev)
     out = BccResult(
         torch.empty(A, dtype=torch.int32, device=dev),
@@ -530,9 +548,9 @@ def main():
     for name, (t, cnt) in rows:
         log(f"  {t / args.steps:9.3f} ms/step  {cnt // args.steps:4d} launches/step  {name}")
     dom_name, (dom_ms, dom_cnt) = rows[0]
-    roofline = None
+    modelled = []
     for name, (t, cnt) in rows:
-        b = alg_bytes(name, n, A)
+        b = alg_bytes(name, n, A, deg, args.flags)
         if b is None:
             continue
         avg_ms = t / cnt
@@ -543,7 +561,7 @@ def main():
             f = COUNTERS["copy_factor"]
             traffic = (c["fetch_kib"] * f["fetch"] + c["write_kib"] * f["write"]) * 1024
             traffic_raw = (c["fetch_kib"] + c["write_kib"]) * 1024
-        roofline = {
+        modelled.append({
             "kernel": name,
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -556,8 +574,8 @@ def main():
             "alg_bytes_per_launch": int(b),
             "avg_launch_ms": round(avg_ms, 4),
             "share_of_step": round((t / args.steps) / ms, 3),
-        }
-        break
+        })
+    roofline = modelled[0] if modelled else None
     if roofline and roofline["kernel"] != dom_name:
         roofline["note"] = f"slowest kernel {dom_name} has no byte model; reported the slowest modelled one"
 
@@ -588,6 +606,7 @@ def main():
                    "hip_graph_ms_per_step": ms_graph,
                    "hip_graph_edges_per_s": A / (ms_graph * 1e-3) if ms_graph else None},
         "roofline": roofline,
+        "rooflines_next": modelled[1:3],
         "cpu_baseline": cpu,
     }
     if not args.no_systems and args.workload == "rmat":
