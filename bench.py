@@ -72,8 +72,8 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
         ks = codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3]
         live = int((deg > 0).sum())
         # sampled tags: per vertex its one-vertex-tree rank, first[x], offsets,
-        # the cleared difference-array slot, the (min, max) pair and the
-        # preorder map written by slot; per sampled arc the target and its first[]
+        # the cleared difference-array slot and the (min, max, vertex) record
+        # written by preorder slot; per sampled arc the target and its first[]
         models["k_tag_sample"] = 28 * n + 8 * int(np.minimum(deg, ks).sum())
         # one union-find sampling round: offsets per vertex; per vertex with
         # arcs the sampled target, both sets' parents and the hooking write

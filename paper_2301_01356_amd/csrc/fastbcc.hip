@@ -167,7 +167,7 @@ Layout make_layout(int64_t n, int64_t A) {
   L.first = take(c, n * I);
   L.w1 = take(c, n * I);
   L.w2 = take(c, n * I);
-  L.W = take(c, n * 2 * I);
+  L.W = take(c, n * 4 * I);
   L.pre = take(c, n * 2 * I);
   L.suf = take(c, n * 2 * I);
   L.tab = take(c, (size_t)L.levels * L.nb * 2 * I);
@@ -295,7 +295,8 @@ __global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int
 
 // Slot v of the flag/degree arrays stands for row map[v] (row v without a map).
 __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __restrict__ frank, int n,
-                                   const int* __restrict__ map, int* __restrict__ frow, int* __restrict__ fstart) {
+                                   const int* __restrict__ map, int map_stride, int* __restrict__ frow,
+                                   int* __restrict__ fstart) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v > n) return;
   if (v == n) {
@@ -304,7 +305,7 @@ __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __re
   }
   const int r = frank[v];
   if (frank[v + 1] != r) {
-    frow[r] = map ? map[v] : v;
+    frow[r] = map ? map[(int64_t)v * map_stride] : v;
     fstart[r] = foff[v];
   }
 }
@@ -1070,10 +1071,11 @@ __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__
       });
 }
 
-// Per preorder slot f: (min, max) of the tags, one 8-byte pair so a range
-// query gathers both at once.
+// Per preorder slot f: (min, max) of the tags and the vertex at that slot,
+// one 16-byte record, so a range query gathers both tags at once and the
+// preorder map costs no second line.
 __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restrict__ w1, const int* __restrict__ w2,
-                              int n, int2* __restrict__ W, int* __restrict__ order, int* status) {
+                              int n, int4* __restrict__ W, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int f = first[v];
@@ -1082,8 +1084,7 @@ __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restri
     return;
   }
   int a = w1[v], b = w2[v];
-  W[f] = make_int2(a < f ? a : f, b > f ? b : f);
-  if (order) order[f] = v;
+  W[f] = make_int4(a < f ? a : f, b > f ? b : f, v, 0);
 }
 
 __device__ __forceinline__ int2 mm(int2 p, int2 q) {
@@ -1092,12 +1093,13 @@ __device__ __forceinline__ int2 mm(int2 p, int2 q) {
 
 // In-block prefix/suffix (min, max) (block = 64 consecutive preorder slots
 // = one wave), block (min, max) into sparse-table level 0.
-__global__ void k_rmq_block(const int2* __restrict__ W, int n, int64_t nb, int2* __restrict__ pre,
+__global__ void k_rmq_block(const int4* __restrict__ W, int n, int64_t nb, int2* __restrict__ pre,
                             int2* __restrict__ suf, int2* __restrict__ tab) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = lane_id();
   const bool in = i < n;
-  const int2 w = in ? W[i] : make_int2(INT32_MAX, INT32_MIN);
+  const int4 w4 = in ? W[i] : make_int4(INT32_MAX, INT32_MIN, 0, 0);
+  const int2 w = make_int2(w4.x, w4.y);
   int2 p = w, q = w;
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
@@ -1136,15 +1138,15 @@ __global__ void k_rmq_level(int2* __restrict__ tab, int64_t nb, int j) {
 //   QUERY_RECHECK  exact test for the undecided vertices only.
 enum QueryMode : int { QUERY_EXACT = 0, QUERY_CERTIFY = 1, QUERY_RECHECK = 2 };
 
-//   Thread t handles vertex order[t] (the vertex at preorder slot t), or
-//   vertex t without an order: in preorder the range reads of neighbouring
-//   threads fall on neighbouring slots, since most subtrees are small.
-__global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const int2* __restrict__ pre,
+//   Thread t handles the vertex at preorder slot t (by_slot), or vertex t:
+//   in preorder the range reads of neighbouring threads fall on neighbouring
+//   slots, since most subtrees are small.
+__global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const int2* __restrict__ pre,
                             const int2* __restrict__ suf, const int2* __restrict__ tab, int4* rec, int mode,
-                            const int* __restrict__ order, int* __restrict__ cover, int* status) {
+                            bool by_slot, int* __restrict__ cover, int* status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const int v = order ? order[t] : t;
+  const int v = by_slot ? W[t].z : t;
   if (v < 0 || v >= n) {  // only if first[] was no permutation (already reported)
     atomicExch(status, (int)FASTBCC_ERR_HIP);
     return;
@@ -1167,8 +1169,8 @@ __global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const
   const int bl = l / WAVE, br = r / WAVE;
   int2 m;
   if (bl == br) {
-    m = W[l];
-    for (int k = l + 1; k <= r; ++k) m = mm(m, W[k]);
+    m = make_int2(W[l].x, W[l].y);
+    for (int k = l + 1; k <= r; ++k) m = mm(m, make_int2(W[k].x, W[k].y));
   } else {
     m = mm(suf[l], pre[r]);
     const int len = br - bl - 1;
@@ -1196,8 +1198,8 @@ __global__ void k_rmq_query(int n, int64_t nb, const int2* __restrict__ W, const
 // and w2 only lower than the exact ones, which is what the certification
 // pass relies on.
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
-                             int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int2* __restrict__ W,
-                             int* __restrict__ order, int* __restrict__ cover, int* status) {
+                             int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int4* __restrict__ W,
+                             int* __restrict__ cover, int* status) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x < 2) cover[n + x] = 0;  // the certification's difference array (n + 2 slots) starts at zero
   if (x >= n) return;
@@ -1233,15 +1235,14 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
     atomicExch(status, (int)FASTBCC_ERR_HIP);
     return;
   }
-  // straight into the RMQ input, by preorder slot
-  W[f] = make_int2(mn, mx);
-  order[f] = x;
+  // straight into the RMQ input, by preorder slot, with the vertex
+  W[f] = make_int4(mn, mx, x, 0);
 }
 
-// Slot i of the preorder: the row order[i] needs exact tags when an undecided
+// Slot i of the preorder: its vertex's row needs exact tags when an undecided
 // interval covers i (cover = exclusive scan of the difference array, so the
 // count at i is cover[i + 1]) and its tags were sampled.
-__global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__ order,
+__global__ void k_dirty_deg(const int* __restrict__ off, const int4* __restrict__ W,
                             const int* __restrict__ cover, int n, int ks, int* __restrict__ fdeg,
                             int* __restrict__ fflag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1249,9 +1250,11 @@ __global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__
   bool in = false;
   int d = 0;
   if (cover[i + 1] > 0) {
-    const int x = order[i];
-    d = off[x + 1] - off[x];
-    in = d > ks;
+    const int x = W[i].z;
+    if (x >= 0 && x < n) {  // else first[] was no permutation (already reported)
+      d = off[x + 1] - off[x];
+      in = d > ks;
+    }
   }
   fdeg[i] = in ? d : 0;
   fflag[i] = in ? 1 : 0;
@@ -1260,7 +1263,7 @@ __global__ void k_dirty_deg(const int* __restrict__ off, const int* __restrict__
 // Exact w1/w2 for the listed rows (all their arcs), then their preorder slots.
 __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                             const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                            int tw, const int* __restrict__ first, int2* __restrict__ W) {
+                            int tw, const int* __restrict__ first, int4* __restrict__ W) {
   const int R = *frows;
   const int64_t F = fstart[R];
   arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
@@ -2063,7 +2066,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, foff, frank);
     scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
     scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
-    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)nullptr, frow,
+    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)nullptr, 1, frow,
            fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
   };
@@ -2182,7 +2185,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int4* rec = (int4*)(w + L.rec);
   LAUNCH(c, k_tags, gnode, BLOCK, rootidx, roots, eid, eu, ev, lone, n, pos, eflag, first, rec, scal + S_STATUS);
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
-  int2 *W = (int2*)(w + L.W), *pre = (int2*)(w + L.pre), *suf = (int2*)(w + L.suf), *tab = (int2*)(w + L.tab);
+  int4* W = (int4*)(w + L.W);
+  int2 *pre = (int2*)(w + L.pre), *suf = (int2*)(w + L.suf), *tab = (int2*)(w + L.tab);
   auto rmq_tables = [&]() {
     LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W, n, L.nb, pre, suf, tab);
     for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j);
@@ -2190,31 +2194,30 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   if (!tune.sampled_tags) {
     LAUNCH(c, k_tag_init, gn, BLOCK, lone, n, first, rec, w1, w2);
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
-    int* order = pos;  // preorder -> vertex; the tour positions are dead now
-    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, order, scal + S_STATUS);
+    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, scal + S_STATUS);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, (const int*)order,
-           (int*)nullptr, scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, true, (int*)nullptr,
+           scal + S_STATUS);
   } else {
     // sampled tags certify most non-fences; exact tags for the subtrees of the
     // undecided vertices only
-    int* order = pos;     // preorder -> vertex; the tour positions are dead now
-    int* cover = eflag;   // difference array over preorder slots (2n + 1 >= n + 2 ints)
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, order, cover,
-           scal + S_STATUS);
+    int* cover = eflag;  // difference array over preorder slots (2n + 1 >= n + 2 ints)
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, cover, scal + S_STATUS);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, (const int*)order,
-           cover, scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, true, cover,
+           scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
-    LAUNCH(c, k_dirty_deg, gn, BLOCK, off, order, cover, n, tune.tag_samples, foff, frank);
+    LAUNCH(c, k_dirty_deg, gn, BLOCK, off, W, cover, n, tune.tag_samples, foff, frank);
     scan_inplace(c, foff, n, nullptr, tmp, foff + n);
     scan_inplace(c, frank, n, nullptr, tmp, frows);
-    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, order, frow, fstart);
+    // the preorder map: the vertex field of the RMQ records
+    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)W + 2, 4, frow,
+           fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
     LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, W);
     rmq_tables();
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, (const int*)nullptr,
-           (int*)nullptr, scal + S_STATUS);
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, false, (int*)nullptr,
+           scal + S_STATUS);
   }
 
   // ---- Last-CC on the implicit skeleton
