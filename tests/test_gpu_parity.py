@@ -252,16 +252,21 @@ def test_repeated_solves_identical():
         assert np.array_equal(first[0], again[0]) and np.array_equal(first[1], again[1]) and first[2] == again[2]
 
 
-def test_batched_equals_each_graph_alone():
+BATCH_FLAGS = [0, N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True,
+                                                                          ruler_shift=3)]
+
+
+@pytest.mark.parametrize("flags", BATCH_FLAGS)
+def test_batched_equals_each_graph_alone(flags):
     rng = np.random.default_rng(9)
     graphs = [gen.mixed(41, i, 8, 3000, 4.0, 16.0) for i in range(40)]
     graphs.append(gen.Csr(3, np.zeros(4, np.int64), np.zeros(0, np.int32)))  # an edgeless graph
     graphs.insert(5, gen.from_edges(4, cycle(4)))
     u = gen.unite(graphs)
-    note(f"batched {len(graphs)} graphs n={u.n} arcs={u.num_arcs}")
+    note(f"batched {len(graphs)} graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
     vb = torch.from_numpy(u.vbegin).to(DEV)
     off, adj = to_dev(u)
-    r = solve_batched(vb, off, adj)
+    r = solve_batched(vb, off, adj, flags=flags)
     torch.cuda.synchronize()
     lab = r.edge_label.cpu().numpy()
     ap = r.is_ap.cpu().numpy()
@@ -462,7 +467,7 @@ def test_hubs_above_every_degree_threshold(flags):
     assert_parity(g, gpu_solve(g, flags=flags), f"hub graph {flags:#x}")
 
 
-@pytest.mark.parametrize("flags", HUB_FLAGS[:3])
+@pytest.mark.parametrize("flags", HUB_FLAGS[:3] + HUB_FLAGS[-2:])
 def test_hub_graphs_batched(flags):
     graphs = [hub_graph(21), gen.from_edges(5, cycle(5)), hub_graph(22)]
     u = gen.unite(graphs)
