@@ -87,17 +87,17 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources they were taken on (hash below); otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "8db5b5d318c502be",
+    "src_sha": "10f7757ecdab1a48",
     "workload": "rmat25",
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378527.1, "write_kib": 4090685.2},
-    "k_tag_sample": {"fetch_kib": 2577367.0, "write_kib": 1924777.6},
-    "k_cc_sample": {"fetch_kib": 2372063.3, "write_kib": 658624.3},
-    "k_lr_walk": {"fetch_kib": 1250942.6, "write_kib": 1075887.6},
-    "k_rmq_query": {"fetch_kib": 1137676.2, "write_kib": 188887.8},
-    "k_tree_link": {"fetch_kib": 1246782.2, "write_kib": 829673.4},
-    "k_mirror_find": {"fetch_kib": 2068529.9, "write_kib": 312075.5},
-    "k_lcc_tree": {"fetch_kib": 710133.6, "write_kib": 217790.4},
+    "k_bcc_rows": {"fetch_kib": 378547.2, "write_kib": 4090670.6},
+    "k_tag_sample": {"fetch_kib": 2449361.5, "write_kib": 1445481.0},
+    "k_cc_sample": {"fetch_kib": 2373556.9, "write_kib": 659220.0},
+    "k_lr_walk": {"fetch_kib": 1248949.3, "write_kib": 1076298.5},
+    "k_rmq_query": {"fetch_kib": 1215778.3, "write_kib": 189133.7},
+    "k_tree_link": {"fetch_kib": 1246569.4, "write_kib": 829731.3},
+    "k_mirror_find": {"fetch_kib": 2068510.4, "write_kib": 312075.5},
+    "k_lcc_tree": {"fetch_kib": 709180.1, "write_kib": 219844.2},
 }
 
 
