@@ -1193,10 +1193,10 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
 }
 
 // ------------------------------------------------------------ sampled tags
-// Tags from a sample of each row: ks hashed neighbours, or the whole row when
-// it is no longer (then the tags are exact).  Sampled w1 can only be higher
-// and w2 only lower than the exact ones, which is what the certification
-// pass relies on.
+// Tags from a sample of each row: ks consecutive neighbours from a hashed
+// start, or the whole row when it is no longer (then the tags are exact).
+// Sampled w1 can only be higher and w2 only lower than the exact ones, which
+// is what the certification pass relies on.
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
                              int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int4* __restrict__ W,
                              int* __restrict__ cover, int* status) {
