@@ -10,7 +10,8 @@ sampled-and-certified tags (and how many samples), an atomic-free first
 sampling round, Last-CC's hooking rule and sampling rounds, and the arc-tile
 size (64-arc windows per wave,
 i.e. work per wave).  The tuner times candidates by
-coordinate descent on the real input and keeps the winner per
+coordinate descent on the real input, from the fastest of a few seed
+configurations, settles near-ties by a run-off, and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
 """
 from __future__ import annotations
@@ -37,6 +38,15 @@ FREE = (0, 1)  # First-CC's first sampling round without atomics
 LCC = (0, 1)  # Last-CC hooking: 0 = by id, 1 = by hashed priority + relabelling
 LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)
 START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1}
+# Starting points: the built-in defaults, the usual winner on power-law graphs
+# and the usual winner on lattices and k-NN graphs.  The descent starts from
+# the fastest of them, so noise between near-equal candidates cannot strand
+# it far from a known good configuration.
+SEEDS = (
+    START,
+    {"ruler": 4, "sample": 2, "tile": 4, "uf": 0, "ldd": 0, "tags": 1, "ts": 2, "free": 1, "lcc": 0, "lr": 0},
+    {"ruler": 4, "sample": 1, "tile": 3, "uf": 1, "ldd": 0, "tags": 0, "ts": 4, "free": 1, "lcc": 1, "lr": 0},
+)
 
 
 def skew_class(degrees: np.ndarray) -> str:
@@ -89,12 +99,12 @@ class Tuner:
         cfg = self.cache.get(key)
         return encode(cfg) if cfg else None
 
-    def tune(self, key: str, time_ms: Callable[[int], float], reps: int = 3, force: bool = False) -> int:
-        """Coordinate descent over the knobs; ``time_ms(flags)``
+    def tune(self, key: str, time_ms: Callable[[int], float], reps: int = 5, force: bool = False) -> int:
+        """Coordinate descent over the knobs from the fastest seed, then a
+        run-off between the fastest configurations seen; ``time_ms(flags)``
         runs one solve and returns its duration.  Returns the best flags."""
         if not force and key in self.cache:
             return encode(self.cache[key])
-        cfg = dict(START)
         measured: Dict[tuple, float] = {}
 
         def cost(c):
@@ -105,6 +115,7 @@ class Tuner:
                 measured[t] = float(np.median([time_ms(f) for _ in range(reps)]))
             return measured[t]
 
+        cfg = dict(min(SEEDS, key=cost))
         for _ in range(2):
             changed = False
             for knob, values in (("tags", TAGS), ("uf", UF), ("free", FREE), ("lcc", LCC), ("ldd", LDD), ("sample", SAMPLE),
@@ -122,7 +133,23 @@ class Tuner:
                     changed = True
             if not changed:
                 break
-        self.cache[key] = dict(cfg, ms=round(cost(cfg), 4))
+        # run-off: the descent's pick and the next fastest configurations,
+        # timed again in alternation so that drift hits all of them alike
+        finalists = [dict(t) for t, _ in sorted(measured.items(), key=lambda kv: kv[1])[:3]]
+        if cfg not in finalists:
+            finalists.append(dict(cfg))
+        if len(finalists) > 1:
+            runs = {i: [] for i in range(len(finalists))}
+            flags = [encode(c) for c in finalists]
+            for _ in range(2 * reps + 1):
+                for i, f in enumerate(flags):
+                    runs[i].append(time_ms(f))
+            best = min(runs, key=lambda i: float(np.median(runs[i])))
+            cfg = finalists[best]
+            ms = float(np.median(runs[best]))
+        else:
+            ms = cost(cfg)
+        self.cache[key] = dict(cfg, ms=round(ms, 4))
         self.save()
         return encode(cfg)
 

@@ -1,0 +1,59 @@
+"""The autotuner's search on a synthetic cost (no GPU): it must reach the
+optimum of a separable cost from any seed and cache it."""
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2301_01356_amd import _native as N
+from paper_2301_01356_amd import tune
+
+
+def decode(flags):
+    ruler = (flags >> N.TUNE_RULER_SHIFT) & 0xF
+    tile = (flags >> N.TUNE_TILE_SHIFT) & 0x7
+    tags = 1 if flags & N.TUNE_SAMPLED_TAGS else 0
+    return ruler, tile, tags
+
+
+def test_descent_finds_separable_optimum(tmp_path):
+    calls = []
+
+    def cost(flags):
+        calls.append(flags)
+        ruler, tile, tags = decode(flags)
+        ruler = ruler or 5
+        tile = tile or 2
+        return abs(ruler - 6) + 0.5 * abs(tile - 3) + (0.0 if tags else 2.0)
+
+    t = tune.Tuner(cache_path=str(tmp_path / "cache.json"))
+    f = t.tune("k", cost, reps=1)
+    assert decode(f) == (6, 3, 1)
+    assert t.cache["k"]["ruler"] == 6 and t.cache["k"]["tile"] == 3 and t.cache["k"]["tags"] == 1
+    # cached: no new timing
+    n = len(calls)
+    t2 = tune.Tuner(cache_path=str(tmp_path / "cache.json"))
+    assert t2.tune("k", cost, reps=1) == f
+    assert len(calls) == n
+
+
+def test_runoff_prefers_the_faster_of_near_ties(tmp_path):
+    # one configuration is timed lucky (fast) on its first measurement only;
+    # the run-off re-times the finalists and must keep the truly faster one
+    lucky = []
+    seen = {}
+
+    def cost(flags):
+        ruler, tile, tags = decode(flags)
+        if ruler == 7 and not lucky:
+            lucky.append(flags)
+        seen[flags] = seen.get(flags, 0) + 1
+        base = 10.0 - (1.0 if tags else 0.0) - 0.1 * (ruler == 3)
+        if lucky and flags == lucky[0] and seen[flags] <= 2:
+            return base - 5.0
+        return base + (0.2 if ruler == 7 else 0.0)
+
+    t = tune.Tuner(cache_path=None)
+    f = t.tune("k", cost, reps=1)
+    assert decode(f)[0] != 7
+    assert decode(f)[2] == 1
