@@ -281,16 +281,76 @@ __global__ void k_tile_rows(const int* __restrict__ off, int n, int64_t A, const
 // parent array on the way (every parent becomes its root), so the pass
 // before it need not.
 __global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int* __restrict__ scal, int slot, int n,
-                               int* __restrict__ fdeg, int* __restrict__ fflag) {
+                               const uint8_t* __restrict__ mark, int* __restrict__ fdeg, int* __restrict__ fflag) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int big = scal[slot];
   const int r = uf_find(comp, v);
   if (ld_relaxed(comp + v) != r) st_relaxed(comp + v, r);
   const int d = off[v + 1] - off[v];
-  const bool in = d > 0 && r != big;
+  // skipped: the sampled largest set, or in a batch each graph's marked set
+  const bool skip = mark ? mark[r] != 0 : r == scal[slot];
+  const bool in = d > 0 && !skip;
   fdeg[v] = in ? d : 0;
   fflag[v] = in ? 1 : 0;
+}
+
+// Per graph of a batch: the most frequent set among up to 256 evenly spaced
+// vertices gets its root marked, and the frontier skips the rows of marked
+// sets as it skips the largest set of a single graph.  No edge joins two
+// graphs and each graph has one marked set, so every edge between a marked
+// and another set is still seen from the other set's rows.
+constexpr int GRAPH_MODE_SAMPLES = 256;
+__global__ void __launch_bounds__(GRAPH_MODE_SAMPLES) k_mark_graph_modes(int* p, const int* __restrict__ vbegin,
+                                                                         uint8_t* __restrict__ mark) {
+  __shared__ int s[GRAPH_MODE_SAMPLES];
+  __shared__ int best_len[GRAPH_MODE_SAMPLES / WAVE];
+  __shared__ int best_val[GRAPH_MODE_SAMPLES / WAVE];
+  const int g = blockIdx.x, i = threadIdx.x;
+  const int v0 = vbegin[g], ng = vbegin[g + 1] - v0;
+  if (ng <= 0) return;  // the whole block
+  const int S = ng < GRAPH_MODE_SAMPLES ? ng : GRAPH_MODE_SAMPLES;
+  s[i] = i < S ? uf_find(p, v0 + (int)((int64_t)i * ng / S)) : INT32_MAX;
+  __syncthreads();
+  for (int k = 2; k <= GRAPH_MODE_SAMPLES; k <<= 1) {  // bitonic sort, padding last
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int ix = i ^ j;
+      if (ix > i) {
+        const int a = s[i], b = s[ix];
+        if ((a > b) == ((i & k) == 0)) {
+          s[i] = b;
+          s[ix] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int len = 0, val = s[i];
+  if (val != INT32_MAX && (i == 0 || s[i - 1] != val)) {
+    int j = i;
+    while (j < GRAPH_MODE_SAMPLES && s[j] == val) ++j;
+    len = j - i;
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int l2 = __shfl_down(len, o, WAVE), v2 = __shfl_down(val, o, WAVE);
+    if (l2 > len) {
+      len = l2;
+      val = v2;
+    }
+  }
+  if (lane_id() == 0) {
+    best_len[i / WAVE] = len;
+    best_val[i / WAVE] = val;
+  }
+  __syncthreads();
+  if (i == 0) {
+    int bl = 0, bv = -1;
+    for (int w = 0; w < GRAPH_MODE_SAMPLES / WAVE; ++w)
+      if (best_len[w] > bl) {
+        bl = best_len[w];
+        bv = best_val[w];
+      }
+    if (bv >= 0) mark[bv] = 1;
+  }
 }
 
 // Slot v of the flag/degree arrays stands for row map[v] (row v without a map).
@@ -2062,8 +2122,14 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *foff = I(L.foff), *frank = I(L.frank), *frow = I(L.frow), *fstart = I(L.fstart), *ftile = I(L.ftile);
   int* frows = frank + n;  // number of compacted frontier rows (scan total)
   // frontier virtual CSR of the rows a sweep still has to visit
+  // in a batch the per-graph marks live in the head flags (unused until the read-out)
+  uint8_t* gmark = G > 1 ? (uint8_t*)(w + L.heads) : nullptr;
   auto frontier = [&](int* comp, int slot) {
-    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, foff, frank);
+    if (gmark) {
+      fill_i32(c, (int*)gmark, 0, cdiv(n, 4));  // n bytes, the allocation is padded to 256
+      LAUNCH(c, k_mark_graph_modes, (unsigned)G, GRAPH_MODE_SAMPLES, comp, vbegin, gmark);
+    }
+    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark, foff, frank);
     scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
     scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
     LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)nullptr, 1, frow,
