@@ -1176,7 +1176,10 @@ __global__ void k_rmq_block(const int4* __restrict__ W, int n, int64_t nb, int2*
   if (lane == 0 && blk < nb) tab[blk] = q;
 }
 
-__global__ void k_rmq_level(int2* __restrict__ tab, int64_t nb, int j) {
+// Sparse-table levels j and, when two_levels, j + 1, both from level j - 1
+// (level j + 1 takes four entries of level j - 1), so a launch builds two
+// levels.  Entries past the last block are left out of a minimum.
+__global__ void k_rmq_level(int2* __restrict__ tab, int64_t nb, int j, bool two_levels) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   const int64_t h = int64_t(1) << (j - 1);
@@ -1184,6 +1187,10 @@ __global__ void k_rmq_level(int2* __restrict__ tab, int64_t nb, int j) {
   int2 m = pt[b];
   if (b + h < nb) m = mm(m, pt[b + h]);
   tab[(size_t)j * nb + b] = m;
+  if (!two_levels) return;
+  if (b + 2 * h < nb) m = mm(m, pt[b + 2 * h]);
+  if (b + 3 * h < nb) m = mm(m, pt[b + 3 * h]);
+  tab[(size_t)(j + 1) * nb + b] = m;
 }
 
 // low/high over [first, last]; fence(p(v), v) = first[p] <= low[v] and
@@ -2255,7 +2262,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int2 *pre = (int2*)(w + L.pre), *suf = (int2*)(w + L.suf), *tab = (int2*)(w + L.tab);
   auto rmq_tables = [&]() {
     LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W, n, L.nb, pre, suf, tab);
-    for (int j = 1; j < L.levels; ++j) LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j);
+    for (int j = 1; j < L.levels; j += 2)
+      LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j, j + 1 < L.levels);
   };
   if (!tune.sampled_tags) {
     LAUNCH(c, k_tag_init, gn, BLOCK, lone, n, first, rec, w1, w2);
