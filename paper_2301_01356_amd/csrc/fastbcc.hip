@@ -441,42 +441,46 @@ __global__ void k_root_select(const int* __restrict__ off, const int* __restrict
   if (c >= 0 && (lane_id() == WAVE - 1 || cn != c)) rsel[c] = v;
 }
 
-// Most frequent value of p[] over a stratified sample of vertices (one block).
+// Most frequent value of p[] over a stratified sample of vertices (one
+// block): the samples' roots are counted in an LDS hash table with twice as
+// many slots as samples (linear probing always finds a slot), then the block
+// takes the slot with the largest count.
+constexpr int MODE_SLOTS = 2 * MODE_SAMPLES;
 __global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(int* p, int n, int* out) {
-  __shared__ int s[MODE_SAMPLES];
+  __shared__ int key[MODE_SLOTS];
+  __shared__ int cnt[MODE_SLOTS];
   __shared__ int best_len[MODE_SAMPLES / WAVE];
   __shared__ int best_val[MODE_SAMPLES / WAVE];
   const int i = threadIdx.x;
+  for (int k = i; k < MODE_SLOTS; k += MODE_SAMPLES) {
+    key[k] = -1;
+    cnt[k] = 0;
+  }
   int64_t stride = n / MODE_SAMPLES;
   if (stride < 1) stride = 1;
   uint32_t h = (uint32_t)i * 2654435761u + 0x9e3779b9u;
   h ^= h >> 15;
   h *= 0x2c1b3c6du;
   h ^= h >> 12;
-  int64_t v = ((int64_t)i * stride + (int64_t)(h % (uint32_t)stride)) % n;
-  s[i] = uf_find(p, (int)v);  // the sets need not be flattened yet
+  const int64_t v = ((int64_t)i * stride + (int64_t)(h % (uint32_t)stride)) % n;
+  const int r = uf_find(p, (int)v);  // the sets need not be flattened yet
   __syncthreads();
-  // bitonic sort of MODE_SAMPLES values
-  for (int k = 2; k <= MODE_SAMPLES; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      int ix = i ^ j;
-      if (ix > i) {
-        int a = s[i], b = s[ix];
-        bool up = (i & k) == 0;
-        if ((a > b) == up) {
-          s[i] = b;
-          s[ix] = a;
-        }
-      }
-      __syncthreads();
+  uint32_t slot = ((uint32_t)r * 2654435761u) % (uint32_t)MODE_SLOTS;
+  for (;;) {
+    const int k = atomicCAS(&key[slot], -1, r);
+    if (k == -1 || k == r) {
+      atomicAdd(&cnt[slot], 1);
+      break;
     }
+    slot = slot + 1 == (uint32_t)MODE_SLOTS ? 0 : slot + 1;
   }
-  int len = 0, val = s[i];
-  if (i == 0 || s[i - 1] != val) {
-    int j = i;
-    while (j < MODE_SAMPLES && s[j] == val) ++j;
-    len = j - i;
-  }
+  __syncthreads();
+  int len = -1, val = 0;
+  for (int k = i; k < MODE_SLOTS; k += MODE_SAMPLES)
+    if (cnt[k] > len) {
+      len = cnt[k];
+      val = key[k];
+    }
   // block argmax of (len, val)
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     int l2 = __shfl_down(len, o, WAVE), v2 = __shfl_down(val, o, WAVE);
