@@ -1135,9 +1135,9 @@ __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__
       });
 }
 
-// Per preorder slot f: (min, max) of the tags and the vertex at that slot,
-// one 16-byte record, so a range query gathers both tags at once and the
-// preorder map costs no second line.
+// Per preorder slot f: (min, max) of the tags, the vertex at that slot and
+// whether its tags are exact, one 16-byte record, so a range query gathers
+// both tags at once and the preorder map costs no second line.
 __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restrict__ w1, const int* __restrict__ w2,
                               int n, int4* __restrict__ W, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1148,7 +1148,7 @@ __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restri
     return;
   }
   int a = w1[v], b = w2[v];
-  W[f] = make_int4(a < f ? a : f, b > f ? b : f, v, 0);
+  W[f] = make_int4(a < f ? a : f, b > f ? b : f, v, 1);
 }
 
 __device__ __forceinline__ int2 mm(int2 p, int2 q) {
@@ -1253,7 +1253,9 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
   }
   const bool fence = pr.x <= m.x && pr.y >= m.y;
   if (mode == QUERY_CERTIFY) {
-    if (fence) {
+    if (fence && l == r && W[l].w) {
+      rec[v].w = 1;  // a leaf whose row was read whole: its tags, and so the test, are exact
+    } else if (fence) {
       rec[v].w = 2;
       atomicAdd(cover + l, 1);
       atomicAdd(cover + r + 1, -1);
@@ -1276,11 +1278,13 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
   if (x >= n) return;
   cover[x] = 0;
   int f, mn, mx;
+  bool exact = true;  // the tags are exact unless the row was sampled
   if (lone_tags(lone, n, x, first, rec)) {  // no neighbour but itself: its tags are its own
     f = mn = mx = first[x];
   } else {
     f = mn = mx = first[x];
     const int b = off[x], d = off[x + 1] - b;
+    exact = d <= ks;
     if (d <= ks) {
       for (int k = 0; k < d; ++k) {
         const int y = adj[b + k];
@@ -1306,8 +1310,9 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
     atomicExch(status, (int)FASTBCC_ERR_HIP);
     return;
   }
-  // straight into the RMQ input, by preorder slot, with the vertex
-  W[f] = make_int4(mn, mx, x, 0);
+  // straight into the RMQ input, by preorder slot, with the vertex and
+  // whether the tags are exact
+  W[f] = make_int4(mn, mx, x, exact ? 1 : 0);
 }
 
 // Slot i of the preorder: its vertex's row needs exact tags when an undecided
