@@ -1239,9 +1239,15 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
   }
   const int bl = l / WAVE, br = r / WAVE;
   int2 m;
+  bool exact = false;  // every row of the subtree read whole (known for small subtrees)
   if (bl == br) {
     m = make_int2(W[l].x, W[l].y);
-    for (int k = l + 1; k <= r; ++k) m = mm(m, make_int2(W[k].x, W[k].y));
+    exact = W[l].w != 0;
+    for (int k = l + 1; k <= r; ++k) {
+      const int4 wk = W[k];
+      m = mm(m, make_int2(wk.x, wk.y));
+      exact = exact && wk.w != 0;
+    }
   } else {
     m = mm(suf[l], pre[r]);
     const int len = br - bl - 1;
@@ -1253,8 +1259,8 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
   }
   const bool fence = pr.x <= m.x && pr.y >= m.y;
   if (mode == QUERY_CERTIFY) {
-    if (fence && l == r && W[l].w) {
-      rec[v].w = 1;  // a leaf whose row was read whole: its tags, and so the test, are exact
+    if (fence && exact) {
+      rec[v].w = 1;  // every row under v was read whole: the tags, and so the test, are exact
     } else if (fence) {
       rec[v].w = 2;
       atomicAdd(cover + l, 1);
