@@ -1157,10 +1157,13 @@ __device__ __forceinline__ int2 mm(int2 p, int2 q) {
 
 // In-block prefix/suffix (min, max) (block = 64 consecutive preorder slots
 // = one wave), block (min, max) into sparse-table level 0.
-__global__ void k_rmq_block(const int4* __restrict__ W, int n, int64_t nb, int2* __restrict__ pre,
-                            int2* __restrict__ suf, int2* __restrict__ tab) {
+// With `only`, blocks whose flag is clear are left as they are (a rebuild
+// after a few slots changed).
+__global__ void k_rmq_block(const int4* __restrict__ W, int n, int64_t nb, const uint8_t* __restrict__ only,
+                            int2* __restrict__ pre, int2* __restrict__ suf, int2* __restrict__ tab) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = lane_id();
+  if (only && i / WAVE < nb && !only[i / WAVE]) return;  // the whole wave: one block per wave
   const bool in = i < n;
   const int4 w4 = in ? W[i] : make_int4(INT32_MAX, INT32_MIN, 0, 0);
   const int2 w = make_int2(w4.x, w4.y);
@@ -1345,7 +1348,8 @@ __global__ void k_dirty_deg(const int* __restrict__ off, const int4* __restrict_
 // Exact w1/w2 for the listed rows (all their arcs), then their preorder slots.
 __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                             const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                            int tw, const int* __restrict__ first, int4* __restrict__ W) {
+                            int tw, const int* __restrict__ first, int4* __restrict__ W,
+                            uint8_t* __restrict__ dirty_block) {
   const int R = *frows;
   const int64_t F = fstart[R];
   arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
@@ -1371,9 +1375,11 @@ __global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__
     const int knext = __shfl_down(key, 1, WAVE);
     const bool tail = (lane == WAVE - 1) || knext != key;
     if (tail && key >= 0 && mn != INT32_MAX) {  // onto the sampled tags, in place
-      int* wx = (int*)(W + first[x]);
+      const int f = first[x];
+      int* wx = (int*)(W + f);
       atomicMin(wx, mn);
       atomicMax(wx + 1, mx);
+      dirty_block[f / WAVE] = 1;  // its RMQ block is rebuilt
     }
   });
 }
@@ -2275,8 +2281,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   unsigned long long* dbits = (unsigned long long*)(w + L.dbits);
   int4* W = (int4*)(w + L.W);
   int2 *pre = (int2*)(w + L.pre), *suf = (int2*)(w + L.suf), *tab = (int2*)(w + L.tab);
-  auto rmq_tables = [&]() {
-    LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W, n, L.nb, pre, suf, tab);
+  auto rmq_tables = [&](const uint8_t* only) {
+    LAUNCH(c, k_rmq_block, (unsigned)cdiv(L.nb * WAVE, BLOCK), BLOCK, W, n, L.nb, only, pre, suf, tab);
     for (int j = 1; j < L.levels; j += 2)
       LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j, j + 1 < L.levels);
   };
@@ -2284,7 +2290,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_tag_init, gn, BLOCK, lone, n, first, rec, w1, w2);
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, scal + S_STATUS);
-    rmq_tables();
+    rmq_tables(nullptr);
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, true, (int*)nullptr,
            scal + S_STATUS);
   } else {
@@ -2292,7 +2298,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     // undecided vertices only
     int* cover = eflag;  // difference array over preorder slots (2n + 1 >= n + 2 ints)
     LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, cover, scal + S_STATUS);
-    rmq_tables();
+    rmq_tables(nullptr);
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, true, cover,
            scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
@@ -2303,8 +2309,10 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)W + 2, 4, frow,
            fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
-    LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, W);
-    rmq_tables();
+    uint8_t* dirty_block = (uint8_t*)(w + L.heads);  // nb <= n bytes, unused until the read-out
+    fill_i32(c, (int*)dirty_block, 0, cdiv(L.nb, 4));
+    LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, W, dirty_block);
+    rmq_tables(dirty_block);
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, false, (int*)nullptr,
            scal + S_STATUS);
   }
