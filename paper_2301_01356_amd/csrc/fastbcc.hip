@@ -1220,6 +1220,8 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
                             bool by_slot, int* __restrict__ cover, int* status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
+  // the recheck by slot visits only covered slots (cover holds the scanned counts then)
+  if (mode == QUERY_RECHECK && cover && cover[t + 1] <= 0) return;
   const int v = by_slot ? W[t].z : t;
   if (v < 0 || v >= n) {  // only if first[] was no permutation (already reported)
     atomicExch(status, (int)FASTBCC_ERR_HIP);
@@ -2313,7 +2315,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     fill_i32(c, (int*)dirty_block, 0, cdiv(L.nb, 4));
     LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, W, dirty_block);
     rmq_tables(dirty_block);
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, false, (int*)nullptr,
+    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, true, cover,
            scal + S_STATUS);
   }
 
