@@ -80,6 +80,7 @@ constexpr int MIN_TILE_ARCS = 256;  // workspace is sized for this tile size
 constexpr int DEF_TILE_SHIFT = 2;   // 4 windows of 64 arcs
 constexpr int MAX_TILE_SHIFT = 6;
 constexpr int ROWS_TILE_WINDOWS = 64;  // windows per wave in the row-wise label fill
+constexpr int TAG_ROWS_GRID = 2048;    // blocks of the exact-tag pass over listed rows
 constexpr int HUB_DEG = 4096;    // graph degree from which tree-degree counters are sharded
 constexpr int HUB_SHARDS = 32;   // counters per hub (power of two, <= 32: 5 bits of a slot)
 
@@ -96,6 +97,7 @@ enum Scalar : int {
   S_BIG_ROOT = 12,  // Last-CC root of the sampled largest set (priority hooking)
   S_BIG_MIN = 13,   // its smallest member
   S_HUBS = 14,      // hubs numbered so far
+  S_DIRTY = 15,     // rows listed for exact tags
   S_COUNT = 64,
 };
 
@@ -353,10 +355,9 @@ __global__ void __launch_bounds__(GRAPH_MODE_SAMPLES) k_mark_graph_modes(int* p,
   }
 }
 
-// Slot v of the flag/degree arrays stands for row map[v] (row v without a map).
+// The frontier rows in order, with their first arc in the virtual CSR.
 __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __restrict__ frank, int n,
-                                   const int* __restrict__ map, int map_stride, int* __restrict__ frow,
-                                   int* __restrict__ fstart) {
+                                   int* __restrict__ frow, int* __restrict__ fstart) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v > n) return;
   if (v == n) {
@@ -365,7 +366,7 @@ __global__ void k_frontier_compact(const int* __restrict__ foff, const int* __re
   }
   const int r = frank[v];
   if (frank[v + 1] != r) {
-    frow[r] = map ? map[(int64_t)v * map_stride] : v;
+    frow[r] = v;
     fstart[r] = foff[v];
   }
 }
@@ -1283,9 +1284,10 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
 // is what the certification pass relies on.
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
                              int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int4* __restrict__ W,
-                             int* __restrict__ cover, int* status) {
+                             int* __restrict__ cover, int* scal, int* status) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x < 2) cover[n + x] = 0;  // the certification's difference array (n + 2 slots) starts at zero
+  if (x == 0) scal[S_DIRTY] = 0;
   if (x >= n) return;
   cover[x] = 0;
   int f, mn, mx;
@@ -1328,62 +1330,71 @@ __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict_
 
 // Slot i of the preorder: its vertex's row needs exact tags when an undecided
 // interval covers i (cover = exclusive scan of the difference array, so the
-// count at i is cover[i + 1]) and its tags were sampled.
-__global__ void k_dirty_deg(const int* __restrict__ off, const int4* __restrict__ W,
-                            const int* __restrict__ cover, int n, int ks, int* __restrict__ fdeg,
-                            int* __restrict__ fflag) {
+// count at i is cover[i + 1]) and its tags were sampled.  Such rows are
+// appended to a list, one counter atomic per block.
+__global__ void __launch_bounds__(BLOCK) k_dirty_list(const int* __restrict__ off, const int4* __restrict__ W,
+                                                      const int* __restrict__ cover, int n, int ks,
+                                                      int* __restrict__ list, int* count) {
+  __shared__ int wsum[BLOCK / WAVE];
+  __shared__ int base;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  bool in = false;
-  int d = 0;
-  if (cover[i + 1] > 0) {
-    const int x = W[i].z;
-    if (x >= 0 && x < n) {  // else first[] was no permutation (already reported)
-      d = off[x + 1] - off[x];
-      in = d > ks;
-    }
+  int x = -1;
+  if (i < n && cover[i + 1] > 0) {
+    const int y = W[i].z;
+    if (y >= 0 && y < n && off[y + 1] - off[y] > ks) x = y;  // else first[] was no permutation (reported)
   }
-  fdeg[i] = in ? d : 0;
-  fflag[i] = in ? 1 : 0;
+  const unsigned long long m = __ballot(x >= 0);
+  const int lane = lane_id(), wid = threadIdx.x / WAVE;
+  if (lane == 0) wsum[wid] = __builtin_popcountll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < BLOCK / WAVE; ++k) {
+      const int c = wsum[k];
+      wsum[k] = t;
+      t += c;
+    }
+    base = t ? atomicAdd(count, t) : 0;
+  }
+  __syncthreads();
+  if (x >= 0) list[base + wsum[wid] + __builtin_popcountll(m & ((1ull << lane) - 1))] = x;
 }
 
-// Exact w1/w2 for the listed rows (all their arcs), then their preorder slots.
-__global__ void k_tag_dirty(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
-                            const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                            int tw, const int* __restrict__ first, int4* __restrict__ W,
-                            uint8_t* __restrict__ dirty_block) {
-  const int R = *frows;
-  const int64_t F = fstart[R];
-  arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
+// Exact w1/w2 of the listed rows: a wave per row (grid-stride over the list)
+// takes min/max of first[] over the whole row and folds them into the row's
+// RMQ slot (each row is listed once), whose block is then rebuilt.
+__global__ void k_tag_rows(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ list,
+                           const int* __restrict__ count, const int* __restrict__ first, int4* __restrict__ W,
+                           uint8_t* __restrict__ dirty_block) {
+  const int lane = lane_id();
+  const int nw = (int)(((int64_t)gridDim.x * blockDim.x) / WAVE);
+  const int cnt = *count;
+  for (int r = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE); r < cnt; r += nw) {
+    const int x = list[r];
+    const int b = off[x], e = off[x + 1];
     int mn = INT32_MAX, mx = INT32_MIN;
-    const int key = ok ? i : -1;
-    int x = -1;
-    if (ok) {
-      x = frow[i];
-      const int y = adj[(int64_t)off[x] + (k - (int64_t)fstart[i])];
-      if (y != x) mn = mx = first[y];
+    for (int a = b + lane; a < e; a += WAVE) {
+      const int y = adj[a];
+      if (y == x) continue;
+      const int fy = first[y];
+      mn = fy < mn ? fy : mn;
+      mx = fy > mx ? fy : mx;
     }
-    const int lane = lane_id();
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      int k2 = __shfl_up(key, o, WAVE);
-      int m2 = __shfl_up(mn, o, WAVE);
-      int x2 = __shfl_up(mx, o, WAVE);
-      if (lane >= o && k2 == key) {
-        mn = m2 < mn ? m2 : mn;
-        mx = x2 > mx ? x2 : mx;
-      }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const int m2 = __shfl_xor(mn, o, WAVE), x2 = __shfl_xor(mx, o, WAVE);
+      mn = m2 < mn ? m2 : mn;
+      mx = x2 > mx ? x2 : mx;
     }
-    const int knext = __shfl_down(key, 1, WAVE);
-    const bool tail = (lane == WAVE - 1) || knext != key;
-    if (tail && key >= 0 && mn != INT32_MAX) {  // onto the sampled tags, in place
+    if (lane == 0 && mn != INT32_MAX) {
       const int f = first[x];
-      int* wx = (int*)(W + f);
-      atomicMin(wx, mn);
-      atomicMax(wx + 1, mx);
-      dirty_block[f / WAVE] = 1;  // its RMQ block is rebuilt
+      int4 wf = W[f];
+      wf.x = mn < wf.x ? mn : wf.x;
+      wf.y = mx > wf.y ? mx : wf.y;
+      W[f] = wf;
+      dirty_block[f / WAVE] = 1;
     }
-  });
+  }
 }
 
 // ------------------------------------------------------------ Last-CC
@@ -2162,8 +2173,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark, foff, frank);
     scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
     scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
-    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)nullptr, 1, frow,
-           fstart);
+    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, frow, fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
   };
 
@@ -2299,21 +2309,17 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     // sampled tags certify most non-fences; exact tags for the subtrees of the
     // undecided vertices only
     int* cover = eflag;  // difference array over preorder slots (2n + 1 >= n + 2 ints)
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, cover, scal + S_STATUS);
+    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, cover, scal,
+           scal + S_STATUS);
     rmq_tables(nullptr);
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, true, cover,
            scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
-    LAUNCH(c, k_dirty_deg, gn, BLOCK, off, W, cover, n, tune.tag_samples, foff, frank);
-    scan_inplace(c, foff, n, nullptr, tmp, foff + n);
-    scan_inplace(c, frank, n, nullptr, tmp, frows);
-    // the preorder map: the vertex field of the RMQ records
-    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, (const int*)W + 2, 4, frow,
-           fstart);
-    LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
+    int* dirty = w1;  // rows listed for exact tags (w1/w2 are unused with sampled tags)
+    LAUNCH(c, k_dirty_list, gn, BLOCK, off, W, cover, n, tune.tag_samples, dirty, scal + S_DIRTY);
     uint8_t* dirty_block = (uint8_t*)(w + L.heads);  // nb <= n bytes, unused until the read-out
     fill_i32(c, (int*)dirty_block, 0, cdiv(L.nb, 4));
-    LAUNCH(c, k_tag_dirty, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, first, W, dirty_block);
+    LAUNCH(c, k_tag_rows, TAG_ROWS_GRID, BLOCK, off, adj, dirty, scal + S_DIRTY, first, W, dirty_block);
     rmq_tables(dirty_block);
     LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, true, cover,
            scal + S_STATUS);
