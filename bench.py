@@ -85,19 +85,20 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
 # HBM traffic of the slowest kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE; KiB per dispatch) on R-MAT scale 25, and the factors a 1 GiB
 # device copy gives the same counters (known bytes / counter).  Valid only for
-# the kernel sources they were taken on (hash below); otherwise traffic = null.
+# the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "22bddd29a89c33a4",
+    "src_sha": "48c802a4b937f5be",
     "workload": "rmat25",
+    "flags": 0x2B12306,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378491.3, "write_kib": 4090670.9},
-    "k_tag_sample": {"fetch_kib": 2449811.4, "write_kib": 1445438.2},
-    "k_cc_sample": {"fetch_kib": 2371516.7, "write_kib": 657543.6},
-    "k_lr_walk": {"fetch_kib": 1250833.4, "write_kib": 1076058.9},
-    "k_rmq_query": {"fetch_kib": 1215691.3, "write_kib": 188963.6},
-    "k_tree_link": {"fetch_kib": 1246157.0, "write_kib": 829649.5},
-    "k_mirror_find": {"fetch_kib": 2068608.1, "write_kib": 312075.5},
-    "k_lcc_tree": {"fetch_kib": 710181.4, "write_kib": 219277.2},
+    "k_bcc_rows": {"fetch_kib": 378486.8, "write_kib": 4090670.1},
+    "k_tag_sample": {"fetch_kib": 2380244.2, "write_kib": 1445386.5},
+    "k_cc_sample": {"fetch_kib": 2372647.5, "write_kib": 658253.1},
+    "k_lr_walk": {"fetch_kib": 1050754.6, "write_kib": 1081173.9},
+    "k_rmq_query": {"fetch_kib": 871922.4, "write_kib": 67804.7},
+    "k_tree_link": {"fetch_kib": 1246560.7, "write_kib": 829673.5},
+    "k_mirror_find": {"fetch_kib": 2068595.7, "write_kib": 312075.5},
+    "k_lcc_tree": {"fetch_kib": 710949.4, "write_kib": 218909.5},
 }
 
 
@@ -575,7 +576,8 @@ def main():
         achieved = b / (avg_ms * 1e-3) / 1e9
         traffic = traffic_raw = None
         c = COUNTERS.get(name)
-        if c and cfg["workload"] == COUNTERS["workload"] and kernel_src_sha() == COUNTERS["src_sha"]:
+        if (c and cfg["workload"] == COUNTERS["workload"] and kernel_src_sha() == COUNTERS["src_sha"]
+                and args.flags == COUNTERS["flags"]):
             f = COUNTERS["copy_factor"]
             traffic = (c["fetch_kib"] * f["fetch"] + c["write_kib"] * f["write"]) * 1024
             traffic_raw = (c["fetch_kib"] + c["write_kib"]) * 1024

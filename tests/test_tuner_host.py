@@ -57,3 +57,17 @@ def test_runoff_prefers_the_faster_of_near_ties(tmp_path):
     f = t.tune("k", cost, reps=1)
     assert decode(f)[0] != 7
     assert decode(f)[2] == 1
+
+
+def test_shipped_configurations_are_used_without_timing(tmp_path):
+    shipped = tmp_path / "shipped.json"
+    shipped.write_text('{"x": {"ruler": 6, "sample": 1, "tile": 3, "uf": 0, "ldd": 0, "tags": 1, "ts": 2, '
+                       '"free": 1, "lcc": 0, "lr": 0}}')
+    calls = []
+    t = tune.Tuner(cache_path=None, shipped=str(shipped))
+    f = t.tune("x", lambda fl: calls.append(fl) or 1.0)
+    assert calls == [] and decode(f) == (6, 3, 1)
+    # the package's own table parses and encodes
+    own = tune.Tuner(cache_path=None)
+    for key, cfg in own.shipped.items():
+        assert tune.encode(cfg) >= 0, key
