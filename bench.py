@@ -226,7 +226,16 @@ def bench_batch(args):
         log(f"  {t:9.3f} ms  {cnt:3d} launches  {name}")
     tr.close()
 
-    # per-graph plain solves (device-resident inputs, one launch sequence each)
+    if getattr(args, "batch_only", False):  # the batched solve alone (for profiling it)
+        return {"metric": "batched graphs/s (1 GPU)", "value": G / (ms_batch * 1e-3), "unit": "graphs/s",
+                "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+                "data": "synthetic", "config": {"workload": "batch4096_mixed_64..65536", "graphs": G,
+                                                "vertices": u.n, "arcs": u.num_arcs, "hip_graph": True,
+                                                "tuned": cfg},
+                "roofline": None, "cpu_baseline": None}
+    # per-graph plain solves (device-resident inputs, one launch sequence each,
+    # the same flags as the batch)
     dgs = [(torch.from_numpy(g.offsets32()).to(dev), torch.from_numpy(g.adj).to(dev)) for g in graphs]
     from paper_2301_01356_amd import alloc_workspace
     from paper_2301_01356_amd.api import BccResult
@@ -239,14 +248,14 @@ def bench_batch(args):
                       torch.empty(1, dtype=torch.int64, device=dev)) for g in graphs]
     torch.cuda.synchronize()
     for (o, a), out in zip(dgs[:64], outs[:64]):
-        solve(o, a, out=out, workspace=ws, flags=INPUT_FLAGS)
+        solve(o, a, out=out, workspace=ws, flags=solver.flags)
     torch.cuda.synchronize()
     per = []
     for rep in range(max(1, min(3, args.steps))):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for (o, a), out in zip(dgs, outs):
-            solve(o, a, out=out, workspace=ws, flags=INPUT_FLAGS)
+            solve(o, a, out=out, workspace=ws, flags=solver.flags)
         e1.record()
         e1.synchronize()
         per.append(e0.elapsed_time(e1))
@@ -431,6 +440,7 @@ def main():
     ap.add_argument("--flags", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--batch-only", action="store_true", help="batch workload: the batched solve alone")
     ap.add_argument("--no-systems", action="store_true", help="skip the batched and serving legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
