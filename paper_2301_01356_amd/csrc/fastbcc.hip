@@ -1550,8 +1550,10 @@ __global__ void k_bcc_heads(const int4* __restrict__ rec, const int* __restrict_
                             uint8_t* __restrict__ heads, int* rootlab, uint8_t* __restrict__ ap) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int p = rec[v].z;
-  if (p < 0) return;
+  const int4 r = rec[v];
+  const int p = r.z;
+  // a plain (non-fence) tree edge joins v and p in Last-CC: same label, no head
+  if (p < 0 || r.w == 0) return;
   const int L = lab[v];
   if (L == lab[p]) return;
   head[L] = p;
