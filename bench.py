@@ -87,18 +87,18 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "48c802a4b937f5be",
+    "src_sha": "2838e68c81ec4a7d",
     "workload": "rmat25",
     "flags": 0x2B12306,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378486.8, "write_kib": 4090670.1},
-    "k_tag_sample": {"fetch_kib": 2380244.2, "write_kib": 1445386.5},
-    "k_cc_sample": {"fetch_kib": 2372647.5, "write_kib": 658253.1},
-    "k_lr_walk": {"fetch_kib": 1050754.6, "write_kib": 1081173.9},
-    "k_rmq_query": {"fetch_kib": 871922.4, "write_kib": 67804.7},
-    "k_tree_link": {"fetch_kib": 1246560.7, "write_kib": 829673.5},
-    "k_mirror_find": {"fetch_kib": 2068595.7, "write_kib": 312075.5},
-    "k_lcc_tree": {"fetch_kib": 710949.4, "write_kib": 218909.5},
+    "k_bcc_rows": {"fetch_kib": 378443.8, "write_kib": 4090686.8},
+    "k_tag_sample": {"fetch_kib": 2379698.9, "write_kib": 1445445.4},
+    "k_cc_sample": {"fetch_kib": 2372800.4, "write_kib": 657834.8},
+    "k_lr_walk": {"fetch_kib": 1052795.4, "write_kib": 1081108.3},
+    "k_rmq_query": {"fetch_kib": 871766.7, "write_kib": 67711.9},
+    "k_tree_link": {"fetch_kib": 1246407.4, "write_kib": 829667.7},
+    "k_mirror_find": {"fetch_kib": 2068498.4, "write_kib": 312075.5},
+    "k_lcc_tree": {"fetch_kib": 710550.5, "write_kib": 217572.9},
 }
 
 
