@@ -278,6 +278,39 @@ def test_batched_equals_each_graph_alone(flags):
     del rng
 
 
+@pytest.mark.parametrize("flags", BATCH_FLAGS)
+def test_batched_graphs_with_several_components(flags):
+    """Each graph of the batch has several components (the frontier skips
+    one sampled set per graph; the others must still be swept), including
+    a large one next to small ones and a graph whose largest set is tiny."""
+    rng = np.random.default_rng(17)
+    graphs = []
+    for i in range(24):
+        pieces, base = [], 0
+        for _ in range(int(rng.integers(2, 5))):
+            m = int(rng.integers(3, 400 if i % 3 else 8))
+            kind = int(rng.integers(0, 3))
+            if kind == 0:
+                pieces += [(base + a, base + b) for a, b in cycle(m)]
+            elif kind == 1:
+                pieces += [(base + a, base + b) for a, b in path(m)]
+            else:
+                pieces += [(base + a, base + (a + 1 + int(rng.integers(0, m - 1))) % m) for a in range(m)]
+                pieces = [(a, b) for a, b in pieces if a != b]
+            base += m + int(rng.integers(0, 5))  # isolated vertices between pieces
+        graphs.append(gen.from_edges(base, pieces))
+    u = gen.unite(graphs)
+    note(f"batched multi-component graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    r = solve_batched(vb, off, adj, flags=flags)
+    torch.cuda.synchronize()
+    lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for i, g in enumerate(graphs):
+        a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+        assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} in batch")
+
+
 def test_validate_flag():
     g = gen.config("plain_small")
     note("validate ok")
