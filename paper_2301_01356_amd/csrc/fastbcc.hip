@@ -1546,24 +1546,47 @@ __global__ void k_readout_init(int n, int* __restrict__ head, uint8_t* __restric
 // head(l[u]) = p(u) when l[u] != l[p(u)] (paper: Algorithm 1, component
 // heads).  A non-root head is an articulation point; a tree root is one iff
 // it heads two different labels.
-__global__ void k_bcc_heads(const int4* __restrict__ rec, const int* __restrict__ lab, int n, int* __restrict__ head,
-                            uint8_t* __restrict__ heads, int* rootlab, uint8_t* __restrict__ ap) {
+// A BCC label is a Last-CC root that is not a tree root (a tree root is a
+// singleton of the skeleton and heads, but never labels, a BCC).
+__device__ __forceinline__ bool is_bcc_label(const int4* __restrict__ rec, const int* __restrict__ lab, int v) {
+  return lab[v] == v && rec[v].z >= 0;
+}
+
+// Heads, head flags and articulation points; with bsum also the block's
+// count of BCC labels, which shares this pass's reads of rec and lab.
+__global__ void __launch_bounds__(BLOCK) k_bcc_heads(const int4* __restrict__ rec, const int* __restrict__ lab, int n,
+                                                     int* __restrict__ head, uint8_t* __restrict__ heads,
+                                                     int* rootlab, uint8_t* __restrict__ ap, int* __restrict__ bsum) {
+  __shared__ int part[BLOCK / WAVE];
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int4 r = rec[v];
-  const int p = r.z;
-  // a plain (non-fence) tree edge joins v and p in Last-CC: same label, no head
-  if (p < 0 || r.w == 0) return;
-  const int L = lab[v];
-  if (L == lab[p]) return;
-  head[L] = p;
-  heads[p] = 1;
-  if (ap == nullptr) return;
-  if (rec[p].z >= 0) {
-    ap[p] = 1;
-  } else {
-    int old = atomicCAS(rootlab + p, -1, L);
-    if (old != -1 && old != L) ap[p] = 1;
+  bool is_label = false;
+  if (v < n) {
+    const int4 r = rec[v];
+    const int p = r.z;
+    const int L = lab[v];
+    is_label = L == v && p >= 0;  // is_bcc_label on the values at hand
+    // a plain (non-fence) tree edge joins v and p in Last-CC: same label, no head
+    if (p >= 0 && r.w != 0 && L != lab[p]) {
+      head[L] = p;
+      heads[p] = 1;
+      if (ap != nullptr) {
+        if (rec[p].z >= 0) {
+          ap[p] = 1;
+        } else {
+          int old = atomicCAS(rootlab + p, -1, L);
+          if (old != -1 && old != L) ap[p] = 1;
+        }
+      }
+    }
+  }
+  if (bsum == nullptr) return;  // uniform
+  const uint64_t m = __ballot(is_label);
+  if (lane_id() == 0) part[threadIdx.x / WAVE] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) t += part[w];
+    bsum[blockIdx.x] = t;
   }
 }
 
@@ -1577,45 +1600,42 @@ __device__ __forceinline__ int graph_of(const int* __restrict__ vbegin, int G, i
   return lo;
 }
 
-// A BCC label is a Last-CC root that is not a tree root (a tree root is a
-// singleton of the skeleton and heads, but never labels, a BCC).
-__device__ __forceinline__ bool is_bcc_label(const int4* __restrict__ rec, const int* __restrict__ lab, int v) {
-  return lab[v] == v && rec[v].z >= 0;
-}
-
-// BCC count: per-block partial sums (one graph) or per-graph counters.
-__global__ void k_bcc_count(const int4* __restrict__ rec, const int* __restrict__ lab, int n,
-                            const int* __restrict__ vbegin, int G, int* __restrict__ bsum, int64_t* nbcc) {
-  __shared__ int part[BLOCK / WAVE];
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool is_label = v < n && is_bcc_label(rec, lab, v);
-  if (G <= 1) {
-    uint64_t m = __ballot(is_label);
-    if (lane_id() == 0) part[threadIdx.x / WAVE] = __popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int t = 0;
-      for (int w = 0; w < BLOCK / WAVE; ++w) t += part[w];
-      bsum[blockIdx.x] = t;
-    }
-    return;
+// BCC count of a batch, a wave per graph: the whole BLOCK-vertex blocks
+// inside the graph come from the exclusive scan P of k_bcc_heads' block
+// counts, the partial blocks at its two ends are counted here.
+__global__ void k_graph_count(const int4* __restrict__ rec, const int* __restrict__ lab, int n,
+                              const int* __restrict__ vbegin, int G, const int* __restrict__ P,
+                              int64_t* __restrict__ nbcc) {
+  const int g = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+  if (g >= G) return;  // the whole wave
+  const int a = min(max(vbegin[g], 0), n), b = min(max(vbegin[g + 1], a), n);
+  const int ba = (a + BLOCK - 1) / BLOCK, bb = b / BLOCK;  // whole blocks [ba, bb)
+  int64_t t = 0;
+  int lo_end = b, hi_start = b;  // no whole block: count [a, b) directly
+  if (ba < bb) {
+    t = P[bb] - P[ba];
+    lo_end = ba * BLOCK;
+    hi_start = bb * BLOCK;
   }
-  // several graphs: one atomic per wave when the wave's labels share a graph
-  const int g = v < n ? graph_of(vbegin, G, v) : -1;
-  const int g0 = __shfl(g, 0, WAVE);
-  const bool same = __all(g == g0 || v >= n);
-  if (same) {
-    uint64_t m = __ballot(is_label);
-    if (lane_id() == 0 && m) atomicAdd((unsigned long long*)(nbcc + g0), (unsigned long long)__popcll(m));
-  } else if (is_label) {
-    atomicAdd((unsigned long long*)(nbcc + g), 1ull);
-  }
+  const int lane = lane_id();
+  for (int v = a + lane; v - lane < lo_end; v += WAVE)
+    t += __popcll(__ballot(v < lo_end && is_bcc_label(rec, lab, v)));
+  for (int v = hi_start + lane; v - lane < b; v += WAVE)
+    t += __popcll(__ballot(v < b && is_bcc_label(rec, lab, v)));
+  if (lane == 0) nbcc[g] = t;
 }
 
 __global__ void __launch_bounds__(1024) k_sum_blocks(const int* __restrict__ bsum, int nblocks, int64_t* out) {
   __shared__ long long part[1024 / WAVE];
   long long t = 0;
-  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) t += bsum[i];
+  // eight independent loads in flight per lane, not one latency per element
+  for (int i = threadIdx.x; i < nblocks; i += 8 * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = i + k * (int)blockDim.x;
+      if (j < nblocks) t += bsum[j];
+    }
+  }
   for (int o = WAVE / 2; o > 0; o >>= 1) t += __shfl_down(t, o, WAVE);
   if (lane_id() == 0) part[threadIdx.x / WAVE] = t;
   __syncthreads();
@@ -2362,10 +2382,14 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid), *canon = I(L.canon), *bsum = I(L.bsum);
   uint8_t* heads = (uint8_t*)(w + L.heads);
   LAUNCH(c, k_readout_init, gn, BLOCK, n, head, heads, rootlab, minid, out_ap);
-  LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, heads, rootlab, out_ap);
+  LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, heads, rootlab, out_ap, out_nbcc ? bsum : nullptr);
   if (out_nbcc) {
-    LAUNCH(c, k_bcc_count, gn, BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
-    if (G <= 1) LAUNCH(c, k_sum_blocks, 1, 1024, bsum, (int)gn, out_nbcc);
+    if (G <= 1) {
+      LAUNCH(c, k_sum_blocks, 1, 1024, bsum, (int)gn, out_nbcc);
+    } else {
+      scan_inplace(c, bsum, gn, nullptr, I(L.scan_tmp), nullptr);  // bsum[gn] = total
+      LAUNCH(c, k_graph_count, grid_for((int64_t)G * WAVE), BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
+    }
   }
   unsigned long long* bigbits = (unsigned long long*)(w + L.bigbits);
   LAUNCH(c, k_lbig, 1, 1, lab, scal);
