@@ -87,18 +87,18 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "bc956fe423ffc13c",
+    "src_sha": "a275628ffcbdbfd2",
     "workload": "rmat25",
     "flags": 0x2B12306,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378473.2, "write_kib": 4090682.2},
-    "k_tag_sample": {"fetch_kib": 2377196.4, "write_kib": 1445371.4},
-    "k_cc_sample": {"fetch_kib": 2373280.5, "write_kib": 658320.0},
-    "k_lr_walk": {"fetch_kib": 1051842.9, "write_kib": 1080910.8},
-    "k_rmq_query": {"fetch_kib": 871619.6, "write_kib": 67639.3},
-    "k_tree_link": {"fetch_kib": 1246306.8, "write_kib": 829623.6},
-    "k_mirror_find": {"fetch_kib": 2068530.1, "write_kib": 312075.5},
-    "k_lcc_tree": {"fetch_kib": 710833.5, "write_kib": 219101.3},
+    "k_bcc_rows": {"fetch_kib": 378501.1, "write_kib": 4090681.0},
+    "k_tag_sample": {"fetch_kib": 2378639.2, "write_kib": 1445442.8},
+    "k_cc_sample": {"fetch_kib": 2372184.1, "write_kib": 658252.5},
+    "k_lr_walk": {"fetch_kib": 1052600.6, "write_kib": 1081685.3},
+    "k_rmq_query": {"fetch_kib": 871934.4, "write_kib": 67762.7},
+    "k_tree_link": {"fetch_kib": 1246244.5, "write_kib": 829675.1},
+    "k_mirror_find": {"fetch_kib": 2068521.9, "write_kib": 312075.5},
+    "k_lcc_tree": {"fetch_kib": 711359.1, "write_kib": 217435.6},
 }
 
 

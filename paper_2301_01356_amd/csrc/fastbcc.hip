@@ -1521,7 +1521,10 @@ __global__ void k_label_min(const int* __restrict__ lab, int n, const int* __res
     if (lane >= o && l2 == L && m2 < m) m = m2;
   }
   const int ln = __shfl_down(L, 1, WAVE);
-  if (L >= 0 && (lane == WAVE - 1 || ln != L)) atomicMin(minv + L, m);
+  // minima only fall, so a read that already shows m or less makes the
+  // atomic moot; blocks run roughly in vertex order, so the first visitor of
+  // a label usually holds its minimum and the rest only read
+  if (L >= 0 && (lane == WAVE - 1 || ln != L) && m < minv[L]) atomicMin(minv + L, m);
 }
 
 __global__ void k_relabel(int* lab, int n, const int* __restrict__ scal, const int* __restrict__ minv) {
@@ -1625,16 +1628,18 @@ __global__ void k_graph_count(const int4* __restrict__ rec, const int* __restric
   if (lane == 0) nbcc[g] = t;
 }
 
+// Sum of nblocks ints into *out, which the solve zeroed: SUM_PER_LANE
+// values per lane, one 64-bit atomic per block.
+constexpr int SUM_PER_LANE = 4;
 __global__ void __launch_bounds__(1024) k_sum_blocks(const int* __restrict__ bsum, int nblocks, int64_t* out) {
   __shared__ long long part[1024 / WAVE];
+  const int base = blockIdx.x * blockDim.x * SUM_PER_LANE + threadIdx.x;
   long long t = 0;
-  // eight independent loads in flight per lane, not one latency per element
-  for (int i = threadIdx.x; i < nblocks; i += 8 * blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int j = i + k * (int)blockDim.x;
-      if (j < nblocks) t += bsum[j];
-    }
+  for (int k = 0; k < SUM_PER_LANE; ++k) {
+    const int j = base + k * (int)blockDim.x;
+    const int x = bsum[min(j, nblocks - 1)];  // in bounds for every lane, so the loads overlap
+    t += j < nblocks ? x : 0;
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) t += __shfl_down(t, o, WAVE);
   if (lane_id() == 0) part[threadIdx.x / WAVE] = t;
@@ -1642,7 +1647,7 @@ __global__ void __launch_bounds__(1024) k_sum_blocks(const int* __restrict__ bsu
   if (threadIdx.x == 0) {
     long long s = 0;
     for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) s += part[w];
-    *out = s;
+    if (s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
   }
 }
 
@@ -2385,7 +2390,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, heads, rootlab, out_ap, out_nbcc ? bsum : nullptr);
   if (out_nbcc) {
     if (G <= 1) {
-      LAUNCH(c, k_sum_blocks, 1, 1024, bsum, (int)gn, out_nbcc);
+      LAUNCH(c, k_sum_blocks, grid_for(gn, 1024 * SUM_PER_LANE), 1024, bsum, (int)gn, out_nbcc);
     } else {
       scan_inplace(c, bsum, gn, nullptr, I(L.scan_tmp), nullptr);  // bsum[gn] = total
       LAUNCH(c, k_graph_count, grid_for((int64_t)G * WAVE), BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
