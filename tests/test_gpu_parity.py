@@ -262,6 +262,8 @@ def test_batched_equals_each_graph_alone(flags):
     graphs = [gen.mixed(41, i, 8, 3000, 4.0, 16.0) for i in range(40)]
     graphs.append(gen.Csr(3, np.zeros(4, np.int64), np.zeros(0, np.int32)))  # an edgeless graph
     graphs.insert(5, gen.from_edges(4, cycle(4)))
+    empty = gen.Csr(0, np.zeros(1, np.int64), np.zeros(0, np.int32))  # no vertices at all
+    graphs = [empty] + graphs[:20] + [empty, empty] + graphs[20:] + [empty]
     u = gen.unite(graphs)
     note(f"batched {len(graphs)} graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
     vb = torch.from_numpy(u.vbegin).to(DEV)
