@@ -87,18 +87,18 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "a275628ffcbdbfd2",
+    "src_sha": "c91d97a0f6f53577",
     "workload": "rmat25",
     "flags": 0x2B12306,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378501.1, "write_kib": 4090681.0},
-    "k_tag_sample": {"fetch_kib": 2378639.2, "write_kib": 1445442.8},
-    "k_cc_sample": {"fetch_kib": 2372184.1, "write_kib": 658252.5},
-    "k_lr_walk": {"fetch_kib": 1052600.6, "write_kib": 1081685.3},
-    "k_rmq_query": {"fetch_kib": 871934.4, "write_kib": 67762.7},
-    "k_tree_link": {"fetch_kib": 1246244.5, "write_kib": 829675.1},
-    "k_mirror_find": {"fetch_kib": 2068521.9, "write_kib": 312075.5},
-    "k_lcc_tree": {"fetch_kib": 711359.1, "write_kib": 217435.6},
+    "k_bcc_rows": {"fetch_kib": 378476.1, "write_kib": 4090690.6},
+    "k_tag_sample": {"fetch_kib": 2378303.6, "write_kib": 1445424.3},
+    "k_cc_sample": {"fetch_kib": 2372999.0, "write_kib": 659098.0},
+    "k_lr_walk": {"fetch_kib": 1053374.9, "write_kib": 1080994.8},
+    "k_rmq_query": {"fetch_kib": 871825.9, "write_kib": 67939.5},
+    "k_tree_link": {"fetch_kib": 1246462.6, "write_kib": 829752.9},
+    "k_mirror_find": {"fetch_kib": 2068611.6, "write_kib": 312075.5},
+    "k_lcc_tree": {"fetch_kib": 710019.0, "write_kib": 218539.7},
 }
 
 

@@ -276,14 +276,15 @@ __global__ void k_tile_rows(const int* __restrict__ off, int n, int64_t A, const
 
 // Frontier of a connectivity sweep: the rows outside the sampled largest set
 // (their sampled arcs are visited again; re-linking joined ends costs two
-// finds).  fdeg -> scan gives each
-// row's first virtual arc; the non-empty rows are then compacted (row id +
-// start) so the virtual CSR has no empty rows for a wave to walk over.
+// finds).  One scan over fdeg gives each frontier row both its rank (the
+// count of non-zero degrees before it) and its first virtual arc (the sum of
+// degrees before it), and its last pass writes the compacted rows (row id +
+// start), so the virtual CSR has no empty rows for a wave to walk over.
 // Frontier rows: those outside the sampled largest set.  Flattens the
 // parent array on the way (every parent becomes its root), so the pass
 // before it need not.
 __global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int* __restrict__ scal, int slot, int n,
-                               const uint8_t* __restrict__ mark, int* __restrict__ fdeg, int* __restrict__ fflag) {
+                               const uint8_t* __restrict__ mark, int* __restrict__ fdeg) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int r = uf_find(comp, v);
@@ -293,7 +294,6 @@ __global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int
   const bool skip = mark ? mark[r] != 0 : r == scal[slot];
   const bool in = d > 0 && !skip;
   fdeg[v] = in ? d : 0;
-  fflag[v] = in ? 1 : 0;
 }
 
 // Per graph of a batch: the most frequent set among up to 256 evenly spaced
@@ -355,20 +355,57 @@ __global__ void __launch_bounds__(GRAPH_MODE_SAMPLES) k_mark_graph_modes(int* p,
   }
 }
 
-// The frontier rows in order, with their first arc in the virtual CSR.
-__global__ void k_frontier_compact(const int* __restrict__ foff, const int* __restrict__ frank, int n,
-                                   int* __restrict__ frow, int* __restrict__ fstart) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v > n) return;
-  if (v == n) {
-    fstart[frank[n]] = foff[n];  // end of the last compacted row = frontier arc count
-    return;
+// Per scan tile of fdeg: the sum of degrees into bsum[tile] and the count of
+// frontier rows into bsum[tiles + tile].
+__global__ void __launch_bounds__(SCAN_BLOCK) k_fscan_reduce(const int* __restrict__ fdeg, int64_t n,
+                                                              int* __restrict__ bsum, int tiles) {
+  __shared__ int lds[SCAN_BLOCK / WAVE];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load_items(fdeg, base, n, v);
+  int s = 0, k = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    s += v[i];
+    k += v[i] > 0;
   }
-  const int r = frank[v];
-  if (frank[v + 1] != r) {
-    frow[r] = v;
-    fstart[r] = foff[v];
+  int total;
+  block_exclusive_scan(s, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+  block_exclusive_scan(k, lds, total);
+  if (threadIdx.x == 0) bsum[tiles + blockIdx.x] = total;
+}
+
+// The frontier rows in order, with their first arc in the virtual CSR, from
+// the tiles' exclusive sums (bsum after the spine); fstart[rows] closes the
+// last row with the frontier's arc count.
+__global__ void __launch_bounds__(SCAN_BLOCK) k_fscan_compact(const int* __restrict__ fdeg, int64_t n,
+                                                               const int* __restrict__ bsum, int tiles,
+                                                               const int* __restrict__ rows, const int* __restrict__ arcs,
+                                                               int* __restrict__ frow, int* __restrict__ fstart) {
+  __shared__ int lds[SCAN_BLOCK / WAVE];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load_items(fdeg, base, n, v);  // zero past n: no row there
+  int s = 0, k = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    s += v[i];
+    k += v[i] > 0;
   }
+  int total;
+  int start = block_exclusive_scan(s, lds, total) + bsum[blockIdx.x];
+  int rank = block_exclusive_scan(k, lds, total) + bsum[tiles + blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (v[i] > 0) {
+      frow[rank] = (int)(base + i);
+      fstart[rank] = start;
+      ++rank;
+    }
+    start += v[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) fstart[*rows] = *arcs;
 }
 
 // Tree roots: every component with a sampled vertex is rooted at its
@@ -2197,10 +2234,16 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
       fill_i32(c, (int*)gmark, 0, cdiv(n, 4));  // n bytes, the allocation is padded to 256
       LAUNCH(c, k_mark_graph_modes, (unsigned)G, GRAPH_MODE_SAMPLES, comp, vbegin, gmark);
     }
-    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark, foff, frank);
-    scan_inplace(c, foff, n, nullptr, I(L.scan_tmp), foff + n);
-    scan_inplace(c, frank, n, nullptr, I(L.scan_tmp), frows);
-    LAUNCH(c, k_frontier_compact, grid_for((int64_t)n + 1), BLOCK, foff, frank, n, frow, fstart);
+    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark, foff);
+    // one scan of the degrees for both the ranks and the starts (the scratch
+    // holds 2 * tiles sums: cdiv(2n + 1, SCAN_TILE) + 1 >= 2 * cdiv(n, SCAN_TILE))
+    const int tiles = (int)cdiv(n, SCAN_TILE);
+    int* tsum = I(L.scan_tmp);
+    LAUNCH(c, k_fscan_reduce, (unsigned)tiles, SCAN_BLOCK, foff, (int64_t)n, tsum, tiles);
+    LAUNCH(c, k_scan_spine, 1, 1024, tsum, tiles, foff + n);           // arcs of the frontier
+    LAUNCH(c, k_scan_spine, 1, 1024, tsum + tiles, tiles, frows);      // its rows
+    LAUNCH(c, k_fscan_compact, (unsigned)tiles, SCAN_BLOCK, foff, (int64_t)n, tsum, tiles, frows, foff + n, frow,
+           fstart);
     LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, fstart, n, A, frows, tile_arcs, ftile);
   };
 
