@@ -2305,7 +2305,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_edge_compact, gn, BLOCK, hu, hv, eid, n, eu, ev);
   const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
   LAUNCH(c, k_tree_link, grid_for(arcs_max), BLOCK, off, hubidx, eid, n, eu, ev, headp, shard, nxt);
-  int* lone = I(L.frank);  // the frontier ranks are free from here until Tagging's own frontier
+  int* lone = I(L.frank);  // free from here until Last-CC's frontier rewrites its row count (frank[n])
   int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
   LAUNCH(c, k_hub_lists, gn, BLOCK, off, hubidx, cc, n, headp, shard, rootidx, lone, rdeg);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
