@@ -98,3 +98,17 @@ def test_tune_flag_encoding():
     assert N.tune_flags(sampled_tags=True) == N.TUNE_SAMPLED_TAGS
     assert (N.tune_flags(tag_samples=2) >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3 == 1
     assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 27) == N.ERR_INVALID_ARGUMENT
+
+
+def test_host_tensors_are_refused_not_solved_on_the_cpu():
+    """The package has no CPU path: host tensors raise before any work."""
+    import torch
+
+    from paper_2301_01356_amd import solve, solve_batched
+
+    off = torch.tensor([0, 1, 2], dtype=torch.int32)
+    adj = torch.tensor([1, 0], dtype=torch.int32)
+    with pytest.raises(ValueError, match="GPU"):
+        solve(off, adj)
+    with pytest.raises(ValueError, match="GPU"):
+        solve_batched(torch.tensor([0, 2], dtype=torch.int32), off, adj)
