@@ -112,3 +112,17 @@ def test_host_tensors_are_refused_not_solved_on_the_cpu():
         solve(off, adj)
     with pytest.raises(ValueError, match="GPU"):
         solve_batched(torch.tensor([0, 2], dtype=torch.int32), off, adj)
+
+
+def test_binding_constants_match_the_header():
+    """Every FASTBCC_FLAG_* / FASTBCC_TUNE_* define and status code of the
+    header has the same value in the Python binding."""
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"#define\s+FASTBCC_((?:FLAG|TUNE)_\w+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", text))
+    assert defines, "no flag defines found"
+    for name, value in defines.items():
+        assert getattr(N, name) == int(value, 0), name
+    statuses = dict(re.findall(r"\bFASTBCC_(OK|ERR_\w+)\s*=\s*(\d+)", text))
+    assert statuses, "no status codes found"
+    for name, value in statuses.items():
+        assert getattr(N, name) == int(value), name
