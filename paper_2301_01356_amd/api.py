@@ -29,17 +29,37 @@ def _dev_ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
-def _check_tensor(t: torch.Tensor, name: str, dtypes, numel=None):
+def _check_tensor(t: torch.Tensor, name: str, dtypes, numel=None, device=None):
+    """Refuse anything the kernels cannot read as a plain device array: host or
+    foreign-device tensors, wrong dtypes, strided views, wrong sizes."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must live on a GPU (got {t.device})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the graph on {device}")
     if t.dtype not in dtypes:
         raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _check_workspace(ws: torch.Tensor, n: int, num_arcs: int, num_graphs: int, device) -> None:
+    """The workspace must be a contiguous uint8 buffer on the graph's device,
+    large enough (the library checks size and alignment too, but cannot tell
+    a host pointer from a device one)."""
+    _check_tensor(ws, "workspace", (torch.uint8,), device=device)
+    need = workspace_size(n, num_arcs, num_graphs)
+    if ws.numel() < need:
+        raise ValueError(f"workspace has {ws.numel()} bytes, the solve needs {need}")
+
+
+def _check_result(out: "BccResult", n: int, A: int, G: int, device) -> None:
+    _check_tensor(out.edge_label, "edge_label", (torch.int32,), A, device)
+    _check_tensor(out.is_ap, "is_ap", (torch.uint8,), n, device)
+    _check_tensor(out.num_bcc, "num_bcc", (torch.int64,), G, device)
 
 
 def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
@@ -72,22 +92,19 @@ def solve(
     n = offsets.numel() - 1
     if n < 0:
         raise ValueError("offsets needs n + 1 >= 1 entries")
-    _check_tensor(adj, "adj", (torch.int32,))
-    A = adj.numel()
     dev = offsets.device
-    if adj.device != dev:
-        raise ValueError("offsets and adj must be on the same device")
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    A = adj.numel()
     if out is None:
         out = BccResult(
             torch.empty(A, dtype=torch.int32, device=dev),
             torch.empty(n, dtype=torch.uint8, device=dev),
             torch.empty(1, dtype=torch.int64, device=dev),
         )
-    _check_tensor(out.edge_label, "edge_label", (torch.int32,), A)
-    _check_tensor(out.is_ap, "is_ap", (torch.uint8,), n)
-    _check_tensor(out.num_bcc, "num_bcc", (torch.int64,), 1)
+    _check_result(out, n, A, 1, dev)
     if workspace is None:
         workspace = alloc_workspace(n, A, 1, dev)
+    _check_workspace(workspace, n, A, 1, dev)
     fn = N.lib().fastbcc_solve if offsets.dtype == torch.int32 else N.lib().fastbcc_solve_off64
     with torch.cuda.device(dev):
         st = fn(
@@ -119,26 +136,27 @@ def solve_batched(
 ) -> BccResult:
     """BCCs of many graphs concatenated as one CSR (graph g owns vertices
     vbegin[g]..vbegin[g+1]); labels are graph-local, num_bcc is per graph."""
-    _check_tensor(vbegin, "vbegin", (torch.int32,))
     _check_tensor(offsets, "offsets", (torch.int32,))
-    _check_tensor(adj, "adj", (torch.int32,))
+    dev = offsets.device
+    _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
     G = vbegin.numel() - 1
     if G < 1:
         raise ValueError("vbegin needs at least 2 entries")
     n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets needs n + 1 >= 1 entries")
     A = adj.numel()
-    dev = offsets.device
     if out is None:
         out = BccResult(
             torch.empty(A, dtype=torch.int32, device=dev),
             torch.empty(n, dtype=torch.uint8, device=dev),
             torch.empty(G, dtype=torch.int64, device=dev),
         )
-    _check_tensor(out.edge_label, "edge_label", (torch.int32,), A)
-    _check_tensor(out.is_ap, "is_ap", (torch.uint8,), n)
-    _check_tensor(out.num_bcc, "num_bcc", (torch.int64,), G)
+    _check_result(out, n, A, G, dev)
     if workspace is None:
         workspace = alloc_workspace(n, A, G, dev)
+    _check_workspace(workspace, n, A, G, dev)
     with torch.cuda.device(dev):
         st = N.lib().fastbcc_solve_batched(
             G,
@@ -172,19 +190,30 @@ def solve_traced(
 ) -> BccResult:
     """``solve``/``solve_batched`` with an event pair around every kernel."""
     _check_tensor(offsets, "offsets", (torch.int32, torch.int64))
-    _check_tensor(adj, "adj", (torch.int32,))
-    n = offsets.numel() - 1
-    A = adj.numel()
-    G = 1 if vbegin is None else vbegin.numel() - 1
     dev = offsets.device
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets needs n + 1 >= 1 entries")
+    A = adj.numel()
+    G = 1
+    if vbegin is not None:
+        _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+        G = vbegin.numel() - 1
+        if G < 1:
+            raise ValueError("vbegin needs at least 2 entries")
+        if offsets.dtype != torch.int32:
+            raise TypeError("batched solves take int32 offsets")
     if out is None:
         out = BccResult(
             torch.empty(A, dtype=torch.int32, device=dev),
             torch.empty(n, dtype=torch.uint8, device=dev),
             torch.empty(G, dtype=torch.int64, device=dev),
         )
+    _check_result(out, n, A, G, dev)
     if workspace is None:
         workspace = alloc_workspace(n, A, G, dev)
+    _check_workspace(workspace, n, A, G, dev)
     with torch.cuda.device(dev):
         st = N.lib().fastbcc_solve_traced(
             G,
@@ -212,8 +241,15 @@ def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Option
     """BC-labeling of the last solve on ``workspace``: (home int32[n], home_head
     int32[n]) -- each vertex's home BCC (canonical id) and that BCC's head;
     -1 for spanning-tree roots."""
+    _check_tensor(workspace, "workspace", (torch.uint8,))
     dev = workspace.device
-    G = 1 if vbegin is None else vbegin.numel() - 1
+    G = 1
+    if vbegin is not None:
+        _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+        G = vbegin.numel() - 1
+        if G < 1:
+            raise ValueError("vbegin needs at least 2 entries")
+    _check_workspace(workspace, n, num_arcs, G, dev)
     home = torch.empty(n, dtype=torch.int32, device=dev)
     head = torch.empty(n, dtype=torch.int32, device=dev)
     with torch.cuda.device(dev):
@@ -225,8 +261,11 @@ def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Option
 
 
 def read_device_status(workspace: torch.Tensor, stream=None) -> int:
+    """Synchronise ``stream`` and return the status word the last solve on
+    ``workspace`` left (0 = no device-side check fired)."""
     import ctypes
 
+    _check_tensor(workspace, "workspace", (torch.uint8,))
     out = ctypes.c_int32(0)
     N.check(N.lib().fastbcc_read_device_status(workspace.data_ptr(), _stream_handle(stream), ctypes.byref(out)))
     return int(out.value)

@@ -303,12 +303,13 @@ __global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int
 // and another set is still seen from the other set's rows.
 constexpr int GRAPH_MODE_SAMPLES = 256;
 __global__ void __launch_bounds__(GRAPH_MODE_SAMPLES) k_mark_graph_modes(int* p, const int* __restrict__ vbegin,
-                                                                         uint8_t* __restrict__ mark) {
+                                                                         int n, uint8_t* __restrict__ mark) {
   __shared__ int s[GRAPH_MODE_SAMPLES];
   __shared__ int best_len[GRAPH_MODE_SAMPLES / WAVE];
   __shared__ int best_val[GRAPH_MODE_SAMPLES / WAVE];
   const int g = blockIdx.x, i = threadIdx.x;
-  const int v0 = vbegin[g], ng = vbegin[g + 1] - v0;
+  // clamped like the per-graph count: a graph range is never read past n
+  const int v0 = min(max(vbegin[g], 0), n), ng = min(max(vbegin[g + 1], v0), n) - v0;
   if (ng <= 0) return;  // the whole block
   const int S = ng < GRAPH_MODE_SAMPLES ? ng : GRAPH_MODE_SAMPLES;
   s[i] = i < S ? uf_find(p, v0 + (int)((int64_t)i * ng / S)) : INT32_MAX;
@@ -496,6 +497,8 @@ __global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(int* p, int n, int* 
   }
   int64_t stride = n / MODE_SAMPLES;
   if (stride < 1) stride = 1;
+  // jitter inside each stride: Knuth's multiplicative hash (2654435761 =
+  // 2^32 / golden ratio) of the sample index, then a multiply / xor-shift mix
   uint32_t h = (uint32_t)i * 2654435761u + 0x9e3779b9u;
   h ^= h >> 15;
   h *= 0x2c1b3c6du;
@@ -551,6 +554,29 @@ __global__ void k_compress(int* p, int n) {
 }
 
 // ------------------------------------------------------------ validation
+// Graph g of a batch owns vertices [vbegin[g], vbegin[g+1]) (vbegin already
+// checked to be nondecreasing from 0 to n).
+__device__ __forceinline__ int graph_index(const int* __restrict__ vbegin, int G, int v) {
+  int lo = 0, hi = G;  // vbegin[lo] <= v < vbegin[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (vbegin[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The graph ranges of a batch: vbegin[0] = 0, vbegin[G] = n, nondecreasing.
+__global__ void k_validate_vbegin(const int* __restrict__ vbegin, int G, int n, int* status) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > G) return;
+  bool bad = false;
+  if (g == 0 && vbegin[0] != 0) bad = true;
+  if (g == G && vbegin[G] != n) bad = true;
+  if (g < G && vbegin[g] > vbegin[g + 1]) bad = true;
+  if (bad) atomicExch(status, (int)FASTBCC_ERR_INVALID_GRAPH);
+}
+
 template <typename OffT>
 __global__ void k_validate_rows(const OffT* __restrict__ off, int n, int64_t A, int* status) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -563,11 +589,14 @@ __global__ void k_validate_rows(const OffT* __restrict__ off, int n, int64_t A, 
 }
 
 __global__ void k_validate_arcs(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
-                                const int* __restrict__ tile_row, int tw, bool no_loops, int* status) {
+                                const int* __restrict__ tile_row, int tw, bool no_loops, const int* __restrict__ vbegin,
+                                int G, int* status) {
   arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
     if (!ok) return;
     const int y = adj[a];
     bool bad = (y < 0 || y >= n) || (no_loops && y == x);
+    // in a batch every arc stays inside its own graph
+    if (!bad && G > 1 && graph_index(vbegin, G, y) != graph_index(vbegin, G, x)) bad = true;
     if (!bad && a > (int64_t)off[x] && adj[a - 1] > y) bad = true;  // rows sorted
     if (!bad) {
       // x must occur in row y (binary search; rows sorted)
@@ -593,7 +622,9 @@ __global__ void k_cc_init(int* __restrict__ cc, int* __restrict__ hu, int n) {
 
 // Position of the neighbour a vertex samples in round r: a hash of (v, r)
 // over its row, so sampled links do not all point to each row's smallest id
-// (sorted rows would otherwise build long union-find chains).
+// (sorted rows would otherwise build long union-find chains).  The hash is
+// an ad-hoc multiply / xor-shift mix (golden-ratio multiplier for v); the
+// results never depend on which neighbour is sampled, only the speed does.
 __device__ __forceinline__ int64_t sample_pos(int v, int r, int64_t deg) {
   uint32_t h = (uint32_t)v * 0x9E3779B1u ^ (uint32_t)(r + 1) * 0x85EBCA77u;
   h ^= h >> 15;
@@ -1630,16 +1661,6 @@ __global__ void __launch_bounds__(BLOCK) k_bcc_heads(const int4* __restrict__ re
   }
 }
 
-__device__ __forceinline__ int graph_of(const int* __restrict__ vbegin, int G, int v) {
-  int lo = 0, hi = G;  // vbegin[lo] <= v < vbegin[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (vbegin[mid] <= v) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // BCC count of a batch, a wave per graph: the whole BLOCK-vertex blocks
 // inside the graph come from the exclusive scan P of k_bcc_heads' block
 // counts, the partial blocks at its two ends are counted here.
@@ -1739,7 +1760,7 @@ __global__ void __launch_bounds__(BLOCK) k_big_canon(const int* __restrict__ off
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < BLOCK / WAVE; ++w) best = part[w] < best ? part[w] : best;
-    if (best != INT32_MAX && G > 1) best -= off[vbegin[graph_of(vbegin, G, Lb)]];
+    if (best != INT32_MAX && G > 1) best -= off[vbegin[graph_index(vbegin, G, Lb)]];
     scal[S_CANON_BIG] = best == INT32_MAX ? -1 : best;
   }
 }
@@ -1913,7 +1934,7 @@ __global__ void k_canon_first(const int* __restrict__ off, const int* __restrict
     if (lane_id() == j) c = found;
   }
   if (label) {
-    if (G > 1 && c >= 0) c -= off[vbegin[graph_of(vbegin, G, v)]];
+    if (G > 1 && c >= 0) c -= off[vbegin[graph_index(vbegin, G, v)]];
     canon[v] = c;
   }
 }
@@ -2104,7 +2125,7 @@ __global__ void k_bcc_canon(const int4* __restrict__ rec, const int* __restrict_
     return;
   }
   int c = minid[v];
-  if (G > 1) c -= off[vbegin[graph_of(vbegin, G, v)]];
+  if (G > 1) c -= off[vbegin[graph_index(vbegin, G, v)]];
   canon[v] = c;
 }
 
@@ -2142,7 +2163,7 @@ __global__ void k_vertex_labels(const int4* __restrict__ rec, const int* __restr
     const int L = lab[v];
     c = canon[L];
     h = head[L];
-    if (G > 1 && h >= 0) h -= vbegin[graph_of(vbegin, G, v)];
+    if (G > 1 && h >= 0) h -= vbegin[graph_index(vbegin, G, v)];
   }
   if (home) home[v] = c;
   if (home_head) home_head[v] = h;
@@ -2232,7 +2253,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   auto frontier = [&](int* comp, int slot) {
     if (gmark) {
       fill_i32(c, (int*)gmark, 0, cdiv(n, 4));  // n bytes, the allocation is padded to 256
-      LAUNCH(c, k_mark_graph_modes, (unsigned)G, GRAPH_MODE_SAMPLES, comp, vbegin, gmark);
+      LAUNCH(c, k_mark_graph_modes, (unsigned)G, GRAPH_MODE_SAMPLES, comp, vbegin, n, gmark);
     }
     LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark, foff);
     // one scan of the degrees for both the ranks and the starts (the scratch
@@ -2249,7 +2270,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
 
   if (validate) {
     int h = 0;
-    LAUNCH(c, k_validate_arcs, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, no_loops, scal + S_STATUS);
+    LAUNCH(c, k_validate_arcs, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, no_loops, vbegin, G > 1 ? G : 1,
+           scal + S_STATUS);
     if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, c.st) != hipSuccess ||
         hipStreamSynchronize(c.st) != hipSuccess)
       return FASTBCC_ERR_HIP;
@@ -2517,6 +2539,7 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
   const bool no_loops = (flags & FASTBCC_FLAG_NO_SELF_LOOPS) != 0;
   if (validate) {
     LAUNCH(c, k_validate_rows<OffT>, grid_for(n64 + 1), BLOCK, off, n, A, scal + S_STATUS);
+    if (GG > 1) LAUNCH(c, k_validate_vbegin, grid_for((int64_t)GG + 1), BLOCK, vbegin, GG, n, scal + S_STATUS);
     int h = 0;
     if (!c.ok || hipMemcpyAsync(&h, scal + S_STATUS, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)

@@ -211,7 +211,10 @@ __device__ __forceinline__ void uf_link_record(int* p, int u, int v, int* hook_u
 // Hook by hashed priority instead of by id: the root whose (bijectively
 // mixed) id is smaller goes under the other.  Roots are then arbitrary
 // members, which connectivity with forest recording allows, and structured
-// ids (lattices, chains) no longer line up into long hook chains.
+// ids (lattices, chains) no longer line up into long hook chains.  The mixer
+// is the 32-bit finaliser "fmix32" of Austin Appleby's public-domain
+// MurmurHash3 (xor-shift 16, multiply, xor-shift 13, multiply, xor-shift
+// 16); every step is invertible, so distinct ids get distinct priorities.
 __device__ __forceinline__ uint32_t uf_prio(int x) {
   uint32_t h = (uint32_t)x;
   h ^= h >> 16;

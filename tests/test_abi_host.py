@@ -114,6 +114,32 @@ def test_host_tensors_are_refused_not_solved_on_the_cpu():
         solve_batched(torch.tensor([0, 2], dtype=torch.int32), off, adj)
 
 
+def test_host_workspace_vbegin_and_outputs_are_refused():
+    """A host workspace, a host vbegin or host outputs would hand host
+    pointers to the kernels: every wrapper refuses them before any call."""
+    import torch
+
+    from paper_2301_01356_amd import api, read_device_status, solve_traced, vertex_labels
+
+    host_ws = torch.empty(1 << 16, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="GPU"):
+        api._check_workspace(host_ws, 2, 2, 1, None)
+    with pytest.raises(ValueError, match="GPU"):
+        vertex_labels(host_ws, 2, 2)
+    with pytest.raises(ValueError, match="GPU"):
+        read_device_status(host_ws)
+    off = torch.tensor([0, 1, 2], dtype=torch.int32)
+    adj = torch.tensor([1, 0], dtype=torch.int32)
+    with pytest.raises(ValueError, match="GPU"):
+        solve_traced(off, adj, None, vbegin=torch.tensor([0, 2], dtype=torch.int32))
+    with pytest.raises(ValueError, match="GPU"):
+        api._check_tensor(torch.tensor([0, 2], dtype=torch.int32), "vbegin", (torch.int32,))
+    out = api.BccResult(torch.empty(2, dtype=torch.int32), torch.empty(2, dtype=torch.uint8),
+                        torch.empty(1, dtype=torch.int64))
+    with pytest.raises(ValueError, match="GPU"):
+        api._check_result(out, 2, 2, 1, None)
+
+
 def test_binding_constants_match_the_header():
     """Every FASTBCC_FLAG_* / FASTBCC_TUNE_* define and status code of the
     header has the same value in the Python binding."""

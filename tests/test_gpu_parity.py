@@ -334,6 +334,30 @@ def test_validate_flag():
     assert ei.value.status == N.ERR_INVALID_GRAPH
 
 
+def test_validate_batched_graph_ranges():
+    """Under validation a batch's graph ranges must run from 0 to n without
+    decreasing, and no arc may leave its graph; a valid batch still solves."""
+    graphs = [gen.from_edges(4, cycle(4)), gen.from_edges(3, path(3)), gen.from_edges(5, cycle(5))]
+    u = gen.unite(graphs)
+    off, adj = to_dev(u)
+    note("validate batch: valid ranges")
+    r = solve_batched(torch.from_numpy(u.vbegin).to(DEV), off, adj, flags=N.FLAG_VALIDATE)
+    torch.cuda.synchronize()
+    lab, nb = r.edge_label.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for i, g in enumerate(graphs):
+        a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+        want, _, wnb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+        assert np.array_equal(lab[a0:a1], want) and int(nb[i]) == wnb
+    for bad, what in ((np.array([0, 4, 3, 12], np.int32), "decreasing"),
+                      (np.array([0, 4, 7, 11], np.int32), "short of n"),
+                      (np.array([1, 4, 7, 12], np.int32), "not from 0"),
+                      (np.array([0, 3, 7, 12], np.int32), "an arc leaves its graph")):
+        note(f"validate batch: {what}")
+        with pytest.raises(N.FastBccError) as ei:
+            solve_batched(torch.from_numpy(bad).to(DEV), off, adj, flags=N.FLAG_VALIDATE)
+        assert ei.value.status == N.ERR_INVALID_GRAPH, what
+
+
 def test_validate_loop_free_promise():
     """A self-loop is a valid input, but not under the loop-free flag: with
     validation on, breaking that promise is reported as an invalid graph."""
