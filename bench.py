@@ -82,6 +82,31 @@ def alg_bytes(kernel, n, A, deg=None, flags=0):
     return models.get(kernel)
 
 
+# Random word accesses per launch that each land on a cache line of their
+# own (a lower bound: accesses that happen to share a line, and union-find
+# finds longer than one hop, are left out).  Against the measured random-gather
+# rate of the GPU these give a kernel's fraction of its line-rate ceiling.
+def random_accesses(kernel, n, A, deg=None, flags=0):
+    if deg is None:
+        return None
+    import numpy as np
+
+    from paper_2301_01356_amd import _native as N
+
+    live = int((deg > 0).sum())
+    if kernel == "k_tag_sample":
+        codes = {c: k for k, c in N.TAG_SAMPLE_CODES.items()}
+        ks = codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3]
+        # first[] of every sampled neighbour, and the record written by
+        # preorder slot for every vertex with arcs
+        return int(np.minimum(deg, ks).sum()) + live
+    if kernel == "k_cc_sample":
+        # per vertex with arcs: the sampled adjacency word, the parent of the
+        # sampled neighbour and the root word that the hook tests and swaps
+        return 3 * live
+    return None
+
+
 # HBM traffic of the slowest kernels from two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE; KiB per dispatch) on R-MAT scale 25, and the factors a 1 GiB
 # device copy gives the same counters (known bytes / counter).  Valid only for
@@ -119,25 +144,73 @@ def kernel_src_sha():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(sample_scale):
-    """The oracle (Hopcroft-Tarjan, one host thread) on a bounded sample of
-    the same workload recipe: R-MAT at a smaller scale."""
+def cpu_baseline(sample_scale, g=None, gpu=None):
+    """The oracle (Hopcroft-Tarjan, one host thread) on the workload itself
+    (``g``, the benchmarked input) or, with a smaller ``sample_scale``, on a
+    bounded sample of the same recipe (R-MAT at that scale).  When ``gpu``
+    holds the benchmarked solve's (labels, AP flags, #BCC) of ``g``, they must
+    equal the oracle's bit for bit."""
+    import numpy as np
+
     import oracle
     from paper_2301_01356_amd import gen
 
-    g = gen.rmat(scale=sample_scale)
+    whole = g is not None
+    if not whole:
+        g = gen.rmat(scale=sample_scale)
     t0 = time.perf_counter()
-    _, _, nb, tp, th = oracle.ht_bcc(g.offsets, g.adj)
+    lab, ap, nb, tp, th = oracle.ht_bcc(g.offsets, g.adj)
     wall = time.perf_counter() - t0
-    return {
+    what = (f"the benchmarked R-MAT scale {sample_scale} input itself" if whole else
+            f"R-MAT scale {sample_scale} (n=2^{sample_scale}, edge factor 16, same recipe and seed)")
+    out = {
         "value": g.num_arcs / wall,
         "unit": "edges/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"R-MAT scale {sample_scale} (n=2^{sample_scale}, edge factor 16, same recipe and seed), "
-        f"{g.num_arcs} arcs, {nb} BCCs; prep {tp:.2f}s + DFS {th:.2f}s",
+        "sample": f"{what}, {g.num_arcs} arcs, {nb} BCCs; prep {tp:.2f}s + DFS {th:.2f}s",
+        "prep_s": round(tp, 3),
+        "dfs_s": round(th, 3),
         "seconds": wall,
     }
+    if gpu is not None:
+        glab, gap, gnb = gpu
+        out["gpu_equals_oracle"] = bool(gnb == nb and np.array_equal(gap, ap) and np.array_equal(glab, lab))
+    return out
+
+
+def gather_calibration(table_mib=256, count_log2=28):
+    """Random-gather ceiling of this GPU: ``2^count_log2`` int32 reads at
+    uniform random positions of a ``table_mib`` MiB table (one per lane, no
+    reuse to speak of), timed with events.  Every such read that misses the
+    caches moves a whole line, so this rate, not bytes/s, bounds the kernels
+    whose work is one random word per item."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    n_tab = (table_mib << 20) // 4
+    cnt = 1 << count_log2
+    gen_ = torch.Generator(device=dev)
+    gen_.manual_seed(7)
+    tab = torch.arange(n_tab, dtype=torch.int32, device=dev)
+    idx = torch.randint(0, n_tab, (cnt,), dtype=torch.int32, device=dev, generator=gen_)
+    out = torch.empty(cnt, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        torch.index_select(tab, 0, idx, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        torch.index_select(tab, 0, idx, out=out)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(out, idx))
+    del tab, idx, out
+    torch.cuda.empty_cache()
+    return {"table_bytes": n_tab * 4, "gathers": cnt, "ms": round(ms, 4), "gathers_per_s": cnt / (ms * 1e-3),
+            "stream_bytes_per_s": 8 * cnt / (ms * 1e-3), "result_ok": ok}
 
 
 # Every generated input has ascending rows and no self-loops; the solve is
@@ -435,7 +508,9 @@ def main():
     ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--qps", type=float, default=0.0)
-    ap.add_argument("--cpu-sample-scale", type=int, default=22)
+    ap.add_argument("--cpu-sample-scale", type=int, default=25,
+                    help="25: the oracle runs on the benchmarked R-MAT input itself and is compared with the GPU")
+    ap.add_argument("--no-gather-calibration", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=lambda s: int(s, 0), default=0)
     ap.add_argument("--no-tune", action="store_true")
@@ -531,6 +606,32 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     num_bcc = int(out.num_bcc.item())
     log(f"[bench] {args.steps} steps: {ms:.3f} ms/step, {A / ms / 1e6:.2f} G arcs/s, #BCC={num_bcc}")
+    from paper_2301_01356_amd import read_device_status
+
+    status = read_device_status(ws, stream)
+    if status != 0:
+        raise SystemExit(f"[bench] the solve's device-side checks fired (status {status})")
+
+    # what the input promises buy: the same solve under the general input
+    # contract (rows in any order, self-loops allowed), and with the device
+    # validation pass in front (which synchronises the host once per solve)
+    ref_label = out.edge_label.clone()
+    contract = {}
+    for what, f in (("general_contract", args.flags & ~INPUT_FLAGS), ("validated", args.flags | N.FLAG_VALIDATE)):
+        solve(off, adj, out=out, workspace=ws, flags=f, stream=stream)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(args.steps):
+            solve(off, adj, out=out, workspace=ws, flags=f, stream=stream)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(out.edge_label, ref_label)) and int(out.num_bcc.item()) == num_bcc
+        if not same or read_device_status(ws, stream) != 0:
+            raise SystemExit(f"[bench] the {what} solve disagrees with the benchmarked one")
+        contract[what] = {"flags": f, "ms_per_step": c0.elapsed_time(c1) / args.steps, "same_result": same}
+        log(f"[bench] {what}: {contract[what]['ms_per_step']:.3f} ms/step (flags {f:#x})")
+    del ref_label
 
     # the same solve captured once into a HIP graph (the solve enqueues
     # kernels only) and replayed K times: the launch gaps between its kernels
@@ -609,12 +710,30 @@ def main():
     if roofline and roofline["kernel"] != dom_name:
         roofline["note"] = f"slowest kernel {dom_name} has no byte model; reported the slowest modelled one"
 
+    gather = None
+    if not args.no_gather_calibration:
+        gather = gather_calibration()
+        log(f"[bench] random-gather calibration: {gather['gathers_per_s'] / 1e9:.1f} G gathers/s "
+            f"from a {gather['table_bytes'] >> 20} MiB table")
+        for r in [roofline] + modelled[1:3]:
+            lines = r and random_accesses(r["kernel"], n, A, deg, args.flags)
+            if lines:
+                rate = lines / (r["avg_launch_ms"] * 1e-3)
+                r["random_accesses_per_launch"] = int(lines)
+                r["line_rate_frac"] = round(rate / gather["gathers_per_s"], 4)
+
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle on R-MAT scale {args.cpu_sample_scale} ...")
-        cpu = cpu_baseline(args.cpu_sample_scale)
-        log(f"[bench] CPU oracle: {cpu['value'] / 1e6:.1f} M arcs/s in {cpu['seconds']:.1f}s")
+        whole = args.workload == "rmat" and args.cpu_sample_scale == 25
+        log(f"[bench] CPU oracle on {'the benchmarked input' if whole else f'R-MAT scale {args.cpu_sample_scale}'} ...")
+        gpu_res = (out.edge_label.cpu().numpy(), out.is_ap.cpu().numpy(), num_bcc) if whole else None
+        cpu = cpu_baseline(args.cpu_sample_scale, g if whole else None, gpu_res)
+        del gpu_res
+        log(f"[bench] CPU oracle: {cpu['value'] / 1e6:.1f} M arcs/s in {cpu['seconds']:.1f}s"
+            + (f", GPU == oracle: {cpu['gpu_equals_oracle']}" if whole else ""))
         del cpu["seconds"]
+        if whole and not cpu["gpu_equals_oracle"]:
+            raise SystemExit("[bench] the benchmarked solve differs from the oracle")
 
     value = A / (ms * 1e-3)
     line = {
@@ -634,9 +753,12 @@ def main():
                    "edge_convention": "directed arcs (paper Table 1 m)",
                    "undirected_edges_per_s": value / 2, "parallelism": "single GPU",
                    "hip_graph_ms_per_step": ms_graph,
-                   "hip_graph_edges_per_s": A / (ms_graph * 1e-3) if ms_graph else None},
+                   "hip_graph_edges_per_s": A / (ms_graph * 1e-3) if ms_graph else None,
+                   "general_contract_ms_per_step": contract["general_contract"]["ms_per_step"],
+                   "validated_ms_per_step": contract["validated"]["ms_per_step"], "contract": contract},
         "roofline": roofline,
         "rooflines_next": modelled[1:3],
+        "gather_calibration": gather,
         "cpu_baseline": cpu,
     }
     if not args.no_systems and args.workload == "rmat":

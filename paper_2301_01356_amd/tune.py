@@ -70,6 +70,19 @@ def cache_key(arch: str, n: int, arcs: int, graphs: int, skew: str) -> str:
     return f"{arch}|n2^{bucket(n)}|a2^{bucket(arcs)}|g2^{bucket(graphs)}|{skew}"
 
 
+def decode(flags: int) -> Dict:
+    """The tuning fields of a flags word as a configuration (inverse of ``encode``)."""
+    codes = {c: k for k, c in N.TAG_SAMPLE_CODES.items()}
+    sample = (flags >> N.TUNE_SAMPLE_SHIFT) & 0x3
+    lr = (flags >> N.TUNE_LCC_ROUNDS_SHIFT) & 0x3
+    return {"ruler": (flags >> N.TUNE_RULER_SHIFT) & 0xF, "sample": 0 if sample == 3 else sample,
+            "tile": (flags >> N.TUNE_TILE_SHIFT) & 0x7, "uf": int(bool(flags & N.TUNE_CC_PRIORITY)),
+            "ldd": (flags >> N.TUNE_LDD_SHIFT) & 0x3, "tags": int(bool(flags & N.TUNE_SAMPLED_TAGS)),
+            "ts": codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3],
+            "free": int(bool(flags & N.TUNE_FREE_FIRST_ROUND)), "lcc": int(bool(flags & N.TUNE_LCC_PRIORITY)),
+            "lr": lr - 1}
+
+
 def encode(cfg: Dict) -> int:
     return N.tune_flags(ruler_shift=cfg["ruler"], sample_rounds=cfg["sample"], tile_shift=cfg["tile"],
                         cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)),
@@ -170,3 +183,115 @@ def gpu_arch() -> str:
         return getattr(p, "gcnArchName", p.name).split(":")[0]
     except Exception:
         return "unknown"
+
+
+# ------------------------------------------------------------ shipped table
+# Benchmark workloads whose tuned configurations ship in ``tuned_gfx950.json``.
+# Every generated input has ascending, loop-free rows, and the solve is told so.
+SHIP_WORKLOADS = ("rmat25", "grid", "plain", "batch4096", "knn2", "knn5", "knn10", "knn15", "knn20")
+
+
+def generated_input_flags() -> int:
+    return N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
+
+
+def workload_runner(name: str, device="cuda:0"):
+    """(cache key, time_ms(flags)) for a named benchmark workload whose input
+    is put on the GPU once; ``time_ms`` times one solve with HIP events on
+    the solve's stream (the batch: one launch sequence of the batched solve,
+    as the benchmark times it)."""
+    import torch
+
+    from . import gen
+    from .api import BccResult, alloc_workspace, solve
+
+    dev = torch.device(device)
+    promises = generated_input_flags()
+    if name == "batch4096":
+        from .batch import BatchedSolver
+
+        u = gen.batch()
+        G = len(u.vbegin) - 1
+        graphs = []
+        for i in range(G):
+            v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
+            a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
+            graphs.append(gen.Csr(v1 - v0, u.offsets[v0 : v1 + 1] - a0, u.adj[a0:a1] - v0))
+        solver = BatchedSolver(u.n + 1, u.num_arcs, G, device=dev, use_graph=False)
+        solver.stage(graphs)
+        solver.launch()
+        solver.done.synchronize()
+
+        def run_batch(flags):
+            solver.flags = flags | promises
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(solver.stream)
+            solver._launch()
+            e1.record(solver.stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1)
+
+        return cache_key(gpu_arch(), u.n, u.num_arcs, G, skew_class(np.diff(u.offsets))), run_batch
+    g = {"rmat25": gen.rmat, "grid": gen.grid, "plain": gen.plain}.get(name, lambda: gen.config(name))()
+    off = torch.from_numpy(g.offsets if name == "rmat25" else g.offsets32()).to(dev)
+    adj = torch.from_numpy(g.adj).to(dev)
+    ws = alloc_workspace(g.n, g.num_arcs, 1, dev)
+    out = BccResult(torch.empty(g.num_arcs, dtype=torch.int32, device=dev),
+                    torch.empty(g.n, dtype=torch.uint8, device=dev), torch.empty(1, dtype=torch.int64, device=dev))
+    st = torch.cuda.current_stream(dev)
+
+    def run_one(flags):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        solve(off, adj, out=out, workspace=ws, flags=flags | promises, stream=st)
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    return cache_key(gpu_arch(), g.n, g.num_arcs, 1, skew_class(np.diff(g.offsets))), run_one
+
+
+def ship(names, path: str = SHIPPED, out: Optional[str] = None) -> Dict[str, Dict]:
+    """Tune each named workload from scratch on this GPU and record the pick,
+    tagged with its workload, in the shipped table read from ``path`` and
+    written to ``out`` (default: ``path``)."""
+    import torch
+
+    out = out or path
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    for name in names:
+        key, run = workload_runner(name)
+        t = Tuner(cache_path=None, shipped=None)
+        flags = t.tune(key, run, force=True)
+        for k in [k for k, e in table.items() if e.get("workload") == name]:
+            del table[k]
+        table[key] = dict(t.cache[key], workload=name, source="shipped")
+        print(f"{name}: {key} -> {flags:#x} {table[key]}", flush=True)
+        del run
+        torch.cuda.empty_cache()
+        tmp = out + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, out)
+    return table
+
+
+def shipped_entries(path: str = SHIPPED) -> Dict[str, Dict]:
+    """{workload name: (flags, entry)} of the shipped table."""
+    with open(path) as f:
+        table = json.load(f)
+    return {e["workload"]: (encode(e), e) for e in table.values() if "workload" in e}
+
+
+if __name__ == "__main__":
+    import argparse
+
+    ap = argparse.ArgumentParser(description="tune benchmark workloads and record the picks in the shipped table")
+    ap.add_argument("command", choices=["ship"])
+    ap.add_argument("workloads", nargs="*", default=list(SHIP_WORKLOADS))
+    ap.add_argument("--out", default=None, help="write the table here instead of over the shipped one")
+    a = ap.parse_args()
+    ship(a.workloads, out=a.out)

@@ -66,3 +66,13 @@ def test_recorded_counters_are_whole():
     # write counter cannot be below that
     assert kernels["k_bcc_rows"]["write_kib"] * 1024 >= 4 * 1_047_198_154
     assert len(c["src_sha"]) == 16
+
+
+def test_random_access_models():
+    deg = np.array([0, 1, 2, 3, 5, 100])
+    flags = N.tune_flags(sampled_tags=True, tag_samples=2)
+    # first[] of min(deg, 2) neighbours per row plus one slot write per vertex with arcs
+    assert bench.random_accesses("k_tag_sample", 6, int(deg.sum()), deg, flags) == (0 + 1 + 2 + 2 + 2 + 2) + 5
+    assert bench.random_accesses("k_cc_sample", 6, int(deg.sum()), deg, flags) == 3 * 5
+    assert bench.random_accesses("k_bcc_rows", 6, int(deg.sum()), deg, flags) is None
+    assert bench.random_accesses("k_tag_sample", 6, 0) is None

@@ -1,5 +1,10 @@
-"""Full-size parity: the benchmark workloads at their real sizes, in the
-launch configurations the benchmark times, against the full CPU oracle."""
+"""Full-size parity: every benchmark workload at its real size, in the launch
+configurations the benchmark times -- the tuned flags shipped in
+``tuned_gfx950.json`` together with the input promises every generated graph
+keeps (ascending, loop-free rows) -- against the full CPU oracle.  The same
+inputs also run under the general input contract (no promises) and with
+device-side validation.  After every solve the device status word (the
+solve's in-kernel invariant checks) must read 0."""
 import sys
 
 import numpy as np
@@ -8,10 +13,13 @@ import torch
 
 import oracle
 from paper_2301_01356_amd import _native as N
-from paper_2301_01356_amd import gen, solve, solve_batched
+from paper_2301_01356_amd import alloc_workspace, gen, read_device_status, solve, solve_batched
+from paper_2301_01356_amd.tune import SHIP_WORKLOADS, shipped_entries
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
+PROMISES = N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
+SHIPPED = shipped_entries()
 
 
 def note(msg):
@@ -19,74 +27,108 @@ def note(msg):
     sys.stdout.flush()
 
 
+def shipped_flags(name):
+    assert name in SHIPPED, f"no shipped tuning entry for the {name} workload"
+    return SHIPPED[name][0]
+
+
+def gpu_solve(g, flags, off64=False):
+    off = torch.from_numpy(g.offsets if off64 else g.offsets32()).to(DEV)
+    adj = torch.from_numpy(g.adj).to(DEV)
+    ws = alloc_workspace(g.n, g.num_arcs, 1, DEV)
+    r = solve(off, adj, workspace=ws, flags=flags)
+    assert read_device_status(ws) == 0, f"a device-side invariant check fired (flags {flags:#x})"
+    got = (r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), int(r.num_bcc.item()))
+    del off, adj, ws, r
+    torch.cuda.empty_cache()
+    return got
+
+
+def assert_same(ref, got, what):
+    lab, ap, nb = ref
+    glab, gap, gnb = got
+    assert gnb == nb, f"{what}: num_bcc {gnb} != {nb}"
+    assert np.array_equal(gap, ap), f"{what}: articulation points differ"
+    bad = np.flatnonzero(glab != lab)
+    assert bad.size == 0, f"{what}: {bad.size} labels differ, first at arc {bad[0]}"
+
+
+def run_single(name, g, off64, flag_sets):
+    outs = []
+    for what, flags in flag_sets:
+        note(f"{name}: GPU solve ({what}) flags={flags:#x}")
+        outs.append((what, flags, gpu_solve(g, flags, off64)))
+    note(f"{name}: oracle")
+    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+    for what, flags, got in outs:
+        assert_same((lab, ap, nb), got, f"{name} {what} {flags:#x}")
+
+
 def test_rmat25_full_size_exact():
+    """The headline input: the benchmarked configuration (shipped flags with
+    the input promises, int64 offsets), the same flags under the general
+    input contract and with validation, the defaults, and other variants."""
+    f = shipped_flags("rmat25")
     note("R-MAT scale 25: generate")
     g = gen.rmat()
-    off = torch.from_numpy(g.offsets).to(DEV)  # int64 offsets, as benchmarked
-    adj = torch.from_numpy(g.adj).to(DEV)
-    outs = []
-    # the defaults, the variants, and the configurations the autotuner picks for
-    # this graph in the benchmark (sorted loop-free rows, certified tags, free
-    # first round, no Last-CC sampling rounds)
-    for flags in (0, N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True), N.tune_flags(ldd=1),
-                  N.FLAG_SORTED_ROWS | N.tune_flags(sampled_tags=True, cc_priority=True),
-                  N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
-                  | N.tune_flags(ruler_shift=4, sample_rounds=2, tile_shift=4, sampled_tags=True, tag_samples=2,
-                                 free_first_round=True, lcc_rounds=0),
-                  N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
-                  | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True,
-                                                    sampled_tags=True, tag_samples=3, free_first_round=True,
-                                                    lcc_priority=True)):
-        note(f"R-MAT scale 25: GPU solve flags={flags:#x}")
-        r = solve(off, adj, flags=flags)
-        torch.cuda.synchronize()
-        outs.append((r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), int(r.num_bcc.item())))
-        del r
-    del off, adj
-    torch.cuda.empty_cache()
-    note("R-MAT scale 25: oracle")
-    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
-    for glab, gap, gnb in outs:
-        assert gnb == nb
-        assert np.array_equal(gap, ap)
-        bad = np.flatnonzero(glab != lab)
-        assert bad.size == 0, f"{bad.size} labels differ, first at arc {bad[0]}"
+    run_single("R-MAT scale 25", g, True, [
+        ("benchmarked", f | PROMISES),
+        ("general contract", f),
+        ("validated", f | PROMISES | N.FLAG_VALIDATE),
+        ("defaults", 0),
+        ("priority union-find, exact tags", N.FLAG_SORTED_ROWS
+         | N.tune_flags(ruler_shift=6, sample_rounds=2, tile_shift=4, cc_priority=True)),
+        ("decomposition", N.tune_flags(ldd=1)),
+    ])
+
+
+@pytest.mark.parametrize("name", ["grid", "plain"])
+def test_grid_and_plain_full_size_exact(name):
+    f = shipped_flags(name)
+    note(f"{name}: generate")
+    g = gen.config(name)
+    run_single(name, g, False, [("benchmarked", f | PROMISES), ("general contract", f), ("defaults", 0)])
+
+
+@pytest.mark.parametrize("k", [2, 5, 10, 15, 20])
+def test_knn_sweep_full_size_exact(k):
+    f = shipped_flags(f"knn{k}")
+    note(f"k-NN 2^22 points, k={k}: generate")
+    g = gen.config(f"knn{k}")
+    sets = [("benchmarked", f | PROMISES)]
+    if k in (2, 20):
+        sets.append(("defaults", 0))
+    run_single(f"knn{k}", g, False, sets)
 
 
 def test_batch4096_full_size_exact():
+    """The 4096-graph batch in the benchmarked configuration (shipped flags,
+    input promises), under the general contract and with the defaults."""
+    f = shipped_flags("batch4096")
     note("batch of 4096: generate")
     u = gen.batch()
     vb = torch.from_numpy(u.vbegin).to(DEV)
     off = torch.from_numpy(u.offsets32()).to(DEV)
     adj = torch.from_numpy(u.adj).to(DEV)
+    G = len(u.vbegin) - 1
+    ws = alloc_workspace(u.n, u.num_arcs, G, DEV)
     outs = []
-    for flags in (0, N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS
-                  | N.tune_flags(cc_priority=True, free_first_round=True, lcc_priority=True)):
-        note(f"batch of 4096: GPU batched solve flags={flags:#x}")
-        r = solve_batched(vb, off, adj, flags=flags)
-        torch.cuda.synchronize()
-        outs.append((r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()))
+    for what, flags in (("benchmarked", f | PROMISES), ("general contract", f), ("defaults", 0)):
+        note(f"batch of 4096: GPU batched solve ({what}) flags={flags:#x}")
+        r = solve_batched(vb, off, adj, workspace=ws, flags=flags)
+        assert read_device_status(ws) == 0, f"a device-side invariant check fired ({what})"
+        outs.append((what, r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()))
         del r
     note("batch of 4096: oracle per graph")
-    for i in range(len(u.vbegin) - 1):
+    for i in range(G):
         v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
         a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
         olab, oap, onb, _, _ = oracle.ht_bcc(u.offsets[v0 : v1 + 1] - a0, u.adj[a0:a1] - v0)
-        for lab, ap, nb in outs:
-            assert int(nb[i]) == onb, f"graph {i}"
-            assert np.array_equal(ap[v0:v1], oap), f"graph {i}"
-            assert np.array_equal(lab[a0:a1], olab), f"graph {i}"
+        for what, lab, ap, nb in outs:
+            assert int(nb[i]) == onb, f"graph {i} ({what})"
+            assert np.array_equal(ap[v0:v1], oap), f"graph {i} ({what})"
+            assert np.array_equal(lab[a0:a1], olab), f"graph {i} ({what})"
 
 
-@pytest.mark.parametrize("k", [2, 20])
-def test_knn_sweep_endpoints_full_size_exact(k):
-    note(f"k-NN 2^22 points, k={k}")
-    g = gen.config(f"knn{k}")
-    off = torch.from_numpy(g.offsets32()).to(DEV)
-    adj = torch.from_numpy(g.adj).to(DEV)
-    r = solve(off, adj)
-    torch.cuda.synchronize()
-    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
-    assert int(r.num_bcc.item()) == nb
-    assert np.array_equal(r.is_ap.cpu().numpy(), ap)
-    assert np.array_equal(r.edge_label.cpu().numpy(), lab)
+def test_shipped_table_names_every_benchmark_workload():
+    assert sorted(SHIPPED) == sorted(SHIP_WORKLOADS)

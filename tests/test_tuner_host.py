@@ -71,3 +71,15 @@ def test_shipped_configurations_are_used_without_timing(tmp_path):
     own = tune.Tuner(cache_path=None)
     for key, cfg in own.shipped.items():
         assert tune.encode(cfg) >= 0, key
+
+
+def test_decode_inverts_encode():
+    from paper_2301_01356_amd.tune import LCC_ROUNDS, SEEDS, decode, encode
+
+    for c in SEEDS:
+        assert decode(encode(c)) == c
+    for lr in LCC_ROUNDS:
+        c = dict(SEEDS[1], lr=lr, ts=3, tags=1, uf=1, ldd=2, sample=0)
+        assert decode(encode(c)) == c
+    # the input-promise and validation bits are no tuning fields
+    assert decode(encode(SEEDS[2]) | 0x7) == SEEDS[2]
