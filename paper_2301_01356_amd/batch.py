@@ -1,17 +1,31 @@
-"""Batched solving: many graphs, one launch sequence, replayed as a HIP graph.
+"""Batched solving: many graphs, one launch sequence.
 
 A batch is a disjoint union of graphs in one CSR (graph g owns a contiguous
 vertex range; its arcs hold global ids).  ``fastbcc_solve_batched`` solves the
-union in one launch sequence and returns graph-local labels; this module adds
-fixed-capacity device buffers and captures that sequence once into a HIP
-graph (torch's CUDA-graph API drives hipStreamBeginCapture on ROCm), so each
-later batch costs one graph launch.  The solve issues no host synchronisation
-and no memset, only kernels, which is what makes it capturable.
+union in one launch sequence and returns graph-local labels.  This module
+keeps device-resident buffers for a batch and moves only what a batch uses:
 
-A batch smaller than the capacity is padded: one extra padding graph takes
-the unused vertices, and its last vertex holds the unused arcs as self-loops
-(label -1, no BCC, no articulation point), so the captured shapes never
-change.
+* host side, each graph's own CSR (graph-local ids) is copied into pinned
+  staging memory, or, when the graph already lives in pinned memory
+  (``PinnedGraph``), copied to the device straight from there;
+* device side, the graph's vertex and arc offsets are added to its ids and
+  offsets by two element-wise passes over the used prefix.
+
+Two modes:
+
+* exact (``exact=True``): the batched solve runs eagerly on exactly the
+  vertices, arcs and graphs of the batch -- what a serving slot does;
+* fixed shape (default): the buffers always hold ``max_vertices`` vertices,
+  ``max_arcs`` arcs and ``max_graphs + 1`` graphs, so the launch sequence can
+  be captured once into a HIP graph (torch's CUDA-graph API drives
+  hipStreamBeginCapture on ROCm) and replayed for every later batch.  The
+  unused part is one padding graph: empty rows, and the unused arcs as
+  parallel copies of one edge between its last two vertices (a 2-cycle: one
+  BCC of its own, no articulation point), so the padding keeps rows sorted
+  and free of self-loops; only an odd leftover arc becomes a self-loop.
+
+The solve issues no host synchronisation and no memset, only kernels, which
+is what makes it capturable.
 """
 from __future__ import annotations
 
@@ -27,21 +41,52 @@ from .api import BccResult, alloc_workspace, solve_batched
 
 @dataclass
 class GraphResult:
-    edge_label: np.ndarray  # int32, graph-local arc ids
-    is_ap: np.ndarray  # uint8
+    edge_label: Optional[np.ndarray]  # int32, graph-local arc ids (None when not kept)
+    is_ap: Optional[np.ndarray]  # uint8
     num_bcc: int
+    digest: Optional[int] = None  # device-side fingerprint of the labels and AP flags
+
+
+class PinnedGraph:
+    """A host CSR graph whose arrays live in pinned memory, so a batch copies
+    it to the device without a staging copy (``.n``, ``.offsets``, ``.adj`` as
+    numpy views of the pinned buffers, int32)."""
+
+    def __init__(self, g):
+        n, A = int(g.n), int(g.offsets[-1])
+        self.n = n
+        self.t_off = torch.empty(n + 1, dtype=torch.int32, pin_memory=True)
+        self.t_adj = torch.empty(max(A, 1), dtype=torch.int32, pin_memory=True)[:A]
+        self.offsets = self.t_off.numpy()
+        self.adj = self.t_adj.numpy()
+        self.offsets[:] = np.asarray(g.offsets)
+        self.adj[:] = np.asarray(g.adj)
+
+    @property
+    def num_arcs(self) -> int:
+        return int(self.adj.shape[0])
+
+
+def pad_layout(used_v: int, used_a: int, cap_v: int, cap_a: int):
+    """Where the padding graph puts the leftover arcs: (row start of vertex
+    cap_v - 2, row start of vertex cap_v - 1, arcs per direction of the
+    parallel edge, whether one self-loop closes an odd leftover)."""
+    left = cap_a - used_a
+    half = left // 2
+    return used_a, used_a + half, half, bool(left & 1)
 
 
 def pack(graphs: Sequence, max_vertices: int, max_arcs: int, max_graphs: int):
-    """Concatenate host CSR graphs (objects with .n, .offsets, .adj) into
-    padded union arrays: (vbegin int32[max_graphs+2], offsets int32[max_vertices+1],
-    adj int32[max_arcs], per-graph (vbegin, abegin))."""
+    """The padded union on the host (what the fixed-shape device buffers hold
+    after a batch is staged): (vbegin int32[max_graphs+2], offsets
+    int32[max_vertices+1], adj int32[max_arcs], per-graph (v0, v1, a0, a1))."""
     G = len(graphs)
     if G > max_graphs:
         raise ValueError(f"{G} graphs exceed the capacity {max_graphs}")
     nv = sum(int(g.n) for g in graphs)
     na = sum(int(g.offsets[-1]) for g in graphs)
-    if nv > max_vertices - 1 or na > max_arcs:
+    spare = 2 if na < max_arcs else 1
+    if nv > max_vertices - spare or na > max_arcs:
         raise ValueError("batch exceeds the vertex/arc capacity")
     vbegin = np.zeros(max_graphs + 2, np.int32)
     offsets = np.empty(max_vertices + 1, np.int32)
@@ -56,26 +101,55 @@ def pack(graphs: Sequence, max_vertices: int, max_arcs: int, max_graphs: int):
         spans.append((v0, v0 + n, a0, a0 + A))
         v0 += n
         a0 += A
-    # padding graph(s): empty graphs up to max_graphs, then one graph holding
-    # the remaining vertices; its last vertex carries the leftover arcs as loops
     vbegin[G : max_graphs + 1] = v0
     vbegin[max_graphs + 1] = max_vertices
+    r2, r1, half, odd = pad_layout(v0, a0, max_vertices, max_arcs)
     offsets[v0:max_vertices] = a0
-    offsets[max_vertices - 1] = a0
+    if max_arcs > a0:
+        offsets[max_vertices - 1] = r1
+        adj[r2:r1] = max_vertices - 1
+        adj[r1 : r1 + half] = max_vertices - 2
+        if odd:
+            adj[max_arcs - 1] = max_vertices - 1
     offsets[max_vertices] = max_arcs
-    adj[a0:] = max_vertices - 1
     return vbegin, offsets, adj, spans
 
 
+def device_digests(label: torch.Tensor, is_ap: torch.Tensor, abound: torch.Tensor, vbound: torch.Tensor):
+    """Per-graph fingerprint, computed on the device, of graph-local labels
+    and AP flags of consecutive graphs (arc and vertex bounds int64[G+1]):
+    sum over the graph's arcs of (label + 2) * (local arc index + 1) plus
+    sum over its vertices of ap * (local vertex index + 1), in wrapping
+    int64 arithmetic.  Equal results give equal digests; the serving
+    benchmark compares them between served and serial solves."""
+    dev = label.device
+
+    def seg(vals: torch.Tensor, bound: torch.Tensor):
+        m = vals.numel()
+        idx = torch.arange(1, m + 1, dtype=torch.int64, device=dev)
+        c1 = torch.zeros(m + 1, dtype=torch.int64, device=dev)
+        c0 = torch.zeros(m + 1, dtype=torch.int64, device=dev)
+        torch.cumsum(vals * idx, 0, out=c1[1:])
+        torch.cumsum(vals, 0, out=c0[1:])
+        lo, hi = bound[:-1], bound[1:]
+        # sum (x) * (global + 1) - start * sum (x) = sum (x) * (local + 1)
+        return (c1[hi] - c1[lo]) - lo * (c0[hi] - c0[lo])
+
+    return seg(label.to(torch.int64) + 2, abound) + seg(is_ap.to(torch.int64), vbound)
+
+
 class BatchedSolver:
-    """Fixed-capacity batched solver with optional HIP-graph replay."""
+    """Device-resident batch buffers, exact or fixed-shape (HIP-graph replay)."""
 
     def __init__(self, max_vertices: int, max_arcs: int, max_graphs: int, device="cuda:0", flags: int = 0,
-                 use_graph: bool = True, stream: Optional[torch.cuda.Stream] = None):
+                 use_graph: bool = True, stream: Optional[torch.cuda.Stream] = None, exact: bool = False,
+                 digests: bool = False):
         self.cap_v, self.cap_a, self.cap_g = int(max_vertices), int(max_arcs), int(max_graphs)
         self.device = torch.device(device)
         self.flags = flags
-        self.use_graph = use_graph
+        self.exact = exact
+        self.use_graph = use_graph and not exact
+        self.digests = digests
         G1 = self.cap_g + 1  # + the padding graph
         dev = self.device
         self.d_vbegin = torch.empty(G1 + 1, dtype=torch.int32, device=dev)
@@ -89,22 +163,23 @@ class BatchedSolver:
         self.ws = alloc_workspace(self.cap_v, self.cap_a, G1, dev)
         # pinned staging for host<->device copies
         self.h_vbegin = torch.empty(G1 + 1, dtype=torch.int32, pin_memory=True)
+        self.h_bounds = torch.empty(2 * (G1 + 1), dtype=torch.int64, pin_memory=True)
         self.h_off = torch.empty(self.cap_v + 1, dtype=torch.int32, pin_memory=True)
         self.h_adj = torch.empty(self.cap_a, dtype=torch.int32, pin_memory=True)
         self.h_label = torch.empty(self.cap_a, dtype=torch.int32, pin_memory=True)
         self.h_ap = torch.empty(self.cap_v, dtype=torch.uint8, pin_memory=True)
         self.h_nb = torch.empty(G1, dtype=torch.int64, pin_memory=True)
+        self.h_dig = torch.empty(G1, dtype=torch.int64, pin_memory=True)
         self.stream = stream or torch.cuda.Stream(device=dev)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.done = torch.cuda.Event()
         self.spans: List[tuple] = []
+        self._copies: List[tuple] = []
+        self._keep_host = True
         # the device buffers always hold a valid (padded) CSR: start with the
         # empty batch so no launch can ever read uninitialised memory
         self.stage([])
-        with torch.cuda.stream(self.stream):
-            self.d_vbegin.copy_(self.h_vbegin, non_blocking=True)
-            self.d_off.copy_(self.h_off, non_blocking=True)
-            self.d_adj.copy_(self.h_adj, non_blocking=True)
+        self._copy_in()
         self.stream.synchronize()
 
     @staticmethod
@@ -112,9 +187,103 @@ class BatchedSolver:
         ws = N.workspace_size(max_vertices, max_arcs, max_graphs + 1)
         return ws + 2 * 4 * max_arcs + 5 * max_vertices + 8 * (max_graphs + 2) + 4 * (max_graphs + 2)
 
+    # ------------------------------------------------------------ staging
+    def stage(self, graphs: Sequence) -> None:
+        """Lay the graphs out for the next launch: per graph its vertex and
+        arc range; its CSR is copied into pinned staging now unless it lives
+        in pinned memory already (then the launch copies it from there)."""
+        G = len(graphs)
+        if G > self.cap_g:
+            raise ValueError(f"{G} graphs exceed the capacity {self.cap_g}")
+        spans, copies = [], []
+        v0 = a0 = 0
+        for g in graphs:
+            n, A = int(g.n), int(g.offsets[-1])
+            spans.append((v0, v0 + n, a0, a0 + A))
+            v0 += n
+            a0 += A
+        spare = 0 if self.exact else (2 if a0 < self.cap_a else 1)
+        if v0 > self.cap_v - spare or a0 > self.cap_a:
+            raise ValueError("batch exceeds the vertex/arc capacity")
+        hoff, hadj = self.h_off.numpy(), self.h_adj.numpy()
+        for g, (s0, s1, b0, b1) in zip(graphs, spans):
+            if isinstance(g, PinnedGraph):
+                copies.append((s0, s1, b0, b1, g.t_off, g.t_adj))
+            else:
+                hoff[s0:s1] = np.asarray(g.offsets[: s1 - s0])
+                hadj[b0:b1] = np.asarray(g.adj)
+                copies.append((s0, s1, b0, b1, None, None))
+        vb = self.h_vbegin.numpy()
+        vb[:G] = [s[0] for s in spans]
+        vb[G : self.cap_g + 1] = v0
+        vb[self.cap_g + 1] = self.cap_v
+        bd = self.h_bounds.numpy()
+        bd[: G + 1] = [s[2] for s in spans] + [a0]
+        bd[G + 1 : 2 * G + 2] = [s[0] for s in spans] + [v0]
+        self.spans, self._copies = spans, copies
+        self.used_v, self.used_a = v0, a0
+
+    def _copy_in(self) -> None:
+        """On this solver's stream: the staged graphs into the device buffers,
+        their ids and offsets made global, and (fixed shape) the padding."""
+        s = self.stream
+        G, v0, a0 = len(self.spans), self.used_v, self.used_a
+        with torch.cuda.stream(s):
+            self.d_vbegin.copy_(self.h_vbegin, non_blocking=True)
+            # staged graphs sit contiguously in the staging buffers: copy each
+            # run of them at once, pinned-source graphs one by one
+            run = None
+            for (s0, s1, b0, b1, toff, tadj) in self._copies + [(v0, v0, a0, a0, False, None)]:
+                if toff is None:
+                    run = (s0, b0) if run is None else run
+                    continue
+                if run is not None:
+                    r0, rb = run
+                    if s0 > r0:
+                        self.d_off[r0:s0].copy_(self.h_off[r0:s0], non_blocking=True)
+                    if b0 > rb:
+                        self.d_adj[rb:b0].copy_(self.h_adj[rb:b0], non_blocking=True)
+                    run = None
+                if toff is not False:
+                    if s1 > s0:
+                        self.d_off[s0:s1].copy_(toff[: s1 - s0], non_blocking=True)
+                    if b1 > b0:
+                        self.d_adj[b0:b1].copy_(tadj, non_blocking=True)
+            if G:
+                # graph-local -> global: add each graph's first vertex to its
+                # arcs' targets and its first arc to its row starts
+                bd = self.h_bounds[: 2 * G + 2].to(self.device, non_blocking=True)
+                ab, vbd = bd[: G + 1], bd[G + 1 :]
+                if a0:
+                    self.d_adj[:a0] += torch.repeat_interleave(vbd[:G], ab[1:] - ab[:G], output_size=a0).to(torch.int32)
+                if v0:
+                    self.d_off[:v0] += torch.repeat_interleave(ab[:G], vbd[1:] - vbd[:G], output_size=v0).to(torch.int32)
+                self._bounds = (ab, vbd)
+            if self.exact:
+                self.d_off[v0 : v0 + 1].fill_(a0)
+            else:
+                r2, r1, half, odd = pad_layout(v0, a0, self.cap_v, self.cap_a)
+                self.d_off[v0 : self.cap_v].fill_(a0)
+                self.d_off[self.cap_v : self.cap_v + 1].fill_(self.cap_a)
+                if self.cap_a > a0:
+                    self.d_off[self.cap_v - 1 : self.cap_v].fill_(r1)
+                    self.d_adj[r2:r1].fill_(self.cap_v - 1)
+                    self.d_adj[r1 : r1 + half].fill_(self.cap_v - 2)
+                    if odd:
+                        self.d_adj[self.cap_a - 1 :].fill_(self.cap_v - 1)
+
+    # ------------------------------------------------------------ solving
     def _launch(self):
-        solve_batched(self.d_vbegin, self.d_off, self.d_adj, out=self.out, workspace=self.ws, flags=self.flags,
-                      stream=self.stream)
+        if self.exact:
+            G, v, a = len(self.spans), self.used_v, self.used_a
+            if G == 0:
+                return
+            out = BccResult(self.out.edge_label[:a], self.out.is_ap[:v], self.out.num_bcc[:G])
+            solve_batched(self.d_vbegin[: G + 1], self.d_off[: v + 1], self.d_adj[:a], out=out, workspace=self.ws,
+                          flags=self.flags, stream=self.stream)
+        else:
+            solve_batched(self.d_vbegin, self.d_off, self.d_adj, out=self.out, workspace=self.ws, flags=self.flags,
+                          stream=self.stream)
 
     def _ensure_graph(self):
         if not self.use_graph or self.graph is not None:
@@ -129,52 +298,56 @@ class BatchedSolver:
         self.stream.synchronize()
         self.graph = g
 
-    def stage(self, graphs: Sequence) -> None:
-        """Pack host graphs into the pinned staging buffers."""
-        vb, off, adj, spans = pack(graphs, self.cap_v, self.cap_a, self.cap_g)
-        self.h_vbegin.numpy()[:] = vb
-        self.h_off.numpy()[:] = off
-        self.h_adj.numpy()[:] = adj
-        self.spans = spans
-
-    def launch(self) -> None:
+    def launch(self, keep_host: bool = True) -> None:
         """Copy the staged batch in, solve, copy results out -- all
         asynchronous on this solver's stream; ``self.done`` marks the end.
-        Inputs are copied BEFORE any solve (the first call also runs one eager
-        solve and captures the graph, both on the copied batch)."""
+        Inputs are copied BEFORE any solve (the first call in fixed-shape mode
+        also runs one eager solve and captures the graph, both on the copied
+        batch).  ``keep_host=False`` copies only the counts (and digests)
+        back, not the labels and AP flags."""
         s = self.stream
-        with torch.cuda.stream(s):
-            self.d_vbegin.copy_(self.h_vbegin, non_blocking=True)
-            self.d_off.copy_(self.h_off, non_blocking=True)
-            used_a = self.spans[-1][3] if self.spans else 0
-            if used_a:
-                self.d_adj[:used_a].copy_(self.h_adj[:used_a], non_blocking=True)
-            # padding arcs: self-loops on the last vertex (device fill)
-            if used_a < self.cap_a:
-                self.d_adj[used_a:].fill_(self.cap_v - 1)
+        self._copy_in()
         self._ensure_graph()
+        G, v, a = len(self.spans), self.used_v, self.used_a
         with torch.cuda.stream(s):
             if self.graph is not None:
                 self.graph.replay()
             else:
                 self._launch()
-            if used_a:
-                self.h_label[:used_a].copy_(self.out.edge_label[:used_a], non_blocking=True)
-            self.h_ap.copy_(self.out.is_ap, non_blocking=True)
-            self.h_nb.copy_(self.out.num_bcc, non_blocking=True)
+            if self.digests and G:
+                ab, vbd = self._bounds
+                dig = device_digests(self.out.edge_label[:a], self.out.is_ap[:v], ab, vbd)
+                self.h_dig[:G].copy_(dig, non_blocking=True)
+            if keep_host:
+                if a:
+                    self.h_label[:a].copy_(self.out.edge_label[:a], non_blocking=True)
+                if v:
+                    self.h_ap[:v].copy_(self.out.is_ap[:v], non_blocking=True)
+            if G:
+                self.h_nb[:G].copy_(self.out.num_bcc[:G], non_blocking=True)
             self.done.record(s)
+        self._keep_host = keep_host
 
     def ready(self) -> bool:
         return self.done.query()
 
-    def results(self) -> List[GraphResult]:
+    def results(self, copy: bool = True) -> List[GraphResult]:
+        """Per-graph results of the last launch.  ``copy=False`` returns views
+        of the pinned host buffers, valid until the next launch."""
         self.done.synchronize()
         lab = self.h_label.numpy()
         ap = self.h_ap.numpy()
         nb = self.h_nb.numpy()
+        dig = self.h_dig.numpy()
         out = []
         for i, (v0, v1, a0, a1) in enumerate(self.spans):
-            out.append(GraphResult(lab[a0:a1].copy(), ap[v0:v1].copy(), int(nb[i])))
+            if self._keep_host:
+                gl, ga = lab[a0:a1], ap[v0:v1]
+                if copy:
+                    gl, ga = gl.copy(), ga.copy()
+            else:
+                gl = ga = None
+            out.append(GraphResult(gl, ga, int(nb[i]), int(dig[i]) if self.digests else None))
         return out
 
     def solve(self, graphs: Sequence) -> List[GraphResult]:

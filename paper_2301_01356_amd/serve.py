@@ -7,7 +7,12 @@ capacity and (b) the HBM budget still free, packs those graphs into one batch
 and launches it.  Requests that arrive while other batches are on the GPU
 join the next batch as soon as a slot and memory free up; several slots
 (each with its own HIP stream and device-resident buffers) keep copies and
-kernels of different batches overlapping on the device.
+kernels of different batches overlapping on the device.  The budget is
+re-read from the live free HBM (``free_hbm``) whenever a slot completes.
+
+Slots solve under the general input contract (rows in any order, self-loops
+allowed): a request is not trusted to keep the sorted-row or loop-free
+promises, only its ids are range-checked at admission.
 
 Malformed requests are rejected at admission (status set on that request
 only); an oversized request that no slot can hold is rejected the same way.
@@ -44,6 +49,7 @@ class Completion:
     arrival: float = 0.0
     admitted: float = 0.0
     finished: float = 0.0
+    digest: Optional[int] = None
 
     @property
     def latency(self) -> float:
@@ -86,7 +92,7 @@ class Slot:
     cap_a: int
     cap_g: int
 
-    def launch(self, graphs: Sequence) -> None: ...
+    def launch(self, graphs: Sequence, keep: Optional[Sequence[bool]] = None) -> None: ...
     def ready(self) -> bool: ...
     def results(self) -> list: ...
 
@@ -114,15 +120,38 @@ class _Inflight:
 
 
 class Server:
+    """``hbm_budget``: bytes the in-flight requests may hold.  ``free_hbm``
+    (optional): a function returning the device's free bytes now; the budget
+    is then re-read at every completion as what the in-flight batches hold
+    plus ``hbm_fraction`` of the free bytes (capped by ``hbm_budget``).
+    ``keep(request)`` decides whether a completion keeps the labels and AP
+    flags on the host (default: always); the BCC count and, when the slot
+    computes one, a device-side digest of the result are always kept."""
+
     def __init__(self, slots: Sequence[Slot], hbm_budget: int, clock: Optional[Clock] = None,
-                 max_batch_graphs: Optional[int] = None, on_idle: Optional[Callable[[], None]] = None):
+                 max_batch_graphs: Optional[int] = None, on_idle: Optional[Callable[[], None]] = None,
+                 free_hbm: Optional[Callable[[], int]] = None, hbm_fraction: float = 0.6,
+                 keep: Optional[Callable[[Request], bool]] = None):
         self.slots = list(slots)
+        self.cap_budget = int(hbm_budget)
         self.budget = int(hbm_budget)
         self.clock = clock or Clock()
         self.max_batch = max_batch_graphs
         self.on_idle = on_idle
+        self.free_hbm = free_hbm
+        self.hbm_fraction = hbm_fraction
+        self.keep = keep
         self.stats: Dict[str, int] = {"batches": 0, "admitted": 0, "rejected": 0, "max_queue": 0,
-                                      "blocked_on_memory": 0, "max_inflight_bytes": 0}
+                                      "blocked_on_memory": 0, "max_inflight_bytes": 0, "budget_reads": 0,
+                                      "min_budget": int(hbm_budget)}
+
+    def _reread_budget(self, used: int) -> None:
+        if self.free_hbm is None:
+            return
+        live = used + int(self.hbm_fraction * max(int(self.free_hbm()), 0))
+        self.budget = min(self.cap_budget, live)
+        self.stats["budget_reads"] += 1
+        self.stats["min_budget"] = min(self.stats["min_budget"], self.budget)
 
     def _fits_any_slot(self, g) -> bool:
         n, a = int(g.n), int(g.offsets[-1])
@@ -138,6 +167,7 @@ class Server:
         used = 0
         done: Dict[int, Completion] = {}
         i = 0
+        self._reread_budget(0)
         t0 = self.clock.now()
         while i < len(pending) or queue or inflight:
             now = self.clock.now() - t0
@@ -161,11 +191,14 @@ class Server:
                     res = self.slots[si].results()
                     fin = self.clock.now() - t0
                     for r, gr in zip(fl.reqs, res):
-                        done[r.rid] = Completion(r.rid, True, "", gr.edge_label, gr.is_ap, gr.num_bcc,
-                                                 r.arrival, fl.admitted, fin)
+                        kept = self.keep is None or self.keep(r)
+                        done[r.rid] = Completion(r.rid, True, "", gr.edge_label if kept else None,
+                                                 gr.is_ap if kept else None, gr.num_bcc, r.arrival, fl.admitted,
+                                                 fin, getattr(gr, "digest", None))
                     used -= fl.bytes
                     del inflight[si]
                     free.append(si)
+                    self._reread_budget(used)
             # admission: FIFO prefix that fits a free slot and the budget
             while free and queue:
                 head = queue[0]
@@ -197,7 +230,7 @@ class Server:
                 del queue[: len(batch)]
                 free.remove(si)
                 adm = self.clock.now() - t0
-                s.launch([r.graph for r in batch])
+                s.launch([r.graph for r in batch], keep=[self.keep is None or self.keep(r) for r in batch])
                 inflight[si] = _Inflight(si, batch, nbytes, adm)
                 used += nbytes
                 self.stats["max_inflight_bytes"] = max(self.stats["max_inflight_bytes"], used)
@@ -239,17 +272,18 @@ def poisson_arrivals(count: int, qps: float, seed: int) -> np.ndarray:
 
 # ---------------------------------------------------------------- executors
 class HipSlot(Slot):
-    """A BatchedSolver with its own stream and device-resident buffers."""
+    """A batched solver with its own stream and device-resident buffers; it
+    solves each batch eagerly on exactly the batch's vertices and arcs."""
 
-    def __init__(self, cap_v: int, cap_a: int, cap_g: int, device="cuda:0", flags: int = 0, use_graph: bool = True):
+    def __init__(self, cap_v: int, cap_a: int, cap_g: int, device="cuda:0", flags: int = 0, digests: bool = False):
         from .batch import BatchedSolver
 
         self.cap_v, self.cap_a, self.cap_g = cap_v, cap_a, cap_g
-        self.solver = BatchedSolver(cap_v, cap_a, cap_g, device=device, flags=flags, use_graph=use_graph)
+        self.solver = BatchedSolver(cap_v, cap_a, cap_g, device=device, flags=flags, exact=True, digests=digests)
 
-    def launch(self, graphs):
+    def launch(self, graphs, keep=None):
         self.solver.stage(graphs)
-        self.solver.launch()
+        self.solver.launch(keep_host=keep is None or any(keep))
 
     def ready(self):
         return self.solver.ready()
@@ -259,8 +293,96 @@ class HipSlot(Slot):
 
 
 def hip_slots(num_slots: int, cap_v: int, cap_a: int, cap_g: int, device="cuda:0", flags: int = 0,
-              use_graph: bool = True) -> List[HipSlot]:
-    return [HipSlot(cap_v, cap_a, cap_g, device, flags, use_graph) for _ in range(num_slots)]
+              digests: bool = False) -> List[HipSlot]:
+    return [HipSlot(cap_v, cap_a, cap_g, device, flags, digests) for _ in range(num_slots)]
+
+
+class PlainSlot(Slot):
+    """Serial baseline: one request at a time through the plain solve
+    (fastbcc_solve): the request's own CSR copied in, solved in a workspace
+    sized for it, its labels and AP flags copied out -- nothing padded, no
+    batching."""
+
+    cap_g = 1
+
+    def __init__(self, cap_v: int, cap_a: int, device="cuda:0", flags: int = 0, digests: bool = False):
+        from .api import BccResult
+
+        self.cap_v, self.cap_a = cap_v, cap_a
+        self.device = torch_device(device)
+        self.flags, self.digests = flags, digests
+        import torch
+
+        dev = self.device
+        self.d_off = torch.empty(cap_v + 1, dtype=torch.int32, device=dev)
+        self.d_adj = torch.empty(cap_a, dtype=torch.int32, device=dev)
+        self.out = BccResult(torch.empty(cap_a, dtype=torch.int32, device=dev),
+                             torch.empty(cap_v, dtype=torch.uint8, device=dev),
+                             torch.empty(1, dtype=torch.int64, device=dev))
+        self.h_off = torch.empty(cap_v + 1, dtype=torch.int32, pin_memory=True)
+        self.h_adj = torch.empty(cap_a, dtype=torch.int32, pin_memory=True)
+        self.h_label = torch.empty(cap_a, dtype=torch.int32, pin_memory=True)
+        self.h_ap = torch.empty(cap_v, dtype=torch.uint8, pin_memory=True)
+        self.h_nb = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.h_dig = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.stream = torch.cuda.Stream(device=dev)
+        self.done = torch.cuda.Event()
+        self.n = self.a = 0
+        self.kept = True
+
+    def launch(self, graphs, keep=None):
+        import numpy as np
+        import torch
+
+        from .api import BccResult, alloc_workspace, solve
+        from .batch import PinnedGraph, device_digests
+
+        (g,) = graphs
+        n, A = int(g.n), int(g.offsets[-1])
+        if isinstance(g, PinnedGraph):
+            src_off, src_adj = g.t_off, g.t_adj
+        else:
+            self.h_off.numpy()[: n + 1] = np.asarray(g.offsets)
+            self.h_adj.numpy()[:A] = np.asarray(g.adj)
+            src_off, src_adj = self.h_off[: n + 1], self.h_adj[:A]
+        self.n, self.a = n, A
+        self.kept = keep is None or keep[0]
+        s = self.stream
+        with torch.cuda.stream(s):
+            self.d_off[: n + 1].copy_(src_off, non_blocking=True)
+            if A:
+                self.d_adj[:A].copy_(src_adj, non_blocking=True)
+            ws = alloc_workspace(n, A, 1, self.device)
+            out = BccResult(self.out.edge_label[:A], self.out.is_ap[:n], self.out.num_bcc)
+            solve(self.d_off[: n + 1], self.d_adj[:A], out=out, workspace=ws, flags=self.flags, stream=s)
+            if self.digests:
+                ab = torch.tensor([0, A], dtype=torch.int64).to(self.device, non_blocking=True)
+                vb = torch.tensor([0, n], dtype=torch.int64).to(self.device, non_blocking=True)
+                self.h_dig.copy_(device_digests(out.edge_label, out.is_ap, ab, vb), non_blocking=True)
+            if self.kept:
+                if A:
+                    self.h_label[:A].copy_(out.edge_label, non_blocking=True)
+                if n:
+                    self.h_ap[:n].copy_(out.is_ap, non_blocking=True)
+            self.h_nb.copy_(out.num_bcc, non_blocking=True)
+            self.done.record(s)
+
+    def ready(self):
+        return self.done.query()
+
+    def results(self):
+        from .batch import GraphResult
+
+        self.done.synchronize()
+        lab = self.h_label.numpy()[: self.a].copy() if self.kept else None
+        ap = self.h_ap.numpy()[: self.n].copy() if self.kept else None
+        return [GraphResult(lab, ap, int(self.h_nb.numpy()[0]), int(self.h_dig.numpy()[0]) if self.digests else None)]
+
+
+def torch_device(device):
+    import torch
+
+    return torch.device(device)
 
 
 class SimClock(Clock):
@@ -287,7 +409,7 @@ class SimSlot(Slot):
         self.t_ready = None
         self.graphs = None
 
-    def launch(self, graphs):
+    def launch(self, graphs, keep=None):
         assert self.t_ready is None, "slot launched while busy"
         self.graphs = list(graphs)
         self.t_ready = self.clock.now() + self.cost(self.graphs)

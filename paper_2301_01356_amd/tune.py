@@ -266,9 +266,13 @@ def ship(names, path: str = SHIPPED, out: Optional[str] = None) -> Dict[str, Dic
         key, run = workload_runner(name)
         t = Tuner(cache_path=None, shipped=None)
         flags = t.tune(key, run, force=True)
-        for k in [k for k, e in table.items() if e.get("workload") == name]:
-            del table[k]
-        table[key] = dict(t.cache[key], workload=name, source="shipped")
+        for k in [k for k, e in table.items() if name in e.get("workloads", ())]:
+            table[k]["workloads"] = [w for w in table[k]["workloads"] if w != name]
+            if not table[k]["workloads"]:
+                del table[k]
+        # workloads of one size class share its entry: the last one tuned sets it
+        names = sorted(set(table.get(key, {}).get("workloads", [])) | {name})
+        table[key] = dict(t.cache[key], workloads=names, tuned_on=name, source="shipped")
         print(f"{name}: {key} -> {flags:#x} {table[key]}", flush=True)
         del run
         torch.cuda.empty_cache()
@@ -279,11 +283,12 @@ def ship(names, path: str = SHIPPED, out: Optional[str] = None) -> Dict[str, Dic
     return table
 
 
-def shipped_entries(path: str = SHIPPED) -> Dict[str, Dict]:
-    """{workload name: (flags, entry)} of the shipped table."""
+def shipped_entries(path: str = SHIPPED) -> Dict[str, tuple]:
+    """{workload name: (flags, entry)} of the shipped table (workloads of one
+    size class share their class's entry)."""
     with open(path) as f:
         table = json.load(f)
-    return {e["workload"]: (encode(e), e) for e in table.values() if "workload" in e}
+    return {w: (encode(e), e) for e in table.values() for w in e.get("workloads", ())}
 
 
 if __name__ == "__main__":

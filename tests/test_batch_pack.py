@@ -1,6 +1,7 @@
 """The padded union that the batched solver feeds the GPU is always a valid
-symmetric CSR (ids in range, offsets monotone, every arc count covered), and
-its BCC structure is exactly the union of the graphs' own (CPU oracle)."""
+symmetric CSR (ids in range, offsets monotone, rows sorted, every arc count
+covered), and its BCC structure is exactly the union of the graphs' own plus
+the padding graph's one 2-cycle (CPU oracle)."""
 import numpy as np
 import pytest
 
@@ -33,15 +34,34 @@ def test_pack_is_valid_and_preserves_bccs(count):
         np.testing.assert_array_equal(np.where(sub >= 0, sub - a0, -1), glab)
         np.testing.assert_array_equal(ap[v0:v1], gap)
         total += gnb
-    # the padding (self-loops on one vertex) adds no BCC and no articulation point
-    assert nb == total
+    # the padding: parallel copies of one edge (one BCC, labelled by its first
+    # arc), a self-loop for an odd leftover arc, no articulation point
+    a_used = spans[-1][3] if spans else 0
+    left = cap_a - a_used
+    assert nb == total + (1 if left >= 2 else 0)
     assert ap[spans[-1][1] if spans else 0 :].sum() == 0
-    assert np.all(lab[spans[-1][3] if spans else 0 :] == -1)
+    assert np.all(lab[a_used : cap_a - (left & 1)] == a_used)
+    if left & 1:
+        assert lab[cap_a - 1] == -1
+    for v in range(u.n):
+        row = u.adj[u.offsets[v] : u.offsets[v + 1]]
+        assert np.all(row[1:] >= row[:-1]), "padded rows must stay sorted"
+
+
+@pytest.mark.parametrize("left", [0, 1, 2, 9])
+def test_pack_padding_is_loop_free_for_even_leftovers(left):
+    g = gen.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)])
+    vb, off, adj, spans = pack([g], 4 + 2, g.num_arcs + left, 2)
+    u = as_csr(vb, off, adj)
+    src = np.repeat(np.arange(u.n), np.diff(u.offsets))
+    assert int((src == u.adj).sum()) == (left & 1)
 
 
 def test_pack_rejects_overflow():
     g = gen.from_edges(10, [(i, i + 1) for i in range(9)])
     with pytest.raises(ValueError):
-        pack([g], 10, 100, 4)  # needs one spare vertex for padding
+        pack([g], 11, 100, 4)  # needs two spare vertices for leftover arcs
+    pack([g], 12, 100, 4)
+    pack([g], 11, 18, 4)  # no leftover arcs: one spare vertex
     with pytest.raises(ValueError):
         pack([g] * 5, 1000, 1000, 4)
