@@ -62,7 +62,9 @@ typedef enum fastbcc_status {
   FASTBCC_ERR_TOO_LARGE = 2,           /* n >= 2^30 or num_arcs >= 2^31 */
   FASTBCC_ERR_WORKSPACE_TOO_SMALL = 3, /* workspace_bytes < fastbcc_workspace_size() */
   FASTBCC_ERR_HIP = 4,                 /* a HIP launch or API call failed */
-  FASTBCC_ERR_INVALID_GRAPH = 5        /* FASTBCC_FLAG_VALIDATE found a malformed CSR */
+  FASTBCC_ERR_INVALID_GRAPH = 5,       /* FASTBCC_FLAG_VALIDATE found a malformed CSR */
+  FASTBCC_ERR_SCRATCH_TOO_SMALL = 6    /* fastbcc_solve_noalloc: the graph's workspace exceeds
+                                          FASTBCC_NOALLOC_SCRATCH_BYTES */
 } fastbcc_status;
 
 /* flags */
@@ -141,6 +143,32 @@ FASTBCC_API fastbcc_status fastbcc_workspace_size(int64_t n, int64_t num_arcs, i
 FASTBCC_API fastbcc_status fastbcc_solve(int64_t n, int64_t num_arcs, const int32_t* offsets, const int32_t* adj,
                              int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
                              void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
+
+/*
+ * Allocation-free variant of fastbcc_solve, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, results and asynchrony as
+ * fastbcc_solve, without the workspace: the library keeps one static
+ * workspace of FASTBCC_NOALLOC_SCRATCH_BYTES per GPU (a __device__ array,
+ * held from the code object's load on that GPU until the process ends) and
+ * solves in it.  No call allocates or frees memory.  The device is the
+ * current HIP device; `stream` must belong to it.
+ *   - A graph whose fastbcc_workspace_size(n, num_arcs, 1) exceeds
+ *     FASTBCC_NOALLOC_SCRATCH_BYTES is refused with
+ *     FASTBCC_ERR_SCRATCH_TOO_SMALL before anything is enqueued (64 MiB hold,
+ *     e.g., about 3 * 10^5 vertices with 2.4 * 10^6 arcs).
+ *   - Every call on one GPU shares that GPU's scratch, which keeps the last
+ *     call's contents (each solve initialises what it reads).  Calls whose
+ *     work overlaps on one GPU -- on different streams, or from different
+ *     threads without ordering -- race on it and give undefined results:
+ *     order them on one stream, or use fastbcc_solve with a workspace each.
+ *   - fastbcc_read_device_status and fastbcc_vertex_labels need a caller's
+ *     workspace, so they do not apply to this entry point.
+ */
+#define FASTBCC_NOALLOC_SCRATCH_BYTES (64u << 20)
+FASTBCC_API fastbcc_status fastbcc_solve_noalloc(int64_t n, int64_t num_arcs, const int32_t* offsets,
+                                                 const int32_t* adj, int32_t* out_edge_label, uint8_t* out_is_ap,
+                                                 int64_t* out_num_bcc, uint32_t flags, void* stream);
 
 /* As fastbcc_solve, with int64 offsets (graphs whose arc count needs them
  * in memory layout; num_arcs must still be < 2^31). */

@@ -9,10 +9,11 @@ from .api import (  # noqa: F401
     read_device_status,
     solve,
     solve_batched,
+    solve_noalloc,
     solve_traced,
     vertex_labels,
     workspace_size,
 )
 
-__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "solve_traced", "vertex_labels",
+__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
            "workspace_size"]

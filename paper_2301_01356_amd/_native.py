@@ -19,6 +19,8 @@ ERR_TOO_LARGE = 2
 ERR_WORKSPACE_TOO_SMALL = 3
 ERR_HIP = 4
 ERR_INVALID_GRAPH = 5
+ERR_SCRATCH_TOO_SMALL = 6
+NOALLOC_SCRATCH_BYTES = 64 << 20  # FASTBCC_NOALLOC_SCRATCH_BYTES
 
 FLAG_VALIDATE = 0x1
 FLAG_SORTED_ROWS = 0x2
@@ -52,6 +54,7 @@ EXPORTED = (
     "fastbcc_trace_dropped",
     "fastbcc_trace_reset",
     "fastbcc_vertex_labels",
+    "fastbcc_solve_noalloc",
 )
 
 
@@ -109,6 +112,8 @@ def lib():
     h.fastbcc_trace_dropped.argtypes = [vp]
     h.fastbcc_trace_reset.restype = None
     h.fastbcc_trace_reset.argtypes = [vp]
+    h.fastbcc_solve_noalloc.restype = st
+    h.fastbcc_solve_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, u32, vp]
     h.fastbcc_vertex_labels.restype = st
     h.fastbcc_vertex_labels.argtypes = [i64, i64, i32, vp, vp, sz, vp, vp, vp]
     _lib = h

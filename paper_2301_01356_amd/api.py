@@ -124,6 +124,42 @@ def solve(
     return out
 
 
+def solve_noalloc(
+    offsets: torch.Tensor,
+    adj: torch.Tensor,
+    *,
+    out: BccResult,
+    flags: int = 0,
+    stream=None,
+) -> BccResult:
+    """``solve`` in the library's static per-GPU scratch instead of a
+    workspace: the call allocates nothing (``out`` is the caller's).  Graphs
+    whose workspace would exceed ``NOALLOC_SCRATCH_BYTES`` are refused; calls
+    that overlap on one GPU race on the shared scratch."""
+    _check_tensor(offsets, "offsets", (torch.int32,))
+    n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets needs n + 1 >= 1 entries")
+    dev = offsets.device
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    A = adj.numel()
+    _check_result(out, n, A, 1, dev)
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_solve_noalloc(
+            n,
+            A,
+            offsets.data_ptr(),
+            _dev_ptr(adj) if A else None,
+            _dev_ptr(out.edge_label) if A else None,
+            _dev_ptr(out.is_ap) if n else None,
+            out.num_bcc.data_ptr(),
+            flags,
+            _stream_handle(stream),
+        )
+    N.check(st, "fastbcc_solve_noalloc")
+    return out
+
+
 def solve_batched(
     vbegin: torch.Tensor,
     offsets: torch.Tensor,

@@ -41,6 +41,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2562,6 +2563,35 @@ fastbcc_status solve_impl(int64_t n64, int64_t A, const OffT* off, const int* ad
 
 }  // namespace
 
+// ------------------------------------------------------------ allocation-free entry point
+// Workspace of fastbcc_solve_noalloc: one static array per GPU, living as long
+// as the process.  In host code `scratch` names only a host-side stand-in;
+// its device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[FASTBCC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch, looked up on the first
+// call made with that device current.
+fastbcc_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return FASTBCC_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return FASTBCC_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FASTBCC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 fastbcc_status fastbcc_workspace_size(int64_t n, int64_t num_arcs, int32_t num_graphs, size_t* bytes) {
@@ -2576,6 +2606,19 @@ fastbcc_status fastbcc_solve(int64_t n, int64_t num_arcs, const int32_t* offsets
                              size_t workspace_bytes, uint32_t flags, void* stream) {
   return solve_impl<int>(n, num_arcs, offsets, adj, 1, nullptr, out_edge_label, out_is_ap, out_num_bcc, workspace,
                          workspace_bytes, flags, (hipStream_t)stream);
+}
+
+fastbcc_status fastbcc_solve_noalloc(int64_t n, int64_t num_arcs, const int32_t* offsets, const int32_t* adj,
+                                     int32_t* out_edge_label, uint8_t* out_is_ap, int64_t* out_num_bcc,
+                                     uint32_t flags, void* stream) {
+  if (n < 0 || num_arcs < 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  if (make_layout(n, num_arcs).total > (size_t)FASTBCC_NOALLOC_SCRATCH_BYTES) return FASTBCC_ERR_SCRATCH_TOO_SMALL;
+  void* ws = nullptr;
+  const fastbcc_status s = scratch_for_current_device(&ws);
+  if (s != FASTBCC_OK) return s;
+  return solve_impl<int>(n, num_arcs, offsets, adj, 1, nullptr, out_edge_label, out_is_ap, out_num_bcc, ws,
+                         (size_t)FASTBCC_NOALLOC_SCRATCH_BYTES, flags, (hipStream_t)stream);
 }
 
 fastbcc_status fastbcc_solve_off64(int64_t n, int64_t num_arcs, const int64_t* offsets, const int32_t* adj,
@@ -2711,6 +2754,8 @@ const char* fastbcc_status_string(fastbcc_status s) {
     case FASTBCC_ERR_WORKSPACE_TOO_SMALL: return "workspace too small or missing";
     case FASTBCC_ERR_HIP: return "HIP runtime error";
     case FASTBCC_ERR_INVALID_GRAPH: return "input is not a valid symmetric CSR";
+    case FASTBCC_ERR_SCRATCH_TOO_SMALL:
+      return "graph needs a larger workspace than the static scratch of fastbcc_solve_noalloc holds";
   }
   return "unknown status";
 }
