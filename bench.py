@@ -179,6 +179,29 @@ def cpu_baseline(sample_scale, g=None, gpu=None):
     return out
 
 
+def space_report(workspace_of):
+    """Space of the Tarjan-Vishkin explicit skeleton (the second CPU solver,
+    paper: the Tarjan-Vishkin appendix and its space comparison) against the
+    workspace this library needs, on bounded samples of the workload
+    families: the skeleton as a CSR with one vertex per edge of the input
+    (4 bytes per offset, 8 per skeleton edge, both directions).  Per-arc
+    figures carry the R-MAT sample to the benchmarked size."""
+    from oracle.tv_bcc import tv_bcc
+    from paper_2301_01356_amd import gen
+
+    rows = []
+    for name, g in (("plain", gen.plain()), ("rmat16", gen.rmat(scale=16)),
+                    ("grid 256x256 p0.7 + path", gen.grid(seed=12, rows=256, cols=256, path_len=1 << 14)),
+                    ("knn10 2^16", gen.family("knn", 1 << 16, 10, seed=6))):
+        _, _, _, sz = tv_bcc(g.offsets, g.adj, return_skeleton_size=True)
+        skel = 4 * (sz["skeleton_vertices"] + 1) + 8 * sz["skeleton_edges"]
+        ws = workspace_of(g.n, g.num_arcs)
+        rows.append({"graph": name, "vertices": g.n, "arcs": g.num_arcs, "skeleton_vertices": sz["skeleton_vertices"],
+                     "skeleton_edges": sz["skeleton_edges"], "skeleton_bytes": skel, "workspace_bytes": ws,
+                     "skeleton_over_workspace": round(skel / ws, 3)})
+    return rows
+
+
 def gather_calibration(table_mib=256, count_log2=28):
     """Random-gather ceiling of this GPU: ``2^count_log2`` int32 reads at
     uniform random positions of a ``table_mib`` MiB table (one per lane, no
@@ -421,79 +444,130 @@ def bench_knn_sweep(args):
     }
 
 
+# Serving arrival rate, frozen: 0.7 x the capacity measured once on MI355X
+# (all requests queued at t = 0, same pool, slots and flags; bench.py
+# --workload serve --measure-capacity).  None: measure it in the run.
+SERVE_QPS = None
+
+
 def bench_serve(args):
-    """Serving: Poisson arrivals of mixed-family requests, n log-uniform in
-    [2^10, 2^22], mean degree 4-32; continuous batching over HIP streams,
-    admission by free HBM; p50/p99 latency, against serial solves."""
+    """Serving: Poisson arrivals at a frozen rate of mixed-family requests
+    (n log-uniform in [2^10, 2^22], mean degree 4-32), for at least a minute;
+    continuous batching over HIP streams, admission by live free HBM; p50/p99
+    latency, against serial plain solves of the same request stream."""
     import numpy as np
     import torch
 
+    import oracle
     from paper_2301_01356_amd import gen
-    from paper_2301_01356_amd.serve import Request, Server, hip_slots, latency_summary, poisson_arrivals
+    from paper_2301_01356_amd.batch import PinnedGraph
+    from paper_2301_01356_amd.serve import (PlainSlot, Request, Server, hip_slots, latency_summary,
+                                            poisson_arrivals, serving_flags)
 
     t0 = time.perf_counter()
-    count = args.requests
-    graphs = [gen.mixed(5, i, 1 << 10, 1 << 22, 4.0, 32.0) for i in range(count)]
-    tot_a = sum(g.num_arcs for g in graphs)
-    log(f"[bench] serve: {count} requests, {tot_a} arcs total, generated in {time.perf_counter() - t0:.1f}s")
-    free_b, total_b = torch.cuda.mem_get_info()
-    budget = int(free_b * 0.6)
-    maxn = max(g.n for g in graphs)
-    maxa = max(g.num_arcs for g in graphs)
+    # a pool of distinct request graphs in pinned host memory; each request
+    # draws one (seeded), as a stream of independent queries would
+    pool_src = [gen.mixed(5, i, 1 << 10, 1 << 22, 4.0, 32.0) for i in range(args.serve_pool)]
+    pool = [PinnedGraph(g) for g in pool_src]
+    log(f"[bench] serve: pool of {len(pool)} graphs, {sum(g.num_arcs for g in pool)} arcs, "
+        f"generated in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    maxn = max(g.n for g in pool)
+    maxa = max(g.num_arcs for g in pool)
     cap_v = max(1 << 23, 2 * maxn + 2)
     cap_a = max(1 << 27, 2 * maxa)
-    # mixed batches: the tuner's seed for batches of assorted graphs (it is the
-    # usual winner on the 4096-graph batch); requests are not tuned one by one
-    from paper_2301_01356_amd.tune import SEEDS, encode
-
-    slots = hip_slots(args.slots, cap_v, cap_a, 64, flags=INPUT_FLAGS | encode(SEEDS[2]))
-    # warm every slot (and its captured graph) once
-    for sl in slots:
-        sl.launch(graphs[:1])
+    flags = serving_flags()
+    slots = hip_slots(args.slots, cap_v, cap_a, 64, flags=flags, digests=True)
+    serial_slot = PlainSlot(maxn + 1, maxa, flags=flags, digests=True)
+    for sl in slots + [serial_slot]:  # warm every slot once
+        sl.launch(pool[:1])
         sl.results()
+    free0, total_b = torch.cuda.mem_get_info()
+    budget = int(free0 * 0.6)
+    def live_free():
+        return torch.cuda.mem_get_info()[0]
 
-    def run(arrivals, srv_slots, max_batch=None):
-        reqs = [Request(i, g, float(arrivals[i])) for i, g in enumerate(graphs)]
-        srv = Server(srv_slots, budget, max_batch_graphs=max_batch)
+    def stream_of(count, arrivals, seed):
+        pick = np.random.default_rng(seed).integers(len(pool), size=count)
+        return [Request(i, pool[pick[i]], float(arrivals[i])) for i in range(count)], pick
+
+    keep_every = 97
+
+    def run(reqs, srv_slots, max_batch=None):
+        srv = Server(srv_slots, budget, max_batch_graphs=max_batch, free_hbm=live_free,
+                     keep=lambda r: r.rid % keep_every == 0)
         t = time.perf_counter()
         comps = srv.run(reqs)
-        wall = time.perf_counter() - t
-        return comps, srv.stats, wall
+        return comps, srv.stats, time.perf_counter() - t
 
-    # capacity: everything queued at t = 0
-    comps, st, wall = run(np.zeros(count), slots)
-    cap = count / wall
-    qps = args.qps or 0.7 * cap
-    log(f"[bench] serve capacity {cap:.1f} graphs/s; running Poisson arrivals at {qps:.1f} QPS")
+    qps = args.qps or SERVE_QPS
+    # capacities: the same requests all queued at t = 0, served (continuous
+    # batching over the slots) and serial (one plain solve at a time)
+    n_cap = args.capacity_requests
+    reqs, _ = stream_of(n_cap, np.zeros(n_cap), 50)
+    comps, st, wall = run(reqs, slots)
+    cap = n_cap / wall
+    log(f"[bench] served capacity {cap:.1f} graphs/s ({n_cap} requests queued at t=0, {st['batches']} batches)")
+    comps_c1, _, wall_c1 = run(reqs, [serial_slot], max_batch=1)
+    cap_serial = n_cap / wall_c1
+    log(f"[bench] serial capacity {cap_serial:.1f} graphs/s")
+    same_cap = all(a.ok and b.ok and a.digest == b.digest for a, b in zip(comps, comps_c1))
+    if qps is None:
+        qps = 0.7 * cap
+    count = max(int(np.ceil(qps * args.serve_seconds)), 1)
     arr = poisson_arrivals(count, qps, 5)
-    comps, st, wall = run(arr, slots)
+    reqs, pick = stream_of(count, arr, 5)
+    log(f"[bench] serve: {count} requests at {qps:.1f} QPS (Poisson) over {arr[-1]:.1f}s")
+    comps, st, wall = run(reqs, slots)
     s_mix = latency_summary(comps)
     ok = all(c.ok for c in comps)
-    # serial plain solves of the same stream: one request at a time, one slot
-    comps1, st1, wall1 = run(arr, slots[:1], max_batch=1)
+    log(f"[bench] served: p50 {s_mix['p50_ms']:.2f} ms p99 {s_mix['p99_ms']:.2f} ms, "
+        f"{s_mix['graphs_per_s']:.1f} graphs/s, {st['batches']} batches, wall {wall:.1f}s")
+    # serial plain solves of the same stream (its first requests): one at a
+    # time, each with only its own copies and a workspace sized for it
+    n_ser = min(count, args.serial_requests)
+    comps1, st1, wall1 = run(reqs[:n_ser], [serial_slot], max_batch=1)
     s_ser = latency_summary(comps1)
-    same = all(np.array_equal(a.edge_label, b.edge_label) for a, b in zip(comps, comps1))
-    log(f"[bench] served p50 {s_mix['p50_ms']:.2f} ms p99 {s_mix['p99_ms']:.2f} ms; "
-        f"serial p50 {s_ser['p50_ms']:.2f} ms p99 {s_ser['p99_ms']:.2f} ms")
+    log(f"[bench] serial ({n_ser} requests): p50 {s_ser['p50_ms']:.2f} ms p99 {s_ser['p99_ms']:.2f} ms, "
+        f"{s_ser['graphs_per_s']:.1f} graphs/s")
+    same = same_cap and all(a.ok and b.ok and a.digest == b.digest and a.num_bcc == b.num_bcc
+                            for a, b in zip(comps[:n_ser], comps1))
+    # the kept results against the oracle, one per distinct pool graph
+    checked, agree, seen = 0, True, set()
+    for c in comps:
+        p = int(pick[c.rid])
+        if c.edge_label is None or p in seen or len(seen) >= args.serve_oracle_checks:
+            continue
+        seen.add(p)
+        lab, ap, nb, _, _ = oracle.ht_bcc(pool_src[p].offsets, pool_src[p].adj)
+        agree = agree and bool(np.array_equal(c.edge_label, lab) and np.array_equal(c.is_ap, ap) and c.num_bcc == nb)
+        checked += 1
+    log(f"[bench] served == serial on {n_cap} + {n_ser} requests: {same}; {checked} kept results == oracle: {agree}")
     return {
         "metric": "serving p50/p99 latency and graphs/s (1 GPU)",
         "value": s_mix["graphs_per_s"],
         "unit": "graphs/s",
         "n_gpus": 1,
         "steps": count,
-        "warmup": args.slots,
+        "warmup": args.slots + 1,
         "ms_per_step": 1e3 / s_mix["graphs_per_s"] if s_mix["graphs_per_s"] else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "serve_mixed_2^10..2^22", "requests": count, "arcs_total": tot_a, "qps": qps,
-                   "flags": INPUT_FLAGS | encode(SEEDS[2]),
-                   "capacity_graphs_per_s": cap, "slots": args.slots, "hbm_budget_bytes": budget,
-                   "served": s_mix, "serial": s_ser, "batches": st["batches"],
-                   "served_vs_serial_throughput": s_mix["graphs_per_s"] / max(s_ser["graphs_per_s"], 1e-9),
-                   "all_ok": ok, "served_equals_serial": bool(same)},
+        "config": {"workload": "serve_mixed_2^10..2^22", "requests": count, "pool_graphs": len(pool),
+                   "pool_arcs": sum(g.num_arcs for g in pool), "qps": qps,
+                   "qps_source": "frozen" if (args.qps or SERVE_QPS) else "0.7 x capacity measured in this run",
+                   "arrival_span_s": float(arr[-1]), "flags": flags, "input_contract": "general",
+                   "capacity_graphs_per_s": cap, "serial_capacity_graphs_per_s": cap_serial,
+                   "capacity_requests": n_cap, "served_vs_serial_capacity": cap / cap_serial,
+                   "slots": args.slots, "hbm_budget_bytes_initial": budget,
+                   "hbm_budget_bytes_min": st["min_budget"], "budget_reads": st["budget_reads"],
+                   "served": s_mix, "batches": st["batches"], "max_queue": st["max_queue"],
+                   "serial": dict(s_ser, requests=n_ser, wall_s=wall1),
+                   "all_ok": ok, "served_equals_serial": bool(same), "oracle_checked": checked,
+                   "oracle_agrees": bool(agree)},
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -505,9 +579,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "plain", "batch", "serve", "knn_sweep"])
-    ap.add_argument("--requests", type=int, default=48)
     ap.add_argument("--slots", type=int, default=3)
-    ap.add_argument("--qps", type=float, default=0.0)
+    ap.add_argument("--qps", type=float, default=0.0, help="serving arrival rate (default: the frozen rate)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
+    ap.add_argument("--serve-pool", type=int, default=64, help="serving: distinct request graphs")
+    ap.add_argument("--serial-requests", type=int, default=1000, help="serving: requests of the serial baseline")
+    ap.add_argument("--serve-oracle-checks", type=int, default=6)
+    ap.add_argument("--capacity-requests", type=int, default=1500, help="serving: requests of the capacity runs")
     ap.add_argument("--cpu-sample-scale", type=int, default=25,
                     help="25: the oracle runs on the benchmarked R-MAT input itself and is compared with the GPU")
     ap.add_argument("--no-gather-calibration", action="store_true")
@@ -732,6 +810,14 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value'] / 1e6:.1f} M arcs/s in {cpu['seconds']:.1f}s"
             + (f", GPU == oracle: {cpu['gpu_equals_oracle']}" if whole else ""))
         del cpu["seconds"]
+        t_sp = time.perf_counter()
+        cpu["space_report"] = space_report(lambda nn, aa: N.workspace_size(nn, aa, 1))
+        r16 = next(r for r in cpu["space_report"] if r["graph"] == "rmat16")
+        skel25 = r16["skeleton_bytes"] / r16["arcs"] * A
+        cpu["space_report_rmat25_extrapolated"] = {"skeleton_bytes": int(skel25), "workspace_bytes": int(ws.numel()),
+                                                   "skeleton_over_workspace": round(skel25 / ws.numel(), 3)}
+        log(f"[bench] space report ({time.perf_counter() - t_sp:.1f}s): "
+            + ", ".join(f"{r['graph']} {r['skeleton_over_workspace']}x" for r in cpu["space_report"]))
         if whole and not cpu["gpu_equals_oracle"]:
             raise SystemExit("[bench] the benchmarked solve differs from the oracle")
 

@@ -164,8 +164,7 @@ class BatchedSolver:
         # pinned staging for host<->device copies
         self.h_vbegin = torch.empty(G1 + 1, dtype=torch.int32, pin_memory=True)
         self.h_bounds = torch.empty(2 * (G1 + 1), dtype=torch.int64, pin_memory=True)
-        self.h_off = torch.empty(self.cap_v + 1, dtype=torch.int32, pin_memory=True)
-        self.h_adj = torch.empty(self.cap_a, dtype=torch.int32, pin_memory=True)
+        self._h_in = None  # pinned staging of graphs that are not pinned themselves (allocated on first use)
         self.h_label = torch.empty(self.cap_a, dtype=torch.int32, pin_memory=True)
         self.h_ap = torch.empty(self.cap_v, dtype=torch.uint8, pin_memory=True)
         self.h_nb = torch.empty(G1, dtype=torch.int64, pin_memory=True)
@@ -205,11 +204,11 @@ class BatchedSolver:
         spare = 0 if self.exact else (2 if a0 < self.cap_a else 1)
         if v0 > self.cap_v - spare or a0 > self.cap_a:
             raise ValueError("batch exceeds the vertex/arc capacity")
-        hoff, hadj = self.h_off.numpy(), self.h_adj.numpy()
         for g, (s0, s1, b0, b1) in zip(graphs, spans):
             if isinstance(g, PinnedGraph):
                 copies.append((s0, s1, b0, b1, g.t_off, g.t_adj))
             else:
+                hoff, hadj = self._staging()
                 hoff[s0:s1] = np.asarray(g.offsets[: s1 - s0])
                 hadj[b0:b1] = np.asarray(g.adj)
                 copies.append((s0, s1, b0, b1, None, None))
@@ -222,6 +221,12 @@ class BatchedSolver:
         bd[G + 1 : 2 * G + 2] = [s[0] for s in spans] + [v0]
         self.spans, self._copies = spans, copies
         self.used_v, self.used_a = v0, a0
+
+    def _staging(self):
+        if self._h_in is None:
+            self._h_in = (torch.empty(self.cap_v + 1, dtype=torch.int32, pin_memory=True),
+                          torch.empty(self.cap_a, dtype=torch.int32, pin_memory=True))
+        return self._h_in[0].numpy(), self._h_in[1].numpy()
 
     def _copy_in(self) -> None:
         """On this solver's stream: the staged graphs into the device buffers,
@@ -239,10 +244,11 @@ class BatchedSolver:
                     continue
                 if run is not None:
                     r0, rb = run
+                    h_off, h_adj = self._h_in
                     if s0 > r0:
-                        self.d_off[r0:s0].copy_(self.h_off[r0:s0], non_blocking=True)
+                        self.d_off[r0:s0].copy_(h_off[r0:s0], non_blocking=True)
                     if b0 > rb:
-                        self.d_adj[rb:b0].copy_(self.h_adj[rb:b0], non_blocking=True)
+                        self.d_adj[rb:b0].copy_(h_adj[rb:b0], non_blocking=True)
                     run = None
                 if toff is not False:
                     if s1 > s0:

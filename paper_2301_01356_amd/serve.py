@@ -56,6 +56,14 @@ class Completion:
         return self.finished - self.arrival
 
 
+def serving_flags() -> int:
+    """Flags of the serving slots: the tuning fields shipped for mixed batches
+    (the 4096-graph batch's pick), under the general input contract."""
+    from . import tune
+
+    return tune.shipped_entries()["batch4096"][0]
+
+
 def request_bytes(n: int, arcs: int) -> int:
     """Device bytes a request occupies inside a batch: its share of the
     workspace (O(n) plus tile bookkeeping) and its input/output arrays."""

@@ -58,27 +58,86 @@ def test_graph_replay_equals_eager():
             assert e.num_bcc == g.num_bcc
 
 
+def test_fixed_shape_buffers_hold_the_padded_union():
+    """After staging, the device buffers of the fixed-shape solver equal the
+    host-side padded union (graph-local ids made global on the device), for
+    graphs staged through pinned staging and graphs already pinned."""
+    from paper_2301_01356_amd.batch import PinnedGraph, pack
+
+    graphs = [gen.mixed(57, i, 8, 900, 4.0, 16.0) for i in range(10)]
+    mixed = [PinnedGraph(g) if i % 3 == 1 else g for i, g in enumerate(graphs)]
+    cap_v = sum(g.n for g in graphs) + 9
+    cap_a = sum(g.num_arcs for g in graphs) + 31
+    s = BatchedSolver(cap_v, cap_a, 12, device=DEV, use_graph=False)
+    s.stage(mixed)
+    s._copy_in()
+    s.stream.synchronize()
+    vb, off, adj, _ = pack(graphs, cap_v, cap_a, 12)
+    note("fixed-shape buffers vs pack()")
+    assert np.array_equal(s.d_vbegin.cpu().numpy(), vb)
+    assert np.array_equal(s.d_off.cpu().numpy(), off)
+    assert np.array_equal(s.d_adj.cpu().numpy(), adj)
+
+
 def test_serving_each_result_same_alone_and_in_the_mix():
+    """Served with the benchmark's serving flags (general input contract,
+    shipped mixed-batch tuning) and live free-HBM admission: every result
+    equals the request's plain solve alone (labels, AP flags, count and
+    device digest), every fifth one the oracle too."""
+    from paper_2301_01356_amd.batch import PinnedGraph
+    from paper_2301_01356_amd.serve import PlainSlot, serving_flags
+
     count = 40
     reqs = []
     arr = poisson_arrivals(count, 400.0, 5)
     for i in range(count):
-        reqs.append(Request(i, gen.mixed(55, i, 64, 60000, 4.0, 32.0), float(arr[i])))
-    slots = hip_slots(3, cap_v=200000, cap_a=4_000_000, cap_g=16, device=DEV)
-    srv = Server(slots, hbm_budget=8 << 30)
-    note(f"serving {count} requests on {len(slots)} slots")
+        g = gen.mixed(55, i, 64, 60000, 4.0, 32.0)
+        reqs.append(Request(i, PinnedGraph(g) if i % 2 else g, float(arr[i])))
+    flags = serving_flags()
+    slots = hip_slots(3, cap_v=200000, cap_a=4_000_000, cap_g=16, device=DEV, flags=flags, digests=True)
+    srv = Server(slots, hbm_budget=8 << 30, free_hbm=lambda: torch.cuda.mem_get_info()[0])
+    note(f"serving {count} requests on {len(slots)} slots, flags {flags:#x}")
     comps = srv.run(reqs)
     assert srv.stats["batches"] < count  # requests were batched together
-    for r, c in zip(reqs, comps):
-        assert c.ok, c.error
-        off = torch.from_numpy(r.graph.offsets32()).to(DEV)
-        adj = torch.from_numpy(r.graph.adj).to(DEV)
-        alone = solve(off, adj)
+    assert srv.stats["budget_reads"] >= srv.stats["batches"]
+    serial = Server([PlainSlot(60001, 4_000_000, DEV, flags, digests=True)], hbm_budget=8 << 30, max_batch_graphs=1)
+    note("serial plain solves of the same requests")
+    comps1 = serial.run(reqs)
+    for r, c, c1 in zip(reqs, comps, comps1):
+        assert c.ok and c1.ok, (c.error, c1.error)
+        off = torch.from_numpy(np.asarray(r.graph.offsets, np.int32)).to(DEV)
+        adj = torch.from_numpy(np.asarray(r.graph.adj, np.int32)).to(DEV)
+        alone = solve(off, adj, flags=flags)
         torch.cuda.synchronize()
         assert np.array_equal(alone.edge_label.cpu().numpy(), c.edge_label), f"request {r.rid}: labels differ"
         assert np.array_equal(alone.is_ap.cpu().numpy(), c.is_ap), f"request {r.rid}: APs differ"
         assert int(alone.num_bcc.item()) == c.num_bcc
+        assert np.array_equal(c1.edge_label, c.edge_label) and c1.digest == c.digest and c1.num_bcc == c.num_bcc
         if r.rid % 5 == 0:
             check_oracle(r.graph, c.edge_label, c.is_ap, c.num_bcc, f"request {r.rid}")
     s = latency_summary(comps)
     note(f"p50 {s['p50_ms']:.2f} ms p99 {s['p99_ms']:.2f} ms")
+
+
+def test_serving_general_contract_unsorted_rows_and_self_loops():
+    """Serving does not trust the sorted-row and loop-free promises: requests
+    with shuffled rows and self-loops are served correctly (oracle)."""
+    from paper_2301_01356_amd.serve import serving_flags
+
+    rng = np.random.default_rng(23)
+    reqs = []
+    for i in range(12):
+        n = int(rng.integers(5, 400))
+        edges = [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(int(rng.integers(n, 4 * n)))]
+        g = gen.multigraph_csr(n, edges)
+        adj = g.adj.copy()
+        for v in range(n):
+            a, b = g.offsets[v], g.offsets[v + 1]
+            adj[a:b] = rng.permutation(adj[a:b])
+        reqs.append(Request(i, gen.Csr(n, g.offsets, adj), 0.0))
+    slots = hip_slots(2, cap_v=5000, cap_a=40000, cap_g=8, device=DEV, flags=serving_flags())
+    note("serving unsorted rows with self-loops")
+    comps = Server(slots, hbm_budget=1 << 30).run(reqs)
+    for r, c in zip(reqs, comps):
+        assert c.ok, c.error
+        check_oracle(r.graph, c.edge_label, c.is_ap, c.num_bcc, f"request {r.rid}")
