@@ -450,6 +450,84 @@ def bench_knn_sweep(args):
 SERVE_QPS = None
 
 
+# Table 1 of the paper for its circular grids with p = 0.6 (context: the
+# statistics a percolated torus of this shape and size has, whoever solves it)
+PAPER_TORI = {"sqr_torus": {"shape": "10^4 x 10^4", "bcc_per_n": 0.2384, "largest_bcc_pct": 70.65},
+              "rec_torus": {"shape": "10^3 x 10^5", "bcc_per_n": 0.2383, "largest_bcc_pct": 70.66}}
+
+
+def bench_tori(args):
+    """The paper's SQR' and REC' shapes: percolated tori (p = 0.6) of 10^8
+    vertices.  Per torus: the tuned solve's time and edges/s, #BCC / n and the
+    largest BCC's share of the vertices (head included), beside Table 1."""
+    import numpy as np
+    import torch
+
+    from paper_2301_01356_amd import alloc_workspace, gen, read_device_status, solve, vertex_labels
+    from paper_2301_01356_amd.api import BccResult
+    from paper_2301_01356_amd.tune import cache_key, gpu_arch, skew_class
+
+    rows = []
+    dev = torch.device("cuda:0")
+    for name in ("sqr_torus", "rec_torus"):
+        t0 = time.perf_counter()
+        g = gen.config(name)
+        off = torch.from_numpy(g.offsets32()).to(dev)
+        adj = torch.from_numpy(g.adj).to(dev)
+        ws = alloc_workspace(g.n, g.num_arcs, 1, dev)
+        out = BccResult(torch.empty(g.num_arcs, dtype=torch.int32, device=dev),
+                        torch.empty(g.n, dtype=torch.uint8, device=dev), torch.empty(1, dtype=torch.int64, device=dev))
+        st = torch.cuda.current_stream()
+
+        def run_once(f):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(st)
+            solve(off, adj, out=out, workspace=ws, flags=f | INPUT_FLAGS, stream=st)
+            a1.record(st)
+            a1.synchronize()
+            return a0.elapsed_time(a1)
+
+        key = cache_key(gpu_arch(), g.n, g.num_arcs, 1, skew_class(np.diff(g.offsets)))
+        flags, cfg = tuned_flags(key, run_once)
+        for _ in range(args.warmup):
+            run_once(flags)
+        times = [run_once(flags) for _ in range(max(3, args.steps))]
+        ms = float(np.median(times))
+        if read_device_status(ws, st) != 0:
+            raise SystemExit(f"[bench] {name}: the solve's device-side checks fired")
+        nb = int(out.num_bcc.item())
+        home, _ = vertex_labels(ws, g.n, g.num_arcs, stream=st)
+        h = home[home >= 0].to(torch.int64)
+        largest = int(torch.bincount(h).max().item()) + 1 if h.numel() else 0  # + the BCC's head
+        rows.append({"torus": name, "shape": PAPER_TORI[name]["shape"], "vertices": g.n, "arcs": g.num_arcs,
+                     "ms": ms, "edges_per_s": g.num_arcs / (ms * 1e-3), "num_bcc": nb,
+                     "bcc_per_n": round(nb / g.n, 5), "largest_bcc_pct": round(100.0 * largest / g.n, 3),
+                     "paper": PAPER_TORI[name], "flags": flags | INPUT_FLAGS, "tuned": cfg})
+        log(f"[bench] {name}: {g.num_arcs} arcs, {ms:.3f} ms, {g.num_arcs / ms / 1e6:.2f} G edges/s, "
+            f"#BCC/n {nb / g.n:.4f} (paper {PAPER_TORI[name]['bcc_per_n']}), largest BCC "
+            f"{100.0 * largest / g.n:.2f}% (paper {PAPER_TORI[name]['largest_bcc_pct']}%), "
+            f"gen {time.perf_counter() - t0:.1f}s")
+        del off, adj, ws, out, home, h
+        torch.cuda.empty_cache()
+    return {
+        "metric": "BCC edges/s end-to-end (1 GPU), paper-shaped tori",
+        "value": rows[0]["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rows[0]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "tori_p0.6_10^8", "rows": rows},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def bench_serve(args):
     """Serving: Poisson arrivals at a frozen rate of mixed-family requests
     (n log-uniform in [2^10, 2^22], mean degree 4-32), for at least a minute;
@@ -578,7 +656,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "plain", "batch", "serve", "knn_sweep"])
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "plain", "batch", "serve", "knn_sweep", "tori"])
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--qps", type=float, default=0.0, help="serving arrival rate (default: the frozen rate)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
@@ -622,6 +700,9 @@ def main():
         return
     if args.workload == "knn_sweep":
         print(json.dumps(bench_knn_sweep(args)), flush=True)
+        return
+    if args.workload == "tori":
+        print(json.dumps(bench_tori(args)), flush=True)
         return
 
     import torch

@@ -107,7 +107,11 @@ typedef enum fastbcc_status {
  *              sample only when the sample ranks above it, without atomics
  *   bit  24    Last-CC hooks by hashed priority, then relabels every set to
  *              its smallest member
- *   bits 25-26 Last-CC sampling rounds: 0 = as First-CC, k = k - 1 rounds */
+ *   bits 25-26 Last-CC sampling rounds: 0 = as First-CC, k = k - 1 rounds
+ *   bits 27-28 threads per block of the per-vertex kernels of the hot phases
+ *              (union-find sampling, tag sampling and range queries, Last-CC
+ *              tree and sampling passes, read-out searches): 0 = 256, 1 = 64,
+ *              2 = 128, 3 = 512 */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
@@ -118,6 +122,7 @@ typedef enum fastbcc_status {
 #define FASTBCC_TUNE_FREE_FIRST_ROUND 0x800000u
 #define FASTBCC_TUNE_LCC_PRIORITY 0x1000000u
 #define FASTBCC_TUNE_LCC_ROUNDS_SHIFT 25
+#define FASTBCC_TUNE_VERTEX_BLOCK_SHIFT 27
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split
@@ -211,6 +216,48 @@ FASTBCC_API fastbcc_status fastbcc_vertex_labels(int64_t n, int64_t num_arcs, in
                                                  const int32_t* graph_vbegin, const void* workspace,
                                                  size_t workspace_bytes, int32_t* out_home,
                                                  int32_t* out_home_head, void* stream);
+
+/*
+ * The rest of the BC labeling of the last solve on `workspace` (paper:
+ * Section "The BC-labeling Technique", Section "Space-Efficient BCC
+ * Representation" and Algorithm 1's labels and heads), plus the bridges and
+ * the block-cut tree.  Call after a solve on the same workspace, with the same
+ * graph (n, num_arcs, graphs, offsets, adj) and that solve's outputs
+ * edge_label and is_ap, enqueued on the solve's stream or after it.  It
+ * overwrites workspace arrays the solve no longer needs; what
+ * fastbcc_vertex_labels reads stays valid.  For every vertex v:
+ *   out_label[v]      l[v], the paper's vertex label: the vertex that
+ *                     represents v's Last-CC component (its smallest
+ *                     member); the BCC labelled l is {u : l[u] = l} plus
+ *                     its head; -1 for a spanning-tree root;
+ *   out_parent[v]     parent of v in the solve's spanning forest (the tree
+ *                     the labels refer to: head(l[u]) = p(u) whenever
+ *                     l[u] != l[p(u)]); -1 for a root;
+ *   out_cut_parent[v] for an articulation point v that is not a tree root:
+ *                     the canonical id of the BCC in which v is a non-head
+ *                     member, its parent in the block-cut tree; else -1.
+ * The block-cut tree (a forest, one tree per connected component with an
+ * edge): BCC nodes are canonical ids c, cut nodes are articulation points.
+ * The parent of BCC node c is its head (out_home_head of
+ * fastbcc_vertex_labels) when the head is an articulation point, else c is a
+ * root; the parent of cut node v is out_cut_parent[v] (-1: v is a root,
+ * a tree root heading two or more BCCs).  Each (cut vertex, BCC containing
+ * it) pair is exactly one tree edge.
+ * For every arc a:
+ *   out_is_bridge[a]  1 if a belongs to a bridge, a BCC with exactly one
+ *                     edge (parallel copies make a 2-cycle, not a bridge),
+ *                     else 0 (0 for self-loops).
+ * Vertex ids and canonical ids are graph-local in a batch.  offsets_bits is
+ * 32 or 64; flags: FASTBCC_FLAG_SORTED_ROWS (rows are searched instead of
+ * scanned), other bits ignored.  Outputs may be null (not computed);
+ * out_is_bridge needs adj and edge_label, out_cut_parent needs is_ap.
+ */
+FASTBCC_API fastbcc_status fastbcc_bc_labeling(int64_t n, int64_t num_arcs, int32_t num_graphs,
+                                               const int32_t* graph_vbegin, const void* offsets, int32_t offsets_bits,
+                                               const int32_t* adj, const int32_t* edge_label, const uint8_t* is_ap,
+                                               void* workspace, size_t workspace_bytes, uint32_t flags,
+                                               int32_t* out_label, int32_t* out_parent, int32_t* out_cut_parent,
+                                               uint8_t* out_is_bridge, void* stream);
 
 /*
  * Synchronise `stream` and copy the device status word kept in `workspace`

@@ -6,6 +6,7 @@ The compute path is ``libfastbcc.so`` (hand-written HIP for gfx950, C ABI in
 from .api import (  # noqa: F401
     BccResult,
     alloc_workspace,
+    bc_labeling,
     read_device_status,
     solve,
     solve_batched,
@@ -15,5 +16,5 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["BccResult", "alloc_workspace", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
+__all__ = ["BccResult", "alloc_workspace", "bc_labeling", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
            "workspace_size"]

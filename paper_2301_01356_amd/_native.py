@@ -36,6 +36,8 @@ TAG_SAMPLE_CODES = {4: 0, 2: 1, 3: 2, 1: 3}
 TUNE_FREE_FIRST_ROUND = 0x800000
 TUNE_LCC_PRIORITY = 0x1000000
 TUNE_LCC_ROUNDS_SHIFT = 25
+TUNE_VERTEX_BLOCK_SHIFT = 27
+VERTEX_BLOCK_CODES = {256: 0, 64: 1, 128: 2, 512: 3}
 
 EXPORTED = (
     "fastbcc_workspace_size",
@@ -55,6 +57,7 @@ EXPORTED = (
     "fastbcc_trace_reset",
     "fastbcc_vertex_labels",
     "fastbcc_solve_noalloc",
+    "fastbcc_bc_labeling",
 )
 
 
@@ -114,6 +117,8 @@ def lib():
     h.fastbcc_trace_reset.argtypes = [vp]
     h.fastbcc_solve_noalloc.restype = st
     h.fastbcc_solve_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, u32, vp]
+    h.fastbcc_bc_labeling.restype = st
+    h.fastbcc_bc_labeling.argtypes = [i64, i64, i32, vp, vp, i32, vp, vp, vp, vp, sz, u32, vp, vp, vp, vp, vp]
     h.fastbcc_vertex_labels.restype = st
     h.fastbcc_vertex_labels.argtypes = [i64, i64, i32, vp, vp, sz, vp, vp, vp]
     _lib = h
@@ -133,11 +138,13 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
 
 def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False,
                ldd: int = 0, sampled_tags: bool = False, tag_samples: int = 4,
-               free_first_round: bool = False, lcc_priority: bool = False, lcc_rounds=None) -> int:
+               free_first_round: bool = False, lcc_priority: bool = False, lcc_rounds=None,
+               vertex_block: int = 256) -> int:
     """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
     the low-diameter decomposition before First-CC's union-find, beta = 2^-k;
     ``sampled_tags`` certifies fences from ``tag_samples`` (1, 2, 3 or 4)
-    sampled neighbours per vertex first."""
+    sampled neighbours per vertex first; ``vertex_block`` (64, 128, 256 or
+    512) is the block size of the hot per-vertex kernels."""
     f = TUNE_CC_PRIORITY if cc_priority else 0
     f |= TUNE_SAMPLED_TAGS if sampled_tags else 0
     f |= TAG_SAMPLE_CODES[tag_samples] << TUNE_TAG_SAMPLES_SHIFT
@@ -146,6 +153,7 @@ def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc
     if lcc_rounds is not None:
         f |= (int(lcc_rounds) + 1) << TUNE_LCC_ROUNDS_SHIFT
     f |= (ldd & 0x3) << TUNE_LDD_SHIFT
+    f |= VERTEX_BLOCK_CODES[vertex_block] << TUNE_VERTEX_BLOCK_SHIFT
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT
     if sample_rounds is not None:

@@ -296,6 +296,43 @@ def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Option
     return home, head
 
 
+@dataclass
+class BcLabeling:
+    label: torch.Tensor  # int32 [n]: l[v], the vertex representing v's label (-1: tree root)
+    parent: torch.Tensor  # int32 [n]: spanning-forest parent (-1: root)
+    cut_parent: torch.Tensor  # int32 [n]: block-cut tree parent BCC of an articulation point (-1 otherwise)
+    is_bridge: torch.Tensor  # uint8 [num_arcs]: arc of a one-edge BCC
+
+
+def bc_labeling(workspace: torch.Tensor, offsets: torch.Tensor, adj: torch.Tensor, result: BccResult,
+                vbegin: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> BcLabeling:
+    """Labels l[], spanning-forest parents, block-cut tree parents of the
+    articulation points and bridge arcs of the last solve on ``workspace``
+    (``result`` is that solve's output)."""
+    _check_tensor(offsets, "offsets", (torch.int32, torch.int64))
+    dev = offsets.device
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    n, A = offsets.numel() - 1, adj.numel()
+    G = 1
+    if vbegin is not None:
+        _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+        G = vbegin.numel() - 1
+    _check_result(result, n, A, G, dev)
+    _check_workspace(workspace, n, A, G, dev)
+    out = BcLabeling(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+                     torch.empty(n, dtype=torch.int32, device=dev), torch.empty(A, dtype=torch.uint8, device=dev))
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_bc_labeling(
+            n, A, G, _dev_ptr(vbegin), offsets.data_ptr(), 32 if offsets.dtype == torch.int32 else 64,
+            _dev_ptr(adj) if A else None, _dev_ptr(result.edge_label) if A else None,
+            _dev_ptr(result.is_ap) if n else None, workspace.data_ptr(), workspace.numel(), flags,
+            out.label.data_ptr() if n else None, out.parent.data_ptr() if n else None,
+            out.cut_parent.data_ptr() if n else None, out.is_bridge.data_ptr() if A else None,
+            _stream_handle(stream))
+    N.check(st, "fastbcc_bc_labeling")
+    return out
+
+
 def read_device_status(workspace: torch.Tensor, stream=None) -> int:
     """Synchronise ``stream`` and return the status word the last solve on
     ``workspace`` left (0 = no device-side check fired)."""

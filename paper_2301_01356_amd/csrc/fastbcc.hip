@@ -209,6 +209,7 @@ struct Tune {
   bool first_round_free = false;  // First-CC's first sampling round links without atomics
   bool lcc_prio = false;          // Last-CC hooks by hashed priority, then relabels to smallest members
   int lcc_rounds = -1;            // Last-CC sampling rounds (-1: as First-CC)
+  int vertex_block = BLOCK;       // threads per block of the hot per-vertex kernels
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
@@ -218,10 +219,14 @@ bool decode_flags(uint32_t flags, Tune& t) {
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
                          FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
                          FASTBCC_TUNE_FREE_FIRST_ROUND | FASTBCC_TUNE_LCC_PRIORITY |
-                         (0x3u << FASTBCC_TUNE_LCC_ROUNDS_SHIFT);
+                         (0x3u << FASTBCC_TUNE_LCC_ROUNDS_SHIFT) | (0x3u << FASTBCC_TUNE_VERTEX_BLOCK_SHIFT);
   {
     const uint32_t lr = (flags >> FASTBCC_TUNE_LCC_ROUNDS_SHIFT) & 0x3;
     t.lcc_rounds = lr == 0 ? -1 : (int)lr - 1;
+  }
+  {
+    static const int kBlock[4] = {BLOCK, 64, 128, 512};
+    t.vertex_block = kBlock[(flags >> FASTBCC_TUNE_VERTEX_BLOCK_SHIFT) & 0x3];
   }
   t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
   t.lcc_prio = (flags & FASTBCC_TUNE_LCC_PRIORITY) != 0;
@@ -2170,6 +2175,89 @@ __global__ void k_vertex_labels(const int4* __restrict__ rec, const int* __restr
   if (home_head) home_head[v] = h;
 }
 
+// ------------------------------------------------------------ BC labeling: labels, bridges, block-cut tree
+// After a solve, from its workspace.  A BCC with exactly one edge is a bridge.
+// Its two vertices are a tree edge (u, p(u)) (a bridge lies on every spanning
+// tree), u is the only non-head member of the label l[u] (the label's vertex
+// set plus its head is the BCC's vertex set), and the edge u-p(u) has no
+// parallel copy.  mark[L] = 1 when some vertex other than L carries label L.
+__global__ void k_bc_mark(const int4* __restrict__ rec, const int* __restrict__ lab, int n, int* __restrict__ mark) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || rec[v].z < 0) return;
+  const int L = lab[v];
+  if (L != v && ld_relaxed(mark + L) == 0) mark[L] = 1;  // idempotent store, tested first
+}
+
+// Per vertex: the paper's label l[v] and the tree parent (graph-local), the
+// block-cut tree parent of a cut vertex (the BCC in which it is a non-head
+// member), and, for the lone member u of a two-vertex BCC, whether u-p(u) is
+// a single edge; if so, the bit of its BCC's canonical id goes into `bits`.
+__global__ void k_bc_vertex(const int* __restrict__ off, const int* __restrict__ adj, const int4* __restrict__ rec,
+                            const int* __restrict__ lab, const int* __restrict__ canon, const int* __restrict__ mark,
+                            int n, bool sorted_rows, const int* __restrict__ vbegin, int G,
+                            const int* __restrict__ edge_label, const uint8_t* __restrict__ is_ap,
+                            unsigned long long* __restrict__ bits, int* __restrict__ abase,
+                            int* __restrict__ out_label, int* __restrict__ out_parent,
+                            int* __restrict__ out_cut_parent) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int p = rec[u].z;
+  const int base = G > 1 ? vbegin[graph_index(vbegin, G, u)] : 0;
+  const int ab = G > 1 ? off[base] : 0;  // first arc of u's graph: canonical ids are graph-local
+  if (G > 1 && abase) abase[u] = ab;
+  const int L = p >= 0 ? lab[u] : -1;
+  if (out_label) out_label[u] = L >= 0 ? L - base : -1;
+  if (out_parent) out_parent[u] = p >= 0 ? p - base : -1;
+  if (out_cut_parent) out_cut_parent[u] = (p >= 0 && is_ap != nullptr && is_ap[u]) ? canon[L] : -1;
+  if (bits == nullptr || p < 0 || L != u || mark[u] != 0) return;
+  // u alone in its label: the BCC is {u, p}; a bridge iff row u holds p once
+  const int b = off[u], e = off[u + 1];
+  int pos = -1, copies = 0;
+  if (sorted_rows) {
+    int lo = b, hi = e;
+    while (lo < hi) {
+      const int mid = lo + ((hi - lo) >> 1);
+      if (adj[mid] < p) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < e && adj[lo] == p) {
+      pos = lo;
+      copies = (lo + 1 < e && adj[lo + 1] == p) ? 2 : 1;
+    }
+  } else {
+    for (int a = b; a < e && copies < 2; ++a)
+      if (adj[a] == p) {
+        pos = a;
+        ++copies;
+      }
+  }
+  if (copies == 1) {
+    const int c = edge_label[pos];  // the BCC's canonical id, shared by both arcs of the edge
+    if (c >= 0) atomicOr(bits + ((c + ab) >> 6), 1ull << ((c + ab) & 63));
+  }
+}
+
+// Per arc: a bridge arc is one whose BCC's canonical id is marked (made
+// global with the first arc of the row's graph in a batch).
+template <bool BATCH>
+__global__ void k_bc_bridges(const int* __restrict__ off, int n, int64_t A, const int* __restrict__ tile_row, int tw,
+                             const int* __restrict__ edge_label, const int* __restrict__ abase,
+                             const unsigned long long* __restrict__ bits, uint8_t* __restrict__ out) {
+  if (!BATCH) {
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
+      const int c = edge_label[a];
+      out[a] = c >= 0 ? (uint8_t)((bits[c >> 6] >> (c & 63)) & 1) : 0;
+    }
+    return;
+  }
+  arc_tiles(off, n, A, tile_row, tw, [&](int64_t a, int x, bool ok) {
+    if (!ok) return;
+    const int c = edge_label[a];
+    const int g = c + abase[x];
+    out[a] = c >= 0 ? (uint8_t)((bits[g >> 6] >> (g & 63)) & 1) : 0;
+  });
+}
+
 // int64 offsets are narrowed once (every offset is < 2^31 because arcs are).
 __global__ void k_narrow_offsets(const int64_t* __restrict__ in, int64_t count, int* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -2280,6 +2368,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   }
 
   const unsigned gn = grid_for(n);
+  // the per-vertex kernels of the hot phases take the tuned block size
+  const int VB = tune.vertex_block;
+  const unsigned gv = grid_for(n, VB);
   int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
 
   // ---- First-CC (spanning forest)
@@ -2300,12 +2391,12 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   for (int r = 0; r < tune.sample_rounds; ++r) {
     const bool free_round = r == 0 && tune.first_round_free && !tune.ldd;
     if (free_round) {
-      if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gn, BLOCK, off, adj, n, cc, hu, hv);
-      else LAUNCH(c, k_cc_first_round<false>, gn, BLOCK, off, adj, n, cc, hu, hv);
+      if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gv, VB, off, adj, n, cc, hu, hv);
+      else LAUNCH(c, k_cc_first_round<false>, gv, VB, off, adj, n, cc, hu, hv);
     } else if (tune.cc_prio) {
-      LAUNCH(c, k_cc_sample<true>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+      LAUNCH(c, k_cc_sample<true>, gv, VB, off, adj, n, r, cc, hu, hv);
     } else {
-      LAUNCH(c, k_cc_sample<false>, gn, BLOCK, off, adj, n, r, cc, hu, hv);
+      LAUNCH(c, k_cc_sample<false>, gv, VB, off, adj, n, r, cc, hu, hv);
     }
     // flattened for the next round, except after the atomic-free round (its
     // chains are short and the next round's finds walk them anyway) and
@@ -2396,16 +2487,16 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
     LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, scal + S_STATUS);
     rmq_tables(nullptr);
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, true, (int*)nullptr,
+    LAUNCH(c, k_rmq_query, gv, VB, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, true, (int*)nullptr,
            scal + S_STATUS);
   } else {
     // sampled tags certify most non-fences; exact tags for the subtrees of the
     // undecided vertices only
     int* cover = eflag;  // difference array over preorder slots (2n + 1 >= n + 2 ints)
-    LAUNCH(c, k_tag_sample, gn, BLOCK, off, adj, lone, first, rec, n, tune.tag_samples, W, cover, scal,
+    LAUNCH(c, k_tag_sample, gv, VB, off, adj, lone, first, rec, n, tune.tag_samples, W, cover, scal,
            scal + S_STATUS);
     rmq_tables(nullptr);
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, true, cover,
+    LAUNCH(c, k_rmq_query, gv, VB, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_CERTIFY, true, cover,
            scal + S_STATUS);
     scan_inplace(c, cover, (int64_t)n + 1, nullptr, tmp, cover + n + 1);
     int* dirty = w1;  // rows listed for exact tags (w1/w2 are unused with sampled tags)
@@ -2414,25 +2505,25 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     fill_i32(c, (int*)dirty_block, 0, cdiv(L.nb, 4));
     LAUNCH(c, k_tag_rows, TAG_ROWS_GRID, BLOCK, off, adj, dirty, scal + S_DIRTY, first, W, dirty_block);
     rmq_tables(dirty_block);
-    LAUNCH(c, k_rmq_query, gn, BLOCK, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, true, cover,
+    LAUNCH(c, k_rmq_query, gv, VB, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_RECHECK, true, cover,
            scal + S_STATUS);
   }
 
   // ---- Last-CC on the implicit skeleton
   int* lab = I(L.lab);
   if (tune.lcc_prio) {
-    LAUNCH(c, k_lcc_tree_free<true>, gn, BLOCK, rec, n, lab);
-    LAUNCH(c, k_lcc_tree<true>, gn, BLOCK, rec, n, lab);
+    LAUNCH(c, k_lcc_tree_free<true>, gv, VB, rec, n, lab);
+    LAUNCH(c, k_lcc_tree<true>, gv, VB, rec, n, lab);
   } else {
-    LAUNCH(c, k_lcc_tree_free<false>, gn, BLOCK, rec, n, lab);
-    LAUNCH(c, k_lcc_tree<false>, gn, BLOCK, rec, n, lab);
+    LAUNCH(c, k_lcc_tree_free<false>, gv, VB, rec, n, lab);
+    LAUNCH(c, k_lcc_tree<false>, gv, VB, rec, n, lab);
   }
   // flattened before each sampling round; the frontier pass flattens the last state
   const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
   for (int r = 0; r < lcc_rounds; ++r) {
     LAUNCH(c, k_compress, gn, BLOCK, lab, n);
-    if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gn, BLOCK, off, adj, rec, n, r, lab);
-    else LAUNCH(c, k_lcc_sample<false>, gn, BLOCK, off, adj, rec, n, r, lab);
+    if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gv, VB, off, adj, rec, n, r, lab);
+    else LAUNCH(c, k_lcc_sample<false>, gv, VB, off, adj, rec, n, r, lab);
   }
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
   frontier(lab, S_BIG_LAB);
@@ -2467,13 +2558,13 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   LAUNCH(c, k_big_bitmap, (unsigned)cdiv((int64_t)n, BLOCK), BLOCK, lab, n, scal, bigbits);
   LAUNCH(c, k_big_canon, 1, BLOCK, off, adj, rec, lab, head, heads, vbegin, G, scal);
   int4* vlh = (int4*)(w + L.ol);  // the list-ranking array (16n + 8 bytes) is dead by now
-  LAUNCH(c, k_vertex_lh, gn, BLOCK, lab, head, heads, rec, scal, n, vlh);
+  LAUNCH(c, k_vertex_lh, gv, VB, lab, head, heads, rec, scal, n, vlh);
   if (sorted_rows) {
     // canonical labels first, then every arc once with its final label
     int *mpos = I(L.w1), *mcnt = I(L.w2);  // tags are done
-    LAUNCH(c, k_mirror_find, gn, BLOCK, off, adj, n, vlh, scal, minid, mpos, mcnt);
+    LAUNCH(c, k_mirror_find, gv, VB, off, adj, n, vlh, scal, minid, mpos, mcnt);
     fill_i32(c, canon, -1, n);
-    LAUNCH(c, k_canon_first, gn, BLOCK, off, adj, n, rec, lab, vlh, heads, bigbits, scal, minid, vbegin, G, canon);
+    LAUNCH(c, k_canon_first, gv, VB, off, adj, n, rec, lab, vlh, heads, bigbits, scal, minid, vbegin, G, canon);
     LAUNCH(c, k_vertex_canon, gn, BLOCK, canon, n, vlh);
     if (no_loops) {
       const int stride = tw >= ROWS_TILE_WINDOWS ? 1 : ROWS_TILE_WINDOWS / tw;
@@ -2651,6 +2742,67 @@ fastbcc_status fastbcc_vertex_labels(int64_t n, int64_t num_arcs, int32_t num_gr
   LAUNCH(c, k_vertex_labels, grid_for(n), BLOCK, (const int4*)(w + L.rec), (const int*)(w + L.lab),
          (const int*)(w + L.head), (const int*)(w + L.canon), (int)n, graph_vbegin, num_graphs, out_home,
          out_home_head);
+  return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+}
+
+fastbcc_status fastbcc_bc_labeling(int64_t n, int64_t num_arcs, int32_t num_graphs, const int32_t* graph_vbegin,
+                                   const void* offsets, int32_t offsets_bits, const int32_t* adj,
+                                   const int32_t* edge_label, const uint8_t* is_ap, void* workspace,
+                                   size_t workspace_bytes, uint32_t flags, int32_t* out_label, int32_t* out_parent,
+                                   int32_t* out_cut_parent, uint8_t* out_is_bridge, void* stream) {
+  if (n < 0 || num_arcs < 0 || num_graphs < 1 || (num_graphs > 1 && graph_vbegin == nullptr))
+    return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (offsets_bits != 32 && offsets_bits != 64) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  const Layout L = make_layout(n, num_arcs);
+  if (workspace == nullptr || workspace_bytes < L.total) return FASTBCC_ERR_WORKSPACE_TOO_SMALL;
+  if (((uintptr_t)workspace & 255) != 0) return FASTBCC_ERR_INVALID_ARGUMENT;
+  const bool bridges = out_is_bridge != nullptr && num_arcs > 0;
+  if (n > 0 && offsets == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (bridges && (adj == nullptr || edge_label == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (out_cut_parent != nullptr && n > 0 && is_ap == nullptr) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n == 0) return FASTBCC_OK;
+  char* w = (char*)workspace;
+  Ctx c{(hipStream_t)stream};
+  const int nn = (int)n;
+  const int* off32 = (const int*)offsets;
+  if (offsets_bits == 64) {  // narrowed into the workspace, as the solve does
+    int* o = (int*)(w + L.off32);
+    unsigned g = grid_for(n + 1);
+    if (g > 65536) g = 65536;
+    LAUNCH(c, k_narrow_offsets, g, BLOCK, (const int64_t*)offsets, n + 1, o);
+    off32 = o;
+  }
+  // arrays of the solve's tagging phase serve as scratch here: the read-out
+  // state that the BC labeling reads (records, labels, heads, canonical ids)
+  // is left as the solve left it
+  int* mark = (int*)(w + L.w1);
+  int* abase = (int*)(w + L.w2);
+  unsigned long long* bits = (unsigned long long*)(w + L.dbits);  // one bit per arc
+  if (bridges) {
+    fill_i32(c, mark, 0, n);
+    fill_i32(c, (int*)bits, 0, 2 * cdiv(num_arcs, 64));
+    LAUNCH(c, k_bc_mark, grid_for(n), BLOCK, (const int4*)(w + L.rec), (const int*)(w + L.lab), nn, mark);
+  }
+  LAUNCH(c, k_bc_vertex, grid_for(n), BLOCK, off32, adj, (const int4*)(w + L.rec), (const int*)(w + L.lab),
+         (const int*)(w + L.canon), (const int*)mark, nn, (flags & FASTBCC_FLAG_SORTED_ROWS) != 0, graph_vbegin,
+         (int)num_graphs, edge_label, is_ap, bridges ? bits : nullptr, abase, out_label, out_parent, out_cut_parent);
+  if (bridges) {
+    if (num_graphs > 1) {
+      constexpr int tw = MIN_TILE_ARCS / WAVE;  // the tile array holds tiles of at least this many arcs
+      int* tile_row = (int*)(w + L.tile_row);
+      const int64_t ntiles = cdiv(num_arcs, (int64_t)WAVE * tw);
+      LAUNCH(c, k_tile_rows, grid_for(ntiles), BLOCK, off32, nn, num_arcs, (const int*)nullptr, (int64_t)WAVE * tw,
+             tile_row);
+      LAUNCH(c, k_bc_bridges<true>, (unsigned)cdiv(ntiles * WAVE, BLOCK), BLOCK, off32, nn, num_arcs,
+             (const int*)tile_row, tw, edge_label, (const int*)abase, (const unsigned long long*)bits, out_is_bridge);
+    } else {
+      unsigned g = grid_for(num_arcs);
+      if (g > 65536) g = 65536;
+      LAUNCH(c, k_bc_bridges<false>, g, BLOCK, off32, nn, num_arcs, (const int*)nullptr, 0, edge_label,
+             (const int*)nullptr, (const unsigned long long*)bits, out_is_bridge);
+    }
+  }
   return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
 }
 

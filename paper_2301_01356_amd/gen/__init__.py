@@ -198,6 +198,16 @@ def config(name: str) -> Csr:
         return batch()
     if name == "batch_small":
         return batch(seed=14, count=64, nmin=16, nmax=2048)
+    # circular grids of the paper's Table 1 shapes (SQR' and REC': 10^8
+    # vertices, each edge kept with p = 0.6), and smaller ones of the same shape
+    if name == "sqr_torus":
+        return grid(seed=8, rows=10_000, cols=10_000, p=0.6, path_len=0, wrap=True)
+    if name == "rec_torus":
+        return grid(seed=9, rows=1_000, cols=100_000, p=0.6, path_len=0, wrap=True)
+    if name == "sqr_torus_2000":
+        return grid(seed=8, rows=2_000, cols=2_000, p=0.6, path_len=0, wrap=True)
+    if name == "rec_torus_400":
+        return grid(seed=9, rows=400, cols=10_000, p=0.6, path_len=0, wrap=True)
     if name.startswith("knn"):  # "knn<k>": 2^22 points in the unit square, k nearest neighbours
         return family("knn", 1 << 22, int(name[3:]), seed=6)
     raise KeyError(name)

@@ -1,15 +1,15 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes nine speed-only knobs in its flags word (they never change
+The C ABI exposes ten speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
 sampling off), the First-CC union-find variant (hook by id or by hashed
 priority), an optional low-diameter decomposition in front of First-CC's
 union-find (the paper's LDD-UF-JTB shape) with its beta, exact or
 sampled-and-certified tags (and how many samples), an atomic-free first
-sampling round, Last-CC's hooking rule and sampling rounds, and the arc-tile
-size (64-arc windows per wave,
-i.e. work per wave).  The tuner times candidates by
+sampling round, Last-CC's hooking rule and sampling rounds, the arc-tile
+size (64-arc windows per wave, i.e. work per wave) and the block size of the
+hot per-vertex kernels.  The tuner times candidates by
 coordinate descent on the real input, from the fastest of a few seed
 configurations, settles near-ties by a run-off, and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
@@ -40,15 +40,19 @@ TAG_SAMPLES = (4, 3, 2, 1)  # sampled neighbours per vertex when certifying
 FREE = (0, 1)  # First-CC's first sampling round without atomics
 LCC = (0, 1)  # Last-CC hooking: 0 = by id, 1 = by hashed priority + relabelling
 LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)
-START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1}
+VBLOCK = (256, 64, 128, 512)  # threads per block of the hot per-vertex kernels
+START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1,
+         "vb": 256}
 # Starting points: the built-in defaults, the usual winner on power-law graphs
 # and the usual winner on lattices and k-NN graphs.  The descent starts from
 # the fastest of them, so noise between near-equal candidates cannot strand
 # it far from a known good configuration.
 SEEDS = (
     START,
-    {"ruler": 4, "sample": 2, "tile": 4, "uf": 0, "ldd": 0, "tags": 1, "ts": 2, "free": 1, "lcc": 0, "lr": 0},
-    {"ruler": 4, "sample": 1, "tile": 3, "uf": 1, "ldd": 0, "tags": 0, "ts": 4, "free": 1, "lcc": 1, "lr": 0},
+    {"ruler": 4, "sample": 2, "tile": 4, "uf": 0, "ldd": 0, "tags": 1, "ts": 2, "free": 1, "lcc": 0, "lr": 0,
+     "vb": 256},
+    {"ruler": 4, "sample": 1, "tile": 3, "uf": 1, "ldd": 0, "tags": 0, "ts": 4, "free": 1, "lcc": 1, "lr": 0,
+     "vb": 256},
 )
 
 
@@ -80,7 +84,7 @@ def decode(flags: int) -> Dict:
             "ldd": (flags >> N.TUNE_LDD_SHIFT) & 0x3, "tags": int(bool(flags & N.TUNE_SAMPLED_TAGS)),
             "ts": codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3],
             "free": int(bool(flags & N.TUNE_FREE_FIRST_ROUND)), "lcc": int(bool(flags & N.TUNE_LCC_PRIORITY)),
-            "lr": lr - 1}
+            "lr": lr - 1, "vb": {c: b for b, c in N.VERTEX_BLOCK_CODES.items()}[(flags >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3]}
 
 
 def encode(cfg: Dict) -> int:
@@ -88,7 +92,8 @@ def encode(cfg: Dict) -> int:
                         cc_priority=bool(cfg.get("uf", 0)), ldd=int(cfg.get("ldd", 0)),
                         sampled_tags=bool(cfg.get("tags", 0)), tag_samples=int(cfg.get("ts", 4)),
                         free_first_round=bool(cfg.get("free", 0)), lcc_priority=bool(cfg.get("lcc", 0)),
-                        lcc_rounds=None if cfg.get("lr", -1) < 0 else int(cfg["lr"]))
+                        lcc_rounds=None if cfg.get("lr", -1) < 0 else int(cfg["lr"]),
+                        vertex_block=int(cfg.get("vb", 256)))
 
 
 class Tuner:
@@ -140,7 +145,8 @@ class Tuner:
         for _ in range(2):
             changed = False
             for knob, values in (("tags", TAGS), ("uf", UF), ("free", FREE), ("lcc", LCC), ("ldd", LDD), ("sample", SAMPLE),
-                                 ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES), ("lr", LCC_ROUNDS)):
+                                 ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES), ("lr", LCC_ROUNDS),
+                                 ("vb", VBLOCK)):
                 if knob == "ts" and not cfg["tags"]:
                     continue
                 best_v, best_t = cfg[knob], cost(cfg)
@@ -188,7 +194,8 @@ def gpu_arch() -> str:
 # ------------------------------------------------------------ shipped table
 # Benchmark workloads whose tuned configurations ship in ``tuned_gfx950.json``.
 # Every generated input has ascending, loop-free rows, and the solve is told so.
-SHIP_WORKLOADS = ("rmat25", "grid", "plain", "batch4096", "knn2", "knn5", "knn10", "knn15", "knn20")
+SHIP_WORKLOADS = ("rmat25", "grid", "plain", "batch4096", "knn2", "knn5", "knn10", "knn15", "knn20", "sqr_torus",
+                  "rec_torus")
 
 
 def generated_input_flags() -> int:

@@ -80,7 +80,7 @@ def test_solve_argument_errors_are_synchronous():
     assert lib.fastbcc_read_device_status(None, None, ctypes.byref(st)) == N.ERR_INVALID_ARGUMENT
 
 
-@pytest.mark.parametrize("code", range(6))
+@pytest.mark.parametrize("code", range(7))
 def test_status_strings(code):
     s = N.lib().fastbcc_status_string(code).decode()
     assert s and s != "unknown status"
@@ -97,7 +97,10 @@ def test_tune_flag_encoding():
     assert N.tune_flags(ldd=2) == 2 << N.TUNE_LDD_SHIFT
     assert N.tune_flags(sampled_tags=True) == N.TUNE_SAMPLED_TAGS
     assert (N.tune_flags(tag_samples=2) >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3 == 1
-    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 27) == N.ERR_INVALID_ARGUMENT
+    assert (N.tune_flags(vertex_block=512) >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3 == 3
+    assert N.tune_flags(vertex_block=256) == 0
+    # bits above the last tuning field are refused
+    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 29) == N.ERR_INVALID_ARGUMENT
 
 
 def test_host_tensors_are_refused_not_solved_on_the_cpu():

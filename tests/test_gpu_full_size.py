@@ -101,6 +101,21 @@ def test_knn_sweep_full_size_exact(k):
     run_single(f"knn{k}", g, False, sets)
 
 
+@pytest.mark.parametrize("name,tuned", [("sqr_torus_2000", "sqr_torus"), ("rec_torus_400", "rec_torus"),
+                                        ("sqr_torus", "sqr_torus"), ("rec_torus", "rec_torus")])
+def test_paper_tori_exact(name, tuned):
+    """Percolated tori of the paper's SQR' / REC' shapes (p = 0.6), at the
+    smaller sizes the oracle pins against Table 1 and at the full 10^8
+    vertices the benchmark solves, with the tori's shipped flags."""
+    f = shipped_flags(tuned)
+    note(f"{name}: generate")
+    g = gen.config(name)
+    sets = [("benchmarked", f | PROMISES)]
+    if name != tuned:
+        sets.append(("defaults", 0))
+    run_single(name, g, False, sets)
+
+
 def test_batch4096_full_size_exact():
     """The 4096-graph batch in the benchmarked configuration (shipped flags,
     input promises), under the general contract and with the defaults."""

@@ -248,6 +248,8 @@ def test_multigraph_self_loops_unsorted_rows():
     N.tune_flags(free_first_round=True), N.tune_flags(free_first_round=True, cc_priority=True, sample_rounds=1),
     N.tune_flags(lcc_priority=True), N.tune_flags(lcc_priority=True, sampled_tags=True, sample_rounds=0),
     N.tune_flags(lcc_rounds=0), N.tune_flags(lcc_rounds=1, lcc_priority=True, sampled_tags=True),
+    N.tune_flags(vertex_block=64), N.tune_flags(vertex_block=128, cc_priority=True, free_first_round=True),
+    N.tune_flags(vertex_block=512, sampled_tags=True, tag_samples=1, lcc_priority=True),
 ])
 @pytest.mark.parametrize("cfg", ["rmat_small", "grid_small"])
 def test_tuning_fields_never_change_results(flags, cfg):
