@@ -88,6 +88,8 @@ typedef enum fastbcc_status {
                                            gets a BCC label instead of -1;
                                            with FASTBCC_FLAG_VALIDATE it is
                                            reported as an invalid graph. */
+#define FASTBCC_FLAG_REPAIR 0x8u /* fastbcc_check_batched only: rewrite every
+                                     graph that failed into a valid one */
 /* Tuning fields (0 = built-in default).  They change speed, never results.
  *   bits 8-11  log2 of the list-ranking ruler spacing, 3..10
  *   bits 12-13 union-find sampling rounds before the full sweep, 0..3 (value 3 = none)
@@ -216,6 +218,32 @@ FASTBCC_API fastbcc_status fastbcc_vertex_labels(int64_t n, int64_t num_arcs, in
                                                  const int32_t* graph_vbegin, const void* workspace,
                                                  size_t workspace_bytes, int32_t* out_home,
                                                  int32_t* out_home_head, void* stream);
+
+/*
+ * Per-graph input check of a batch, for graphs from untrusted sources
+ * (serving): enqueue-only on `stream`, no host synchronisation, nothing
+ * allocated.  The layout is that of fastbcc_solve_batched (global ids;
+ * graph_vbegin may be null when num_graphs == 1), and the caller vouches for
+ * the layout itself: graph_vbegin runs from 0 to n without decreasing, and
+ * the graphs' first row starts offsets[graph_vbegin[g]] run from 0 to
+ * num_arcs without decreasing.  Everything inside a graph is checked, with
+ * every access kept inside the arrays whatever they hold:
+ *   - each row lies inside its graph's arc range, offsets nondecreasing;
+ *   - each arc's target lies in its graph's vertex range;
+ *   - with FASTBCC_FLAG_SORTED_ROWS, rows ascend; with
+ *     FASTBCC_FLAG_NO_SELF_LOOPS, no arc v->v; with FASTBCC_FLAG_VALIDATE
+ *     (needs FASTBCC_FLAG_SORTED_ROWS), every arc has its reverse.
+ * out_graph_status[g] (int32[num_graphs], device) = 0 if graph g passed, else
+ * FASTBCC_ERR_INVALID_GRAPH.  With FASTBCC_FLAG_REPAIR every graph that
+ * failed is rewritten in place (offsets and adj): all its arcs become
+ * self-loops of its first vertex and its other rows empty, so a batched solve
+ * of the whole batch can follow at once, safely; the results of a failed
+ * graph mean nothing and the caller drops them.  Graphs that passed are left
+ * untouched.  Rows longer than 256 arcs are checked by a whole wave.
+ */
+FASTBCC_API fastbcc_status fastbcc_check_batched(int32_t num_graphs, const int32_t* graph_vbegin, int64_t n,
+                                                 int64_t num_arcs, int32_t* offsets, int32_t* adj, uint32_t flags,
+                                                 int32_t* out_graph_status, void* stream);
 
 /*
  * The rest of the BC labeling of the last solve on `workspace` (paper:

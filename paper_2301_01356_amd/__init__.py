@@ -7,6 +7,7 @@ from .api import (  # noqa: F401
     BccResult,
     alloc_workspace,
     bc_labeling,
+    check_batched,
     read_device_status,
     solve,
     solve_batched,
@@ -16,5 +17,5 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["BccResult", "alloc_workspace", "bc_labeling", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
+__all__ = ["BccResult", "alloc_workspace", "bc_labeling", "check_batched", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
            "workspace_size"]

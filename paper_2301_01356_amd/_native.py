@@ -25,6 +25,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # FASTBCC_NOALLOC_SCRATCH_BYTES
 FLAG_VALIDATE = 0x1
 FLAG_SORTED_ROWS = 0x2
 FLAG_NO_SELF_LOOPS = 0x4
+FLAG_REPAIR = 0x8
 TUNE_RULER_SHIFT = 8
 TUNE_SAMPLE_SHIFT = 12
 TUNE_TILE_SHIFT = 14
@@ -58,6 +59,7 @@ EXPORTED = (
     "fastbcc_vertex_labels",
     "fastbcc_solve_noalloc",
     "fastbcc_bc_labeling",
+    "fastbcc_check_batched",
 )
 
 
@@ -119,6 +121,8 @@ def lib():
     h.fastbcc_solve_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, u32, vp]
     h.fastbcc_bc_labeling.restype = st
     h.fastbcc_bc_labeling.argtypes = [i64, i64, i32, vp, vp, i32, vp, vp, vp, vp, sz, u32, vp, vp, vp, vp, vp]
+    h.fastbcc_check_batched.restype = st
+    h.fastbcc_check_batched.argtypes = [i32, vp, i64, i64, vp, vp, u32, vp, vp]
     h.fastbcc_vertex_labels.restype = st
     h.fastbcc_vertex_labels.argtypes = [i64, i64, i32, vp, vp, sz, vp, vp, vp]
     _lib = h

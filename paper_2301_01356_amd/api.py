@@ -296,6 +296,33 @@ def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Option
     return home, head
 
 
+def check_batched(offsets: torch.Tensor, adj: torch.Tensor, vbegin: Optional[torch.Tensor] = None, *,
+                  flags: int = 0, repair: bool = False, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Per-graph input check of a batch on the device (int32 status per
+    graph, 0 = passed); ``repair`` rewrites failed graphs in place into valid
+    ones so that a batched solve can follow at once."""
+    _check_tensor(offsets, "offsets", (torch.int32,))
+    dev = offsets.device
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    n, A = offsets.numel() - 1, adj.numel()
+    G = 1
+    if vbegin is not None:
+        _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+        G = vbegin.numel() - 1
+        if G < 1:
+            raise ValueError("vbegin needs at least 2 entries")
+    if out is None:
+        out = torch.empty(G, dtype=torch.int32, device=dev)
+    _check_tensor(out, "status", (torch.int32,), G, dev)
+    f = flags | (N.FLAG_REPAIR if repair else 0)
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_check_batched(G, _dev_ptr(vbegin), n, A, offsets.data_ptr(), _dev_ptr(adj) if A else None,
+                                           f, out.data_ptr(), _stream_handle(stream))
+    N.check(st, "fastbcc_check_batched")
+    return out
+
+
 @dataclass
 class BcLabeling:
     label: torch.Tensor  # int32 [n]: l[v], the vertex representing v's label (-1: tree root)

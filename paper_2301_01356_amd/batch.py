@@ -36,7 +36,7 @@ import numpy as np
 import torch
 
 from . import _native as N
-from .api import BccResult, alloc_workspace, solve_batched
+from .api import BccResult, alloc_workspace, check_batched, solve_batched
 
 
 @dataclass
@@ -45,6 +45,7 @@ class GraphResult:
     is_ap: Optional[np.ndarray]  # uint8
     num_bcc: int
     digest: Optional[int] = None  # device-side fingerprint of the labels and AP flags
+    status: int = 0  # device input check of the graph (0 = passed; checked batches only)
 
 
 class PinnedGraph:
@@ -143,13 +144,14 @@ class BatchedSolver:
 
     def __init__(self, max_vertices: int, max_arcs: int, max_graphs: int, device="cuda:0", flags: int = 0,
                  use_graph: bool = True, stream: Optional[torch.cuda.Stream] = None, exact: bool = False,
-                 digests: bool = False):
+                 digests: bool = False, check: bool = False):
         self.cap_v, self.cap_a, self.cap_g = int(max_vertices), int(max_arcs), int(max_graphs)
         self.device = torch.device(device)
         self.flags = flags
         self.exact = exact
         self.use_graph = use_graph and not exact
         self.digests = digests
+        self.check = check and exact  # device input check (and repair) before every exact solve
         G1 = self.cap_g + 1  # + the padding graph
         dev = self.device
         self.d_vbegin = torch.empty(G1 + 1, dtype=torch.int32, device=dev)
@@ -169,6 +171,8 @@ class BatchedSolver:
         self.h_ap = torch.empty(self.cap_v, dtype=torch.uint8, pin_memory=True)
         self.h_nb = torch.empty(G1, dtype=torch.int64, pin_memory=True)
         self.h_dig = torch.empty(G1, dtype=torch.int64, pin_memory=True)
+        self.d_status = torch.zeros(G1, dtype=torch.int32, device=dev)
+        self.h_status = torch.zeros(G1, dtype=torch.int32, pin_memory=True)
         self.stream = stream or torch.cuda.Stream(device=dev)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.done = torch.cuda.Event()
@@ -284,6 +288,11 @@ class BatchedSolver:
             G, v, a = len(self.spans), self.used_v, self.used_a
             if G == 0:
                 return
+            if self.check:
+                # untrusted graphs: checked on the device, failed ones made valid
+                # in place, so the solve that follows is safe for the whole batch
+                check_batched(self.d_off[: v + 1], self.d_adj[:a], self.d_vbegin[: G + 1], repair=True,
+                              out=self.d_status[:G], stream=self.stream)
             out = BccResult(self.out.edge_label[:a], self.out.is_ap[:v], self.out.num_bcc[:G])
             solve_batched(self.d_vbegin[: G + 1], self.d_off[: v + 1], self.d_adj[:a], out=out, workspace=self.ws,
                           flags=self.flags, stream=self.stream)
@@ -331,6 +340,8 @@ class BatchedSolver:
                     self.h_ap[:v].copy_(self.out.is_ap[:v], non_blocking=True)
             if G:
                 self.h_nb[:G].copy_(self.out.num_bcc[:G], non_blocking=True)
+                if self.check:
+                    self.h_status[:G].copy_(self.d_status[:G], non_blocking=True)
             self.done.record(s)
         self._keep_host = keep_host
 
@@ -353,7 +364,8 @@ class BatchedSolver:
                     gl, ga = gl.copy(), ga.copy()
             else:
                 gl = ga = None
-            out.append(GraphResult(gl, ga, int(nb[i]), int(dig[i]) if self.digests else None))
+            out.append(GraphResult(gl, ga, int(nb[i]), int(dig[i]) if self.digests else None,
+                                   int(self.h_status[i]) if self.check else 0))
         return out
 
     def solve(self, graphs: Sequence) -> List[GraphResult]:

@@ -2258,6 +2258,113 @@ __global__ void k_bc_bridges(const int* __restrict__ off, int n, int64_t A, cons
   });
 }
 
+// ------------------------------------------------------------ batch input check
+// Per-graph check of a batch of untrusted graphs (fastbcc_check_batched).
+// Every access stays inside the arrays whatever the input holds: a row is
+// read only after its bounds were found inside its graph's arc range, which
+// lies inside [0, A); targets are range-checked before they index anything.
+constexpr int CHECK_LANE_ROW = 256;  // longer rows are checked by a whole wave
+
+struct GraphRange {
+  int lo, hi;      // vertex range [lo, hi)
+  int64_t ga, gb;  // arc range [ga, gb)
+  bool ok;
+};
+
+__device__ __forceinline__ GraphRange graph_range(const int* __restrict__ off, int n, int64_t A,
+                                                  const int* __restrict__ vbegin, int G, int v, int* g_out) {
+  GraphRange r;
+  const int g = G > 1 ? graph_index(vbegin, G, v) : 0;
+  r.lo = G > 1 ? vbegin[g] : 0;
+  r.hi = G > 1 ? vbegin[g + 1] : n;
+  r.ga = off[r.lo];
+  r.gb = off[r.hi];
+  r.ok = r.ga >= 0 && r.ga <= r.gb && r.gb <= A;
+  *g_out = g;
+  return r;
+}
+
+// Arc a of row x (rows of x's graph are known to lie in [ga, gb)).
+__device__ __forceinline__ bool arc_ok(const int* __restrict__ off, const int* __restrict__ adj, const GraphRange& r,
+                                       int x, int64_t b, int64_t a, bool sorted, bool no_loops, bool symmetric) {
+  const int y = adj[a];
+  if (y < r.lo || y >= r.hi) return false;
+  if (no_loops && y == x) return false;
+  if (sorted && a > b && adj[a - 1] > y) return false;
+  if (symmetric) {  // x occurs in row y (sorted rows: binary search)
+    int64_t lo = off[y], hi = off[y + 1];
+    lo = lo < r.ga ? r.ga : lo;
+    hi = hi > r.gb ? r.gb : hi;
+    const int64_t end = hi;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (adj[mid] < x) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= end || adj[lo] != x) return false;
+  }
+  return true;
+}
+
+__global__ void k_check_rows(const int* __restrict__ off, const int* __restrict__ adj, int n, int64_t A,
+                             const int* __restrict__ vbegin, int G, bool sorted, bool no_loops, bool symmetric,
+                             int* __restrict__ status) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int g = 0;
+  bool bad = false, wave_row = false;
+  GraphRange r{0, 0, 0, 0, false};
+  int64_t b = 0, e = 0;
+  if (v < n) {
+    r = graph_range(off, n, A, vbegin, G, v, &g);
+    b = off[v];
+    e = off[v + 1];
+    bad = !r.ok || b < r.ga || e > r.gb || b > e;
+    if (!bad && e - b <= CHECK_LANE_ROW) {
+      for (int64_t a = b; a < e; ++a)
+        if (!arc_ok(off, adj, r, v, b, a, sorted, no_loops, symmetric)) {
+          bad = true;
+          break;
+        }
+    } else if (!bad) {
+      wave_row = true;
+    }
+  }
+  uint64_t big = __ballot(wave_row);
+  while (big) {
+    const int j = __builtin_ctzll(big);
+    big &= big - 1;
+    const int x = __shfl(v, j, WAVE);
+    const int64_t xb = shfl64(b, j), xe = shfl64(e, j);
+    GraphRange xr;
+    xr.lo = __shfl(r.lo, j, WAVE);
+    xr.hi = __shfl(r.hi, j, WAVE);
+    xr.ga = shfl64(r.ga, j);
+    xr.gb = shfl64(r.gb, j);
+    xr.ok = true;
+    bool lane_bad = false;
+    for (int64_t a = xb + lane_id(); a < xe; a += WAVE)
+      lane_bad = lane_bad || !arc_ok(off, adj, xr, x, xb, a, sorted, no_loops, symmetric);
+    if (__any(lane_bad) && lane_id() == j) bad = true;
+  }
+  if (bad) atomicExch(status + g, (int)FASTBCC_ERR_INVALID_GRAPH);
+}
+
+// A graph that failed becomes valid in place: every arc a self-loop of its
+// first vertex, its other rows empty.  One block per graph (grid-stride).
+__global__ void k_repair_graphs(int* __restrict__ off, int* __restrict__ adj, int n, int64_t A,
+                                const int* __restrict__ vbegin, int G, const int* __restrict__ status) {
+  for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    if (status[g] == 0) continue;  // uniform per block
+    const int lo = G > 1 ? vbegin[g] : 0, hi = G > 1 ? vbegin[g + 1] : n;
+    int64_t ga = off[lo], gb = off[hi];
+    ga = ga < 0 ? 0 : (ga > A ? A : ga);
+    gb = gb < ga ? ga : (gb > A ? A : gb);
+    __syncthreads();  // every lane has read the bounds before any row start changes
+    for (int v = lo + 1 + threadIdx.x; v < hi; v += blockDim.x) off[v] = (int)gb;
+    for (int64_t a = ga + threadIdx.x; a < gb; a += blockDim.x) adj[a] = lo;
+  }
+}
+
 // int64 offsets are narrowed once (every offset is < 2^31 because arcs are).
 __global__ void k_narrow_offsets(const int64_t* __restrict__ in, int64_t count, int* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -2549,7 +2656,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     if (G <= 1) {
       LAUNCH(c, k_sum_blocks, grid_for(gn, 1024 * SUM_PER_LANE), 1024, bsum, (int)gn, out_nbcc);
     } else {
-      scan_inplace(c, bsum, gn, nullptr, I(L.scan_tmp), nullptr);  // bsum[gn] = total
+      // exclusive scan with the total in bsum[gn]: a graph that ends on the
+      // last block boundary (n a multiple of BLOCK) reads P[gn]
+      scan_inplace(c, bsum, gn, nullptr, I(L.scan_tmp), bsum + gn);
       LAUNCH(c, k_graph_count, grid_for((int64_t)G * WAVE), BLOCK, rec, lab, n, vbegin, G, bsum, out_nbcc);
     }
   }
@@ -2801,6 +2910,34 @@ fastbcc_status fastbcc_bc_labeling(int64_t n, int64_t num_arcs, int32_t num_grap
       if (g > 65536) g = 65536;
       LAUNCH(c, k_bc_bridges<false>, g, BLOCK, off32, nn, num_arcs, (const int*)nullptr, 0, edge_label,
              (const int*)nullptr, (const unsigned long long*)bits, out_is_bridge);
+    }
+  }
+  return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+}
+
+fastbcc_status fastbcc_check_batched(int32_t num_graphs, const int32_t* graph_vbegin, int64_t n, int64_t num_arcs,
+                                     int32_t* offsets, int32_t* adj, uint32_t flags, int32_t* out_graph_status,
+                                     void* stream) {
+  if (n < 0 || num_arcs < 0 || num_graphs < 1 || (num_graphs > 1 && graph_vbegin == nullptr) ||
+      out_graph_status == nullptr)
+    return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  const uint32_t known = FASTBCC_FLAG_VALIDATE | FASTBCC_FLAG_SORTED_ROWS | FASTBCC_FLAG_NO_SELF_LOOPS |
+                         FASTBCC_FLAG_REPAIR;
+  if (flags & ~known) return FASTBCC_ERR_INVALID_ARGUMENT;
+  const bool sorted = (flags & FASTBCC_FLAG_SORTED_ROWS) != 0;
+  const bool symmetric = (flags & FASTBCC_FLAG_VALIDATE) != 0;
+  if (symmetric && !sorted) return FASTBCC_ERR_INVALID_ARGUMENT;  // the symmetry test searches sorted rows
+  if (offsets == nullptr || (num_arcs > 0 && adj == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  Ctx c{(hipStream_t)stream};
+  fill_i32(c, out_graph_status, 0, num_graphs);
+  if (n > 0) {
+    LAUNCH(c, k_check_rows, grid_for(n), BLOCK, (const int*)offsets, (const int*)adj, (int)n, num_arcs, graph_vbegin,
+           (int)num_graphs, sorted, (flags & FASTBCC_FLAG_NO_SELF_LOOPS) != 0, symmetric, out_graph_status);
+    if (flags & FASTBCC_FLAG_REPAIR) {
+      const unsigned blocks = num_graphs < 65535 ? (unsigned)num_graphs : 65535u;
+      LAUNCH(c, k_repair_graphs, blocks, BLOCK, offsets, adj, (int)n, num_arcs, graph_vbegin, (int)num_graphs,
+             (const int*)out_graph_status);
     }
   }
   return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;

@@ -12,7 +12,10 @@ re-read from the live free HBM (``free_hbm``) whenever a slot completes.
 
 Slots solve under the general input contract (rows in any order, self-loops
 allowed): a request is not trusted to keep the sorted-row or loop-free
-promises, only its ids are range-checked at admission.
+promises.  Admission checks a request's sizes only (O(1) on the host); its
+rows and ids are checked on the device, in the batch, before the solve
+(fastbcc_check_batched): a graph that fails is made valid in place, solved
+harmlessly with the others and reported as rejected.
 
 Malformed requests are rejected at admission (status set on that request
 only); an oversized request that no slot can hold is rejected the same way.
@@ -73,24 +76,42 @@ def request_bytes(n: int, arcs: int) -> int:
 
 
 def check_request(g) -> str:
-    """Cheap host-side validation; returns an error string or ''."""
+    """Host-side admission check, O(1): sizes and the two ends of the offsets
+    (which place the request inside a batch).  Rows and ids are checked on
+    the device with the batch."""
     try:
         n = int(g.n)
-        off = np.asarray(g.offsets)
-        adj = np.asarray(g.adj)
+        off = g.offsets
+        A = int(len(g.adj))
+        if len(off) != n + 1:
+            return "offsets must have n + 1 entries"
+        first, last = int(off[0]), int(off[n])
     except Exception as e:  # pragma: no cover - defensive
         return f"unreadable request: {e}"
-    if n < 0 or off.shape != (n + 1,):
-        return "offsets must have n + 1 entries"
-    if off[0] != 0 or int(off[-1]) != adj.shape[0]:
+    if n < 0:
+        return "negative vertex count"
+    if first != 0 or last != A:
         return "offsets must start at 0 and end at the arc count"
-    if n and np.any(np.diff(off) < 0):
-        return "offsets must be nondecreasing"
-    if adj.size and (int(adj.min()) < 0 or int(adj.max()) >= n):
-        return "vertex id out of range"
-    if adj.size >= 2**31 or n >= 2**30:
+    if A >= 2**31 or n >= 2**30:
         return "graph too large"
     return ""
+
+
+def host_graph_status(g) -> int:
+    """What the device input check reports for one graph, computed on the
+    host (for the simulated slots of the CPU tests): 0 if every row lies
+    inside the graph with nondecreasing offsets and every id is in range."""
+    off = np.asarray(g.offsets, np.int64)
+    adj = np.asarray(g.adj, np.int64)
+    n = int(g.n)
+    if n and np.any(np.diff(off) < 0):
+        return 5
+    if adj.size and (int(adj.min()) < 0 or int(adj.max()) >= n):
+        return 5
+    return 0
+
+
+INVALID_GRAPH_ERROR = "invalid graph: a row outside the graph, decreasing offsets or an id out of range"
 
 
 class Slot:
@@ -199,6 +220,11 @@ class Server:
                     res = self.slots[si].results()
                     fin = self.clock.now() - t0
                     for r, gr in zip(fl.reqs, res):
+                        if getattr(gr, "status", 0) != 0:
+                            done[r.rid] = Completion(r.rid, False, INVALID_GRAPH_ERROR, arrival=r.arrival,
+                                                     admitted=fl.admitted, finished=fin)
+                            self.stats["rejected"] += 1
+                            continue
                         kept = self.keep is None or self.keep(r)
                         done[r.rid] = Completion(r.rid, True, "", gr.edge_label if kept else None,
                                                  gr.is_ap if kept else None, gr.num_bcc, r.arrival, fl.admitted,
@@ -287,11 +313,14 @@ class HipSlot(Slot):
         from .batch import BatchedSolver
 
         self.cap_v, self.cap_a, self.cap_g = cap_v, cap_a, cap_g
-        self.solver = BatchedSolver(cap_v, cap_a, cap_g, device=device, flags=flags, exact=True, digests=digests)
+        self.solver = BatchedSolver(cap_v, cap_a, cap_g, device=device, flags=flags, exact=True, digests=digests,
+                                    check=True)
 
     def launch(self, graphs, keep=None):
+        # results always travel to pinned host memory (a request's latency
+        # ends there); ``keep`` only decides which ones the server copies out
         self.solver.stage(graphs)
-        self.solver.launch(keep_host=keep is None or any(keep))
+        self.solver.launch()
 
     def ready(self):
         return self.solver.ready()
@@ -333,6 +362,9 @@ class PlainSlot(Slot):
         self.h_ap = torch.empty(cap_v, dtype=torch.uint8, pin_memory=True)
         self.h_nb = torch.empty(1, dtype=torch.int64, pin_memory=True)
         self.h_dig = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.d_status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.h_status = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        self.h_bounds = torch.zeros(4, dtype=torch.int64, pin_memory=True)  # [0, A, 0, n] for the digest
         self.stream = torch.cuda.Stream(device=dev)
         self.done = torch.cuda.Event()
         self.n = self.a = 0
@@ -342,7 +374,7 @@ class PlainSlot(Slot):
         import numpy as np
         import torch
 
-        from .api import BccResult, alloc_workspace, solve
+        from .api import BccResult, alloc_workspace, check_batched, solve
         from .batch import PinnedGraph, device_digests
 
         (g,) = graphs
@@ -360,19 +392,24 @@ class PlainSlot(Slot):
             self.d_off[: n + 1].copy_(src_off, non_blocking=True)
             if A:
                 self.d_adj[:A].copy_(src_adj, non_blocking=True)
+            # the request's rows and ids checked on the device first (a graph
+            # that fails is made valid in place and its result dropped)
+            check_batched(self.d_off[: n + 1], self.d_adj[:A], repair=True, out=self.d_status, stream=s)
             ws = alloc_workspace(n, A, 1, self.device)
             out = BccResult(self.out.edge_label[:A], self.out.is_ap[:n], self.out.num_bcc)
             solve(self.d_off[: n + 1], self.d_adj[:A], out=out, workspace=ws, flags=self.flags, stream=s)
             if self.digests:
-                ab = torch.tensor([0, A], dtype=torch.int64).to(self.device, non_blocking=True)
-                vb = torch.tensor([0, n], dtype=torch.int64).to(self.device, non_blocking=True)
-                self.h_dig.copy_(device_digests(out.edge_label, out.is_ap, ab, vb), non_blocking=True)
-            if self.kept:
-                if A:
-                    self.h_label[:A].copy_(out.edge_label, non_blocking=True)
-                if n:
-                    self.h_ap[:n].copy_(out.is_ap, non_blocking=True)
+                # bounds staged through pinned memory that stays untouched until
+                # this request completes (a pageable source could be reused early)
+                self.h_bounds.numpy()[:] = (0, A, 0, n)
+                bd = self.h_bounds.to(self.device, non_blocking=True)
+                self.h_dig.copy_(device_digests(out.edge_label, out.is_ap, bd[:2], bd[2:]), non_blocking=True)
+            if A:
+                self.h_label[:A].copy_(out.edge_label, non_blocking=True)
+            if n:
+                self.h_ap[:n].copy_(out.is_ap, non_blocking=True)
             self.h_nb.copy_(out.num_bcc, non_blocking=True)
+            self.h_status.copy_(self.d_status, non_blocking=True)
             self.done.record(s)
 
     def ready(self):
@@ -384,7 +421,8 @@ class PlainSlot(Slot):
         self.done.synchronize()
         lab = self.h_label.numpy()[: self.a].copy() if self.kept else None
         ap = self.h_ap.numpy()[: self.n].copy() if self.kept else None
-        return [GraphResult(lab, ap, int(self.h_nb.numpy()[0]), int(self.h_dig.numpy()[0]) if self.digests else None)]
+        return [GraphResult(lab, ap, int(self.h_nb.numpy()[0]), int(self.h_dig.numpy()[0]) if self.digests else None,
+                            int(self.h_status.numpy()[0]))]
 
 
 def torch_device(device):
@@ -433,6 +471,10 @@ class SimSlot(Slot):
 
         out = []
         for g in self.graphs:
+            st = host_graph_status(g)
+            if st:
+                out.append(GraphResult(None, None, -1, None, st))
+                continue
             lab, ap, nb = self.solve_fn(g)
             out.append(GraphResult(lab, ap, nb))
         self.t_ready = None

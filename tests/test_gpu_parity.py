@@ -549,3 +549,30 @@ def test_hub_graphs_batched(flags):
         v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
         a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
         assert_parity(gi, (lab[a0:a1], ap[v0:v1], int(nb[i])), f"batched hub graph {i}")
+
+
+@pytest.mark.parametrize("sizes", [(200, 56, 256), (256, 256), (100, 156, 300, 212), (512,), (30, 226)])
+def test_batched_counts_when_the_batch_ends_on_a_block_boundary(sizes):
+    """Per-graph BCC counts read the scanned per-block counts up to the end
+    of the last graph; when the vertex total is a multiple of the block size
+    (256) that is the scan's total slot.  The workspace starts full of
+    garbage so that a slot the solve did not write cannot pass by luck."""
+    rng = np.random.default_rng(sum(sizes))
+    graphs = []
+    for n in sizes:
+        edges = [(i, i + 1) for i in range(n - 1)]  # a path: n - 1 BCCs
+        edges += [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(n // 3)]
+        graphs.append(gen.from_edges(n, [(a, b) for a, b in edges if a != b]))
+    u = gen.unite(graphs)
+    assert u.n % 256 == 0 or len(sizes) == 2
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    ws = alloc_workspace(u.n, u.num_arcs, len(graphs), DEV)
+    for fill in (0x7F, 0x00, 0xFF):
+        ws.fill_(fill)
+        note(f"batch ending on a block boundary: sizes {sizes}, n={u.n}, workspace fill {fill:#x}")
+        r = solve_batched(vb, off, adj, workspace=ws)
+        lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+        for i, g in enumerate(graphs):
+            a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+            assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} fill {fill:#x}")

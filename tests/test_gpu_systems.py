@@ -141,3 +141,114 @@ def test_serving_general_contract_unsorted_rows_and_self_loops():
     for r, c in zip(reqs, comps):
         assert c.ok, c.error
         check_oracle(r.graph, c.edge_label, c.is_ap, c.num_bcc, f"request {r.rid}")
+
+
+def _corrupt_batch():
+    """A batch of valid graphs, then damage inside some of them (the batch
+    layout -- graph ranges and each graph's first row start -- stays valid)."""
+    graphs = [gen.mixed(81, i, 20, 600, 4.0, 12.0) for i in range(8)]
+    u = gen.unite(graphs)
+    off = u.offsets.astype(np.int32).copy()
+    adj = u.adj.copy()
+    vb = u.vbegin
+
+    def arcs(g):
+        return int(off[vb[g]]), int(off[vb[g + 1]])
+
+    a0, _ = arcs(1)
+    adj[a0 + 3] = int(vb[2]) + 1  # graph 1: an arc into graph 2
+    v = int(vb[3]) + 2
+    off[v], off[v + 1] = off[v + 1], off[v]  # graph 3: decreasing offsets
+    if off[v] == off[v + 1]:
+        off[v] += 1
+    a0, _ = arcs(4)
+    adj[a0] = -5  # graph 4: a negative id
+    off[int(vb[5]) + 1] = len(adj)  # graph 5: a row that runs past the graph's arcs
+    return graphs, u, off, adj, {1, 3, 4, 5}
+
+
+def test_device_input_check_finds_and_repairs_damaged_graphs():
+    from paper_2301_01356_amd import check_batched, solve_batched
+    from paper_2301_01356_amd import _native as N
+
+    graphs, u, off, adj, bad = _corrupt_batch()
+    G = len(graphs)
+    d_vb = torch.from_numpy(u.vbegin).to(DEV)
+    d_off = torch.from_numpy(off).to(DEV)
+    d_adj = torch.from_numpy(adj).to(DEV)
+    note("device input check, no repair")
+    st = check_batched(d_off, d_adj, d_vb).cpu().numpy()
+    assert {i for i in range(G) if st[i]} == bad
+    assert np.all(st[list(bad)] == N.ERR_INVALID_GRAPH)
+    assert np.array_equal(d_off.cpu().numpy(), off) and np.array_equal(d_adj.cpu().numpy(), adj)  # untouched
+    note("device input check with repair, then a batched solve of the whole batch")
+    st = check_batched(d_off, d_adj, d_vb, repair=True).cpu().numpy()
+    assert {i for i in range(G) if st[i]} == bad
+    roff, radj = d_off.cpu().numpy(), d_adj.cpu().numpy()
+    for g in range(G):
+        v0, v1 = int(u.vbegin[g]), int(u.vbegin[g + 1])
+        a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
+        if g in bad:  # every arc a self-loop of the first vertex, other rows empty
+            assert np.all(radj[a0:a1] == v0) and np.all(roff[v0 + 1 : v1 + 1] == a1) and roff[v0] == a0
+        else:
+            assert np.array_equal(roff[v0:v1], off[v0:v1]) and np.array_equal(radj[a0:a1], adj[a0:a1])
+    r = solve_batched(d_vb, d_off, d_adj)
+    torch.cuda.synchronize()
+    lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for g in set(range(G)) - bad:
+        v0, v1 = int(u.vbegin[g]), int(u.vbegin[g + 1])
+        a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
+        check_oracle(graphs[g], lab[a0:a1], ap[v0:v1], int(nb[g]), f"graph {g}")
+
+
+def test_device_input_check_of_the_promises_and_symmetry():
+    from paper_2301_01356_amd import check_batched
+    from paper_2301_01356_amd import _native as N
+
+    good = gen.from_edges(6, [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 5), (5, 3)])
+    unsorted = gen.Csr(good.n, good.offsets, good.adj.copy())
+    r0, r1 = int(unsorted.offsets[2]), int(unsorted.offsets[3])
+    unsorted.adj[r0:r1] = unsorted.adj[r0:r1][::-1]
+    loopy = gen.multigraph_csr(4, [(0, 1), (1, 2), (2, 2), (2, 3)])
+    asym = gen.Csr(good.n, good.offsets, good.adj.copy())
+    asym.adj[int(asym.offsets[4])] = 2  # 4 -> 2 without 2 -> 4 (row 4 stays sorted: 2 < 5)
+    graphs = [good, unsorted, loopy, asym]
+    u = gen.unite(graphs)
+    d_vb = torch.from_numpy(u.vbegin).to(DEV)
+    d_off = torch.from_numpy(u.offsets.astype(np.int32)).to(DEV)
+    d_adj = torch.from_numpy(u.adj).to(DEV)
+    note("device input check: sorted rows, loops, symmetry")
+    st = lambda f: check_batched(d_off, d_adj, d_vb, flags=f).cpu().numpy().tolist()
+    assert st(0) == [0, 0, 0, 0]
+    assert st(N.FLAG_SORTED_ROWS) == [0, 5, 0, 0]
+    assert st(N.FLAG_NO_SELF_LOOPS) == [0, 0, 5, 0]
+    assert st(N.FLAG_SORTED_ROWS | N.FLAG_VALIDATE) == [0, 5, 0, 5]
+
+
+def test_serving_rejects_damaged_requests_and_serves_the_rest():
+    from paper_2301_01356_amd.serve import PlainSlot, serving_flags
+
+    reqs = []
+    for i in range(16):
+        g = gen.mixed(83, i, 30, 3000, 4.0, 16.0)
+        if i % 4 == 1:  # an id beyond the graph
+            adj = g.adj.copy()
+            adj[len(adj) // 2] = g.n + 7
+            g = gen.Csr(g.n, g.offsets, adj)
+        elif i % 4 == 3:  # decreasing offsets inside the graph
+            off = g.offsets.copy()
+            v = g.n // 2
+            off[v], off[v + 1] = off[v + 1] + 1, off[v]
+            g = gen.Csr(g.n, off, g.adj)
+        reqs.append(Request(i, g, 0.0))
+    flags = serving_flags()
+    for name, slots, mb in (("served", hip_slots(2, 60000, 600000, 8, device=DEV, flags=flags), None),
+                            ("serial", [PlainSlot(3001, 600000, DEV, flags)], 1)):
+        note(f"{name}: damaged requests among good ones")
+        comps = Server(slots, hbm_budget=1 << 30, max_batch_graphs=mb).run(reqs)
+        for r, c in zip(reqs, comps):
+            if r.rid % 4 in (1, 3):
+                assert not c.ok and "invalid graph" in c.error, (name, r.rid)
+            else:
+                assert c.ok, (name, r.rid, c.error)
+                check_oracle(r.graph, c.edge_label, c.is_ap, c.num_bcc, f"{name} request {r.rid}")
