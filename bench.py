@@ -582,6 +582,11 @@ def bench_serve(args):
     # capacities: the same requests all queued at t = 0, served (continuous
     # batching over the slots) and serial (one plain solve at a time)
     n_cap = args.capacity_requests
+    # warm-up: the first batches of each kind allocate the temporaries that the
+    # caching allocator then keeps
+    warm, _ = stream_of(200, np.zeros(200), 49)
+    run(warm, slots)
+    run(warm[:50], [serial_slot], max_batch=1)
     reqs, _ = stream_of(n_cap, np.zeros(n_cap), 50)
     comps, st, wall = run(reqs, slots)
     cap = n_cap / wall

@@ -559,6 +559,18 @@ __global__ void k_compress(int* p, int n) {
   if (ld_relaxed(p + v) != r) st_relaxed(p + v, r);
 }
 
+// Every entry onto its root, guaranteed: reads only, writes its own entry.
+// Run after a path-halving pass, whose concurrent writes can leave a few
+// entries on an ancestor below the root (those walks are then short); the
+// passes that read p[v] as the set's id (Rooting's component ids, the
+// read-out's labels, the relabelling) need every entry on its root.
+__global__ void k_flatten(int* p, int n) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int r = uf_root_ro(p, v);
+  if (ld_relaxed(p + v) != r) st_relaxed(p + v, r);
+}
+
 // ------------------------------------------------------------ validation
 // Graph g of a batch owns vertices [vbegin[g], vbegin[g+1]) (vbegin already
 // checked to be nondecreasing from 0 to n).
@@ -2522,6 +2534,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *hubidx = I(L.hubidx), *shard = I(L.shard);
   fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
   LAUNCH(c, k_edge_flags, gn, BLOCK, off, hu, n, cc, eid, headp, hubidx, scal);
+  LAUNCH(c, k_flatten, gn, BLOCK, cc, n);  // Rooting reads cc[v] as the component id
   scan_inplace(c, eid, n, nullptr, tmp, eid + n);
   LAUNCH(c, k_edge_compact, gn, BLOCK, hu, hv, eid, n, eu, ev);
   const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
@@ -2637,6 +2650,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   if (tune.lcc_prio) LAUNCH(c, k_lcc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
   else LAUNCH(c, k_lcc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
   LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+  LAUNCH(c, k_flatten, gn, BLOCK, lab, n);  // the relabelling and the read-out read lab[v] as the label
   if (tune.lcc_prio) {
     int* minv = I(L.minid);  // refilled by the read-out
     fill_i32(c, minv, INT32_MAX, n);

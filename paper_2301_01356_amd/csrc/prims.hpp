@@ -174,6 +174,20 @@ __device__ __forceinline__ int uf_find(int* p, int x) {
   return x;
 }
 
+// Root of x without writing anything.  Used where one pass must leave every
+// entry pointing at its root: path-halving writes of concurrent finds can
+// store a stale ancestor over an entry that its own thread had just set to
+// the root, so a flattening pass that needs a guarantee reads only and writes
+// nothing but its own entry.
+__device__ __forceinline__ int uf_root_ro(const int* p, int x) {
+  int px = ld_relaxed(p + x);
+  while (px != x) {
+    x = px;
+    px = ld_relaxed(p + x);
+  }
+  return x;
+}
+
 // Union by CAS: the larger root goes under the smaller one.  Two vertices
 // with the same parent are in the same set: that common case returns without
 // touching the (hot) root slot.

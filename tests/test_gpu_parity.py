@@ -576,3 +576,28 @@ def test_batched_counts_when_the_batch_ends_on_a_block_boundary(sizes):
         for i, g in enumerate(graphs):
             a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
             assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} fill {fill:#x}")
+
+
+def test_priority_last_cc_labels_stable_over_repeated_solves():
+    """Last-CC hooking by priority relabels every set to its smallest member
+    and the read-out reads lab[v] as the label, so every entry must sit on its
+    set's root after the last compression.  Concurrent path halving could
+    leave an entry on a stale ancestor, which split a BCC in about one solve
+    in a thousand on this tree-like graph; the flattening pass that reads only
+    rules that out.  2000 solves, each compared with the oracle on the device."""
+    from paper_2301_01356_amd.serve import serving_flags
+
+    g = gen.mixed(5, 2, 1 << 10, 1 << 22, 4.0, 32.0)
+    lab, ap, nb, _, _ = oracle.ht_bcc(g.offsets, g.adj)
+    off, adj = to_dev(g)
+    rl = torch.from_numpy(lab).to(DEV)
+    ra = torch.from_numpy(ap).to(DEV)
+    ws = alloc_workspace(g.n, g.num_arcs, 1, DEV)
+    flags = serving_flags()
+    note(f"2000 priority Last-CC solves n={g.n} arcs={g.num_arcs} flags={flags:#x}")
+    bad = torch.zeros((), dtype=torch.int64, device=DEV)
+    for _ in range(2000):
+        r = solve(off, adj, workspace=ws, flags=flags)
+        bad += (r.edge_label != rl).any() | (r.is_ap != ra).any() | (r.num_bcc[0] != nb)
+    assert int(bad.item()) == 0
+    assert read_device_status(ws) == 0
