@@ -112,18 +112,18 @@ def random_accesses(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "c91d97a0f6f53577",
+    "src_sha": "80f962138b6cce9f",
     "workload": "rmat25",
-    "flags": 0x2B12306,
+    "flags": 0x2B32506,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378476.1, "write_kib": 4090690.6},
-    "k_tag_sample": {"fetch_kib": 2378303.6, "write_kib": 1445424.3},
-    "k_cc_sample": {"fetch_kib": 2372999.0, "write_kib": 659098.0},
-    "k_lr_walk": {"fetch_kib": 1053374.9, "write_kib": 1080994.8},
-    "k_rmq_query": {"fetch_kib": 871825.9, "write_kib": 67939.5},
-    "k_tree_link": {"fetch_kib": 1246462.6, "write_kib": 829752.9},
-    "k_mirror_find": {"fetch_kib": 2068611.6, "write_kib": 312075.5},
-    "k_lcc_tree": {"fetch_kib": 710019.0, "write_kib": 218539.7},
+    "k_bcc_rows": {"fetch_kib": 378463.5, "write_kib": 4090677.4},
+    "k_tag_sample": {"fetch_kib": 2377793.6, "write_kib": 1445420.6},
+    "k_cc_sample": {"fetch_kib": 2316651.3, "write_kib": 732185.6},
+    "k_lr_walk": {"fetch_kib": 1411174.5, "write_kib": 1063916.0},
+    "k_rmq_query": {"fetch_kib": 871275.9, "write_kib": 67796.0},
+    "k_tree_link": {"fetch_kib": 1257097.9, "write_kib": 830754.3},
+    "k_mirror_find": {"fetch_kib": 2068584.6, "write_kib": 312027.7},
+    "k_lcc_tree": {"fetch_kib": 862530.1, "write_kib": 297130.0},
 }
 
 
