@@ -113,7 +113,12 @@ typedef enum fastbcc_status {
  *   bits 27-28 threads per block of the per-vertex kernels of the hot phases
  *              (union-find sampling, tag sampling and range queries, Last-CC
  *              tree and sampling passes, read-out searches): 0 = 256, 1 = 64,
- *              2 = 128, 3 = 512 */
+ *              2 = 128, 3 = 512
+ *   bit  29    flatten First-CC's sets after its atomic-free first round too
+ *              (the next sampling round's finds then take one hop)
+ *   bit  30    XCD-ordered per-vertex launches: each of the GPU's 8 XCDs (each
+ *              with its own L2) takes one contiguous run of vertices, which
+ *              keeps graph-local accesses (a batch's graphs, lattices) in one L2 */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
@@ -125,6 +130,8 @@ typedef enum fastbcc_status {
 #define FASTBCC_TUNE_LCC_PRIORITY 0x1000000u
 #define FASTBCC_TUNE_LCC_ROUNDS_SHIFT 25
 #define FASTBCC_TUNE_VERTEX_BLOCK_SHIFT 27
+#define FASTBCC_TUNE_COMPRESS_FREE_ROUND 0x20000000u
+#define FASTBCC_TUNE_XCD_ORDER 0x40000000u
 
 /*
  * Workspace bytes needed for a graph with n vertices and num_arcs arcs split

@@ -38,6 +38,8 @@ TUNE_FREE_FIRST_ROUND = 0x800000
 TUNE_LCC_PRIORITY = 0x1000000
 TUNE_LCC_ROUNDS_SHIFT = 25
 TUNE_VERTEX_BLOCK_SHIFT = 27
+TUNE_COMPRESS_FREE_ROUND = 0x20000000
+TUNE_XCD_ORDER = 0x40000000
 VERTEX_BLOCK_CODES = {256: 0, 64: 1, 128: 2, 512: 3}
 
 EXPORTED = (
@@ -143,7 +145,7 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
 def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False,
                ldd: int = 0, sampled_tags: bool = False, tag_samples: int = 4,
                free_first_round: bool = False, lcc_priority: bool = False, lcc_rounds=None,
-               vertex_block: int = 256) -> int:
+               vertex_block: int = 256, compress_free_round: bool = False, xcd_order: bool = False) -> int:
     """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
     the low-diameter decomposition before First-CC's union-find, beta = 2^-k;
     ``sampled_tags`` certifies fences from ``tag_samples`` (1, 2, 3 or 4)
@@ -158,6 +160,8 @@ def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc
         f |= (int(lcc_rounds) + 1) << TUNE_LCC_ROUNDS_SHIFT
     f |= (ldd & 0x3) << TUNE_LDD_SHIFT
     f |= VERTEX_BLOCK_CODES[vertex_block] << TUNE_VERTEX_BLOCK_SHIFT
+    f |= TUNE_COMPRESS_FREE_ROUND if compress_free_round else 0
+    f |= TUNE_XCD_ORDER if xcd_order else 0
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT
     if sample_rounds is not None:

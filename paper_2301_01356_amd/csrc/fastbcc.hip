@@ -210,6 +210,8 @@ struct Tune {
   bool lcc_prio = false;          // Last-CC hooks by hashed priority, then relabels to smallest members
   int lcc_rounds = -1;            // Last-CC sampling rounds (-1: as First-CC)
   int vertex_block = BLOCK;       // threads per block of the hot per-vertex kernels
+  bool compress_free = false;     // flatten the sets after the atomic-free round too
+  bool xcd = false;               // per-vertex launches in XCD-ordered shape
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
@@ -219,7 +221,8 @@ bool decode_flags(uint32_t flags, Tune& t) {
                          FASTBCC_TUNE_CC_PRIORITY | (0x3u << FASTBCC_TUNE_LDD_SHIFT) |
                          FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
                          FASTBCC_TUNE_FREE_FIRST_ROUND | FASTBCC_TUNE_LCC_PRIORITY |
-                         (0x3u << FASTBCC_TUNE_LCC_ROUNDS_SHIFT) | (0x3u << FASTBCC_TUNE_VERTEX_BLOCK_SHIFT);
+                         (0x3u << FASTBCC_TUNE_LCC_ROUNDS_SHIFT) | (0x3u << FASTBCC_TUNE_VERTEX_BLOCK_SHIFT) |
+                         FASTBCC_TUNE_COMPRESS_FREE_ROUND | FASTBCC_TUNE_XCD_ORDER;
   {
     const uint32_t lr = (flags >> FASTBCC_TUNE_LCC_ROUNDS_SHIFT) & 0x3;
     t.lcc_rounds = lr == 0 ? -1 : (int)lr - 1;
@@ -229,6 +232,8 @@ bool decode_flags(uint32_t flags, Tune& t) {
     t.vertex_block = kBlock[(flags >> FASTBCC_TUNE_VERTEX_BLOCK_SHIFT) & 0x3];
   }
   t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
+  t.compress_free = (flags & FASTBCC_TUNE_COMPRESS_FREE_ROUND) != 0;
+  t.xcd = (flags & FASTBCC_TUNE_XCD_ORDER) != 0;
   t.lcc_prio = (flags & FASTBCC_TUNE_LCC_PRIORITY) != 0;
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
   static const int kSamples[4] = {4, 2, 3, 1};
@@ -249,6 +254,18 @@ bool decode_flags(uint32_t flags, Tune& t) {
     t.tile_windows = 1 << w;
   }
   return true;
+}
+
+// ------------------------------------------------------------ XCD-ordered launches
+// MI355X hands workgroup i of a launch to XCD i mod 8, and each XCD has its
+// own L2.  A per-vertex launch of shape (8, per) puts the logical blocks
+// k*per .. k*per + per - 1 (one contiguous run of vertices) on XCD k, so a
+// kernel whose accesses stay near its own vertex (the graphs of a batch,
+// lattices) keeps them in one L2.  The index below is the logical one for
+// both shapes: a plain launch (blocks, 1) gives the usual numbering.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int vertex_index() {
+  return (int)(((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------ small kernels
@@ -291,7 +308,7 @@ __global__ void k_tile_rows(const int* __restrict__ off, int n, int64_t A, const
 // before it need not.
 __global__ void k_frontier_deg(const int* __restrict__ off, int* comp, const int* __restrict__ scal, int slot, int n,
                                const uint8_t* __restrict__ mark, int* __restrict__ fdeg) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int r = uf_find(comp, v);
   if (ld_relaxed(comp + v) != r) st_relaxed(comp + v, r);
@@ -553,7 +570,7 @@ __global__ void __launch_bounds__(MODE_SAMPLES) k_pick_mode(int* p, int n, int* 
 }
 
 __global__ void k_compress(int* p, int n) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   int r = uf_find(p, v);
   if (ld_relaxed(p + v) != r) st_relaxed(p + v, r);
@@ -565,7 +582,7 @@ __global__ void k_compress(int* p, int n) {
 // passes that read p[v] as the set's id (Rooting's component ids, the
 // read-out's labels, the relabelling) need every entry on its root.
 __global__ void k_flatten(int* p, int n) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int r = uf_root_ro(p, v);
   if (ld_relaxed(p + v) != r) st_relaxed(p + v, r);
@@ -661,7 +678,7 @@ __device__ __forceinline__ void cc_link(int* cc, int u, int v, int* hu, int* hv)
 template <bool PRIO>
 __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
                             int* hu, int* hv) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
   if (e > b) {
@@ -684,7 +701,7 @@ __device__ __forceinline__ bool ranks_above(int w, int v) {
 template <bool PRIO>
 __global__ void k_cc_first_round(const int* __restrict__ off, const int* __restrict__ adj, int n, int* cc,
                                  int* __restrict__ hu, int* __restrict__ hv) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
   int w = v;
@@ -1305,7 +1322,7 @@ enum QueryMode : int { QUERY_EXACT = 0, QUERY_CERTIFY = 1, QUERY_RECHECK = 2 };
 __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const int2* __restrict__ pre,
                             const int2* __restrict__ suf, const int2* __restrict__ tab, int4* rec, int mode,
                             bool by_slot, int* __restrict__ cover, int* status) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = vertex_index();
   if (t >= n) return;
   // the recheck by slot visits only covered slots (cover holds the scanned counts then)
   if (mode == QUERY_RECHECK && cover && cover[t + 1] <= 0) return;
@@ -1371,7 +1388,7 @@ __global__ void k_rmq_query(int n, int64_t nb, const int4* __restrict__ W, const
 __global__ void k_tag_sample(const int* __restrict__ off, const int* __restrict__ adj, const int* __restrict__ lone,
                              int* __restrict__ first, int4* __restrict__ rec, int n, int ks, int4* __restrict__ W,
                              int* __restrict__ cover, int* scal, int* status) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int x = vertex_index();
   if (x < 2) cover[n + x] = 0;  // the certification's difference array (n + 2 slots) starts at zero
   if (x == 0) scal[S_DIRTY] = 0;
   if (x >= n) return;
@@ -1503,7 +1520,7 @@ __device__ __forceinline__ void lcc_link(int* lab, int u, int v) {
 // initialises every set.  Then the other plain tree edges by union-find.
 template <bool PRIO>
 __global__ void k_lcc_tree_free(const int4* __restrict__ rec, int n, int* __restrict__ lab) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int4 r = rec[v];
   lab[v] = (r.z >= 0 && r.w == 0 && ranks_above<PRIO>(r.z, v)) ? r.z : v;
@@ -1511,7 +1528,7 @@ __global__ void k_lcc_tree_free(const int4* __restrict__ rec, int n, int* __rest
 
 template <bool PRIO>
 __global__ void k_lcc_tree(const int4* __restrict__ rec, int n, int* lab) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   int4 r = rec[v];
   if (r.z >= 0 && r.w == 0 && !ranks_above<PRIO>(r.z, v)) lcc_link<PRIO>(lab, v, r.z);
@@ -1530,7 +1547,7 @@ __device__ __forceinline__ bool cross_edge(int x, int4 rx, int y, int4 ry) {
 template <bool PRIO>
 __global__ void k_lcc_sample(const int* __restrict__ off, const int* __restrict__ adj, const int4* __restrict__ rec,
                              int n, int r, int* lab) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
   if (e > b) {
@@ -1849,7 +1866,7 @@ __global__ void k_bcc_label(const int* __restrict__ off, const int* __restrict__
 __global__ void k_vertex_lh(const int* __restrict__ lab, const int* __restrict__ head,
                             const uint8_t* __restrict__ heads, const int4* __restrict__ rec,
                             const int* __restrict__ scal, int n, int4* __restrict__ vlh) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   const int l = lab[v], h = head[l], m = bcc_min_vertex(l, h);
   const bool exact = heads[v] && (rec[v].z < 0 || v == head[scal[S_LBIG]] || m == v);
@@ -1882,7 +1899,7 @@ __device__ __forceinline__ int row_lower(const int* __restrict__ off, const int*
 __global__ void k_mirror_find(const int* __restrict__ off, const int* __restrict__ adj, int n,
                               const int4* __restrict__ vlh, const int* __restrict__ scal, int* __restrict__ minid,
                               int* __restrict__ mpos, int* __restrict__ mcnt) {
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = vertex_index();
   if (y >= n) return;
   const int4 r = vlh[y];  // (l, head(l), smallest vertex of the BCC, exact-row flag)
   int a = -1, k = 0;
@@ -1906,7 +1923,7 @@ __global__ void k_canon_first(const int* __restrict__ off, const int* __restrict
                               const unsigned long long* __restrict__ bits, const int* __restrict__ scal,
                               const int* __restrict__ minid, const int* __restrict__ vbegin, int G,
                               int* __restrict__ canon) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = vertex_index();
   const int big = scal[S_LBIG];
   bool label = v < n && is_bcc_label(rec, lab, v);
   int c = -1;
@@ -2386,6 +2403,15 @@ __global__ void k_narrow_offsets(const int64_t* __restrict__ in, int64_t count, 
 // ------------------------------------------------------------ host driver
 inline unsigned grid_for(int64_t count, int block = BLOCK) { return (unsigned)cdiv(count, block); }
 
+// Grid of a per-vertex launch: plain, or XCD-ordered (8, per) when asked and
+// the second dimension allows it.
+inline dim3 vertex_grid(int64_t count, int block, bool xcd) {
+  const int64_t blocks = cdiv(count, block);
+  const int64_t per = cdiv(blocks, NUM_XCD);
+  if (xcd && per > 0 && per <= 65535) return dim3(NUM_XCD, (unsigned)per);
+  return dim3((unsigned)blocks);
+}
+
 struct Ctx {
   hipStream_t st;
   fastbcc_trace* trace = nullptr;
@@ -2413,9 +2439,11 @@ struct Ctx {
   }
 };
 
+inline bool grid_nonempty(unsigned g) { return g > 0; }
+inline bool grid_nonempty(dim3 g) { return g.x > 0 && g.y > 0 && g.z > 0; }
 #define LAUNCH(ctx, kern, grid, block, ...)                                              \
   do {                                                                                   \
-    if ((grid) > 0) {                                                                    \
+    if (grid_nonempty(grid)) {                                                           \
       (ctx).before();                                                                    \
       hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (ctx).st, __VA_ARGS__);      \
       (ctx).check();                                                                     \
@@ -2463,7 +2491,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
       fill_i32(c, (int*)gmark, 0, cdiv(n, 4));  // n bytes, the allocation is padded to 256
       LAUNCH(c, k_mark_graph_modes, (unsigned)G, GRAPH_MODE_SAMPLES, comp, vbegin, n, gmark);
     }
-    LAUNCH(c, k_frontier_deg, grid_for(n), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark, foff);
+    LAUNCH(c, k_frontier_deg, vertex_grid(n, BLOCK, tune.xcd), BLOCK, off, comp, scal, slot, n, (const uint8_t*)gmark,
+           foff);
     // one scan of the degrees for both the ranks and the starts (the scratch
     // holds 2 * tiles sums: cdiv(2n + 1, SCAN_TILE) + 1 >= 2 * cdiv(n, SCAN_TILE))
     const int tiles = (int)cdiv(n, SCAN_TILE);
@@ -2489,7 +2518,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   const unsigned gn = grid_for(n);
   // the per-vertex kernels of the hot phases take the tuned block size
   const int VB = tune.vertex_block;
-  const unsigned gv = grid_for(n, VB);
+  const dim3 gv = vertex_grid(n, VB, tune.xcd);
+  const dim3 gx = vertex_grid(n, BLOCK, tune.xcd);  // compression and frontier passes
   int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
 
   // ---- First-CC (spanning forest)
@@ -2520,7 +2550,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     // flattened for the next round, except after the atomic-free round (its
     // chains are short and the next round's finds walk them anyway) and
     // after the last one (the frontier pass flattens)
-    if (!free_round && r + 1 < tune.sample_rounds) LAUNCH(c, k_compress, gn, BLOCK, cc, n);
+    if ((!free_round || tune.compress_free) && r + 1 < tune.sample_rounds) LAUNCH(c, k_compress, gx, BLOCK, cc, n);
   }
   LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
   frontier(cc, S_BIG_CC);
@@ -2534,7 +2564,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *hubidx = I(L.hubidx), *shard = I(L.shard);
   fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
   LAUNCH(c, k_edge_flags, gn, BLOCK, off, hu, n, cc, eid, headp, hubidx, scal);
-  LAUNCH(c, k_flatten, gn, BLOCK, cc, n);  // Rooting reads cc[v] as the component id
+  LAUNCH(c, k_flatten, gx, BLOCK, cc, n);  // Rooting reads cc[v] as the component id
   scan_inplace(c, eid, n, nullptr, tmp, eid + n);
   LAUNCH(c, k_edge_compact, gn, BLOCK, hu, hv, eid, n, eu, ev);
   const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
@@ -2641,7 +2671,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   // flattened before each sampling round; the frontier pass flattens the last state
   const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
   for (int r = 0; r < lcc_rounds; ++r) {
-    LAUNCH(c, k_compress, gn, BLOCK, lab, n);
+    LAUNCH(c, k_compress, gx, BLOCK, lab, n);
     if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gv, VB, off, adj, rec, n, r, lab);
     else LAUNCH(c, k_lcc_sample<false>, gv, VB, off, adj, rec, n, r, lab);
   }
@@ -2649,8 +2679,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   frontier(lab, S_BIG_LAB);
   if (tune.lcc_prio) LAUNCH(c, k_lcc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
   else LAUNCH(c, k_lcc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
-  LAUNCH(c, k_compress, gn, BLOCK, lab, n);
-  LAUNCH(c, k_flatten, gn, BLOCK, lab, n);  // the relabelling and the read-out read lab[v] as the label
+  LAUNCH(c, k_compress, gx, BLOCK, lab, n);
+  LAUNCH(c, k_flatten, gx, BLOCK, lab, n);  // the relabelling and the read-out read lab[v] as the label
   if (tune.lcc_prio) {
     int* minv = I(L.minid);  // refilled by the read-out
     fill_i32(c, minv, INT32_MAX, n);

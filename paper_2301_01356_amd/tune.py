@@ -1,6 +1,6 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes ten speed-only knobs in its flags word (they never change
+The C ABI exposes twelve speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
 sampling off), the First-CC union-find variant (hook by id or by hashed
@@ -8,8 +8,9 @@ priority), an optional low-diameter decomposition in front of First-CC's
 union-find (the paper's LDD-UF-JTB shape) with its beta, exact or
 sampled-and-certified tags (and how many samples), an atomic-free first
 sampling round, Last-CC's hooking rule and sampling rounds, the arc-tile
-size (64-arc windows per wave, i.e. work per wave) and the block size of the
-hot per-vertex kernels.  The tuner times candidates by
+size (64-arc windows per wave, i.e. work per wave), the block size of the
+hot per-vertex kernels, whether First-CC's sets are flattened after the
+atomic-free round, and whether per-vertex launches are ordered by XCD.  The tuner times candidates by
 coordinate descent on the real input, from the fastest of a few seed
 configurations, settles near-ties by a run-off, and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
@@ -41,8 +42,10 @@ FREE = (0, 1)  # First-CC's first sampling round without atomics
 LCC = (0, 1)  # Last-CC hooking: 0 = by id, 1 = by hashed priority + relabelling
 LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)
 VBLOCK = (256, 64, 128, 512)  # threads per block of the hot per-vertex kernels
+CFREE = (0, 1)  # flatten First-CC's sets after the atomic-free round
+XCD = (0, 1)  # per-vertex launches ordered by XCD
 START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1,
-         "vb": 256}
+         "vb": 256, "cf": 0, "xcd": 0}
 # Starting points: the built-in defaults, the usual winner on power-law graphs
 # and the usual winner on lattices and k-NN graphs.  The descent starts from
 # the fastest of them, so noise between near-equal candidates cannot strand
@@ -50,9 +53,9 @@ START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts":
 SEEDS = (
     START,
     {"ruler": 4, "sample": 2, "tile": 4, "uf": 0, "ldd": 0, "tags": 1, "ts": 2, "free": 1, "lcc": 0, "lr": 0,
-     "vb": 256},
+     "vb": 256, "cf": 0, "xcd": 0},
     {"ruler": 4, "sample": 1, "tile": 3, "uf": 1, "ldd": 0, "tags": 0, "ts": 4, "free": 1, "lcc": 1, "lr": 0,
-     "vb": 256},
+     "vb": 256, "cf": 0, "xcd": 0},
 )
 
 
@@ -84,7 +87,8 @@ def decode(flags: int) -> Dict:
             "ldd": (flags >> N.TUNE_LDD_SHIFT) & 0x3, "tags": int(bool(flags & N.TUNE_SAMPLED_TAGS)),
             "ts": codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3],
             "free": int(bool(flags & N.TUNE_FREE_FIRST_ROUND)), "lcc": int(bool(flags & N.TUNE_LCC_PRIORITY)),
-            "lr": lr - 1, "vb": {c: b for b, c in N.VERTEX_BLOCK_CODES.items()}[(flags >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3]}
+            "lr": lr - 1, "vb": {c: b for b, c in N.VERTEX_BLOCK_CODES.items()}[(flags >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3],
+            "cf": int(bool(flags & N.TUNE_COMPRESS_FREE_ROUND)), "xcd": int(bool(flags & N.TUNE_XCD_ORDER))}
 
 
 def encode(cfg: Dict) -> int:
@@ -93,7 +97,8 @@ def encode(cfg: Dict) -> int:
                         sampled_tags=bool(cfg.get("tags", 0)), tag_samples=int(cfg.get("ts", 4)),
                         free_first_round=bool(cfg.get("free", 0)), lcc_priority=bool(cfg.get("lcc", 0)),
                         lcc_rounds=None if cfg.get("lr", -1) < 0 else int(cfg["lr"]),
-                        vertex_block=int(cfg.get("vb", 256)))
+                        vertex_block=int(cfg.get("vb", 256)), compress_free_round=bool(cfg.get("cf", 0)),
+                        xcd_order=bool(cfg.get("xcd", 0)))
 
 
 class Tuner:
@@ -146,7 +151,7 @@ class Tuner:
             changed = False
             for knob, values in (("tags", TAGS), ("uf", UF), ("free", FREE), ("lcc", LCC), ("ldd", LDD), ("sample", SAMPLE),
                                  ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES), ("lr", LCC_ROUNDS),
-                                 ("vb", VBLOCK)):
+                                 ("vb", VBLOCK), ("cf", CFREE), ("xcd", XCD)):
                 if knob == "ts" and not cfg["tags"]:
                     continue
                 best_v, best_t = cfg[knob], cost(cfg)

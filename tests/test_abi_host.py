@@ -69,7 +69,7 @@ def test_solve_argument_errors_are_synchronous():
     assert _solve(100, 400, 256 + 4, need) == N.ERR_INVALID_ARGUMENT  # misaligned workspace
     assert _solve(-5, 400, 256, need) == N.ERR_INVALID_ARGUMENT
     assert _solve(1 << 30, 400, 256, 1 << 40) == N.ERR_TOO_LARGE
-    assert _solve(100, 400, 256, need, flags=1 << 30) == N.ERR_INVALID_ARGUMENT  # unknown flag bit
+    assert _solve(100, 400, 256, need, flags=1 << 31) == N.ERR_INVALID_ARGUMENT  # unknown flag bit
     assert _solve(100, 400, 256, need, flags=2 << N.TUNE_RULER_SHIFT) == N.ERR_INVALID_ARGUMENT
     assert _solve(100, 400, 256, need, flags=1 << N.TUNE_TILE_SHIFT) == N.ERR_INVALID_ARGUMENT
     assert _solve(100, 400, 256, need, off=0) == N.ERR_INVALID_ARGUMENT
@@ -100,7 +100,8 @@ def test_tune_flag_encoding():
     assert (N.tune_flags(vertex_block=512) >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3 == 3
     assert N.tune_flags(vertex_block=256) == 0
     # bits above the last tuning field are refused
-    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 29) == N.ERR_INVALID_ARGUMENT
+    assert N.tune_flags(compress_free_round=True) == N.TUNE_COMPRESS_FREE_ROUND
+    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 31) == N.ERR_INVALID_ARGUMENT
 
 
 def test_host_tensors_are_refused_not_solved_on_the_cpu():

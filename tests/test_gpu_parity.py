@@ -250,6 +250,10 @@ def test_multigraph_self_loops_unsorted_rows():
     N.tune_flags(lcc_rounds=0), N.tune_flags(lcc_rounds=1, lcc_priority=True, sampled_tags=True),
     N.tune_flags(vertex_block=64), N.tune_flags(vertex_block=128, cc_priority=True, free_first_round=True),
     N.tune_flags(vertex_block=512, sampled_tags=True, tag_samples=1, lcc_priority=True),
+    N.tune_flags(free_first_round=True, compress_free_round=True, cc_priority=True),
+    N.tune_flags(free_first_round=True, compress_free_round=True, sample_rounds=1),
+    N.tune_flags(xcd_order=True), N.tune_flags(xcd_order=True, vertex_block=64, sampled_tags=True, cc_priority=True),
+    N.tune_flags(xcd_order=True, lcc_priority=True, free_first_round=True, lcc_rounds=1, vertex_block=512),
 ])
 @pytest.mark.parametrize("cfg", ["rmat_small", "grid_small"])
 def test_tuning_fields_never_change_results(flags, cfg):
@@ -268,7 +272,8 @@ def test_repeated_solves_identical():
 
 
 BATCH_FLAGS = [0, N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True,
-                                                                          ruler_shift=3)]
+                                                                          ruler_shift=3),
+               N.tune_flags(xcd_order=True, cc_priority=True, lcc_priority=True, free_first_round=True)]
 
 
 @pytest.mark.parametrize("flags", BATCH_FLAGS)
