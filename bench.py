@@ -444,10 +444,10 @@ def bench_knn_sweep(args):
     }
 
 
-# Serving arrival rate, frozen: 0.7 x the capacity measured once on MI355X
-# (all requests queued at t = 0, same pool, slots and flags; bench.py
-# --workload serve --measure-capacity).  None: measure it in the run.
-SERVE_QPS = None
+# Serving arrival rate, frozen: 0.7 x the served capacity measured once on
+# MI355X (952 graphs/s: 1,500 requests of this pool queued at t = 0, 3 slots,
+# the serving flags; the capacity runs of `bench.py --workload serve`).
+SERVE_QPS = 665.0
 
 
 # Table 1 of the paper for its circular grids with p = 0.6 (context: the

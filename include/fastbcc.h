@@ -227,6 +227,21 @@ FASTBCC_API fastbcc_status fastbcc_vertex_labels(int64_t n, int64_t num_arcs, in
                                                  int32_t* out_home_head, void* stream);
 
 /*
+ * Batch assembly: graphs copied into one CSR with their own (graph-local)
+ * ids and row starts get them made global in place.  Graph g owns vertices
+ * [graph_vbegin[g], graph_vbegin[g+1]) and arcs [graph_abegin[g],
+ * graph_abegin[g+1]); every arc of g gets graph_vbegin[g] added to its
+ * target, every row start of g gets graph_abegin[g] added (offsets[n] is not
+ * touched).  Both range arrays: int32[num_graphs + 1] on the device, from 0
+ * to n and to num_arcs, nondecreasing.  Enqueue-only on `stream`.  (The
+ * batched solve itself takes global ids; this is how a batch is built from
+ * requests that arrive with local ones.)
+ */
+FASTBCC_API fastbcc_status fastbcc_batch_rebase(int32_t num_graphs, const int32_t* graph_vbegin,
+                                                const int32_t* graph_abegin, int64_t n, int64_t num_arcs,
+                                                int32_t* offsets, int32_t* adj, void* stream);
+
+/*
  * Per-graph input check of a batch, for graphs from untrusted sources
  * (serving): enqueue-only on `stream`, no host synchronisation, nothing
  * allocated.  The layout is that of fastbcc_solve_batched (global ids;

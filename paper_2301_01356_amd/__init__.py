@@ -6,6 +6,7 @@ The compute path is ``libfastbcc.so`` (hand-written HIP for gfx950, C ABI in
 from .api import (  # noqa: F401
     BccResult,
     alloc_workspace,
+    batch_rebase,
     bc_labeling,
     check_batched,
     read_device_status,
@@ -17,5 +18,5 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 
-__all__ = ["BccResult", "alloc_workspace", "bc_labeling", "check_batched", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
+__all__ = ["BccResult", "alloc_workspace", "batch_rebase", "bc_labeling", "check_batched", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
            "workspace_size"]

@@ -62,6 +62,7 @@ EXPORTED = (
     "fastbcc_solve_noalloc",
     "fastbcc_bc_labeling",
     "fastbcc_check_batched",
+    "fastbcc_batch_rebase",
 )
 
 
@@ -123,6 +124,8 @@ def lib():
     h.fastbcc_solve_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, u32, vp]
     h.fastbcc_bc_labeling.restype = st
     h.fastbcc_bc_labeling.argtypes = [i64, i64, i32, vp, vp, i32, vp, vp, vp, vp, sz, u32, vp, vp, vp, vp, vp]
+    h.fastbcc_batch_rebase.restype = st
+    h.fastbcc_batch_rebase.argtypes = [i32, vp, vp, i64, i64, vp, vp, vp]
     h.fastbcc_check_batched.restype = st
     h.fastbcc_check_batched.argtypes = [i32, vp, i64, i64, vp, vp, u32, vp, vp]
     h.fastbcc_vertex_labels.restype = st

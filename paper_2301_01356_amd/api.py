@@ -296,6 +296,25 @@ def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Option
     return home, head
 
 
+def batch_rebase(offsets: torch.Tensor, adj: torch.Tensor, vbegin: torch.Tensor, abegin: torch.Tensor,
+                 stream=None) -> None:
+    """Make the graph-local ids and row starts of a freshly copied batch
+    global, in place (graph g: vertices vbegin[g].., arcs abegin[g]..)."""
+    _check_tensor(offsets, "offsets", (torch.int32,))
+    dev = offsets.device
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+    _check_tensor(abegin, "abegin", (torch.int32,), vbegin.numel(), dev)
+    G = vbegin.numel() - 1
+    if G < 1:
+        raise ValueError("vbegin needs at least 2 entries")
+    n, A = offsets.numel() - 1, adj.numel()
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_batch_rebase(G, vbegin.data_ptr(), abegin.data_ptr(), n, A, offsets.data_ptr(),
+                                          _dev_ptr(adj) if A else None, _stream_handle(stream))
+    N.check(st, "fastbcc_batch_rebase")
+
+
 def check_batched(offsets: torch.Tensor, adj: torch.Tensor, vbegin: Optional[torch.Tensor] = None, *,
                   flags: int = 0, repair: bool = False, out: Optional[torch.Tensor] = None,
                   stream=None) -> torch.Tensor:

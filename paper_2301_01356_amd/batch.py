@@ -9,7 +9,7 @@ keeps device-resident buffers for a batch and moves only what a batch uses:
   staging memory, or, when the graph already lives in pinned memory
   (``PinnedGraph``), copied to the device straight from there;
 * device side, the graph's vertex and arc offsets are added to its ids and
-  offsets by two element-wise passes over the used prefix.
+  row starts (``fastbcc_batch_rebase``).
 
 Two modes:
 
@@ -36,7 +36,7 @@ import numpy as np
 import torch
 
 from . import _native as N
-from .api import BccResult, alloc_workspace, check_batched, solve_batched
+from .api import BccResult, alloc_workspace, batch_rebase, check_batched, solve_batched
 
 
 @dataclass
@@ -166,6 +166,8 @@ class BatchedSolver:
         # pinned staging for host<->device copies
         self.h_vbegin = torch.empty(G1 + 1, dtype=torch.int32, pin_memory=True)
         self.h_bounds = torch.empty(2 * (G1 + 1), dtype=torch.int64, pin_memory=True)
+        self.h_abegin = torch.empty(G1 + 1, dtype=torch.int32, pin_memory=True)
+        self.d_abegin = torch.empty(G1 + 1, dtype=torch.int32, device=dev)
         self._h_in = None  # pinned staging of graphs that are not pinned themselves (allocated on first use)
         self.h_label = torch.empty(self.cap_a, dtype=torch.int32, pin_memory=True)
         self.h_ap = torch.empty(self.cap_v, dtype=torch.uint8, pin_memory=True)
@@ -223,6 +225,7 @@ class BatchedSolver:
         bd = self.h_bounds.numpy()
         bd[: G + 1] = [s[2] for s in spans] + [a0]
         bd[G + 1 : 2 * G + 2] = [s[0] for s in spans] + [v0]
+        self.h_abegin.numpy()[: G + 1] = bd[: G + 1]
         self.spans, self._copies = spans, copies
         self.used_v, self.used_a = v0, a0
 
@@ -260,15 +263,14 @@ class BatchedSolver:
                     if b1 > b0:
                         self.d_adj[b0:b1].copy_(tadj, non_blocking=True)
             if G:
-                # graph-local -> global: add each graph's first vertex to its
-                # arcs' targets and its first arc to its row starts
-                bd = self.h_bounds[: 2 * G + 2].to(self.device, non_blocking=True)
-                ab, vbd = bd[: G + 1], bd[G + 1 :]
-                if a0:
-                    self.d_adj[:a0] += torch.repeat_interleave(vbd[:G], ab[1:] - ab[:G], output_size=a0).to(torch.int32)
-                if v0:
-                    self.d_off[:v0] += torch.repeat_interleave(ab[:G], vbd[1:] - vbd[:G], output_size=v0).to(torch.int32)
-                self._bounds = (ab, vbd)
+                # graph-local -> global: each graph's first vertex added to its
+                # arcs' targets, its first arc to its row starts (on the device)
+                self.d_abegin[: G + 1].copy_(self.h_abegin[: G + 1], non_blocking=True)
+                batch_rebase(self.d_off[: v0 + 1], self.d_adj[:a0], self.d_vbegin[: G + 1], self.d_abegin[: G + 1],
+                             stream=s)
+                if self.digests:
+                    bd = self.h_bounds[: 2 * G + 2].to(self.device, non_blocking=True)
+                    self._bounds = (bd[: G + 1], bd[G + 1 :])
             if self.exact:
                 self.d_off[v0 : v0 + 1].fill_(a0)
             else:

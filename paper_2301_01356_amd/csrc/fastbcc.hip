@@ -2394,6 +2394,37 @@ __global__ void k_repair_graphs(int* __restrict__ off, int* __restrict__ adj, in
   }
 }
 
+// ------------------------------------------------------------ batch assembly
+// Graph-local ids and row starts made global: graph g's arcs get vbegin[g]
+// added to their targets and its rows abegin[g] added to their starts.  A
+// thread finds its element's graph by binary search over the (short, cached)
+// range arrays.
+__global__ void k_rebase_arcs(const int* __restrict__ abegin, const int* __restrict__ vbegin, int G, int64_t A,
+                              int* __restrict__ adj) {
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = G;  // abegin[lo] <= a < abegin[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (abegin[mid] <= a) lo = mid;
+      else hi = mid;
+    }
+    adj[a] += vbegin[lo];
+  }
+}
+
+__global__ void k_rebase_rows(const int* __restrict__ abegin, const int* __restrict__ vbegin, int G, int64_t n,
+                              int* __restrict__ off) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = G;  // vbegin[lo] <= v < vbegin[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (vbegin[mid] <= v) lo = mid;
+      else hi = mid;
+    }
+    off[v] += abegin[lo];
+  }
+}
+
 // int64 offsets are narrowed once (every offset is < 2^31 because arcs are).
 __global__ void k_narrow_offsets(const int64_t* __restrict__ in, int64_t count, int* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -2983,6 +3014,26 @@ fastbcc_status fastbcc_check_batched(int32_t num_graphs, const int32_t* graph_vb
       LAUNCH(c, k_repair_graphs, blocks, BLOCK, offsets, adj, (int)n, num_arcs, graph_vbegin, (int)num_graphs,
              (const int*)out_graph_status);
     }
+  }
+  return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
+}
+
+fastbcc_status fastbcc_batch_rebase(int32_t num_graphs, const int32_t* graph_vbegin, const int32_t* graph_abegin,
+                                    int64_t n, int64_t num_arcs, int32_t* offsets, int32_t* adj, void* stream) {
+  if (num_graphs < 1 || n < 0 || num_arcs < 0 || graph_vbegin == nullptr || graph_abegin == nullptr)
+    return FASTBCC_ERR_INVALID_ARGUMENT;
+  if ((n > 0 && offsets == nullptr) || (num_arcs > 0 && adj == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
+  if (n >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  Ctx c{(hipStream_t)stream};
+  if (num_arcs > 0) {
+    unsigned g = grid_for(num_arcs);
+    if (g > 65536) g = 65536;
+    LAUNCH(c, k_rebase_arcs, g, BLOCK, graph_abegin, graph_vbegin, (int)num_graphs, num_arcs, adj);
+  }
+  if (n > 0) {
+    unsigned g = grid_for(n);
+    if (g > 65536) g = 65536;
+    LAUNCH(c, k_rebase_rows, g, BLOCK, graph_abegin, graph_vbegin, (int)num_graphs, n, offsets);
   }
   return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
 }

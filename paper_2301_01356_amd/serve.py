@@ -226,8 +226,10 @@ class Server:
                             self.stats["rejected"] += 1
                             continue
                         kept = self.keep is None or self.keep(r)
-                        done[r.rid] = Completion(r.rid, True, "", gr.edge_label if kept else None,
-                                                 gr.is_ap if kept else None, gr.num_bcc, r.arrival, fl.admitted,
+                        lab = ap = None
+                        if kept and gr.edge_label is not None:  # slots may hand out views of reused buffers
+                            lab, ap = np.array(gr.edge_label, copy=True), np.array(gr.is_ap, copy=True)
+                        done[r.rid] = Completion(r.rid, True, "", lab, ap, gr.num_bcc, r.arrival, fl.admitted,
                                                  fin, getattr(gr, "digest", None))
                     used -= fl.bytes
                     del inflight[si]
@@ -326,7 +328,9 @@ class HipSlot(Slot):
         return self.solver.ready()
 
     def results(self):
-        return self.solver.results()
+        # views of the pinned result buffers (valid until this slot's next
+        # launch): the server copies out only the results it keeps
+        return self.solver.results(copy=False)
 
 
 def hip_slots(num_slots: int, cap_v: int, cap_a: int, cap_g: int, device="cuda:0", flags: int = 0,
