@@ -256,15 +256,25 @@ def tuned_flags(tuner_key, run_once):
     return t.tune(tuner_key, run_once), t.cache[tuner_key]
 
 
+# Graphs of at most this many vertices go to the fused small-graph kernels
+# (packed into runs of at most SMALL_PACK vertices) in the batch leg.
+SMALL_SPLIT = 3072
+SMALL_PACK = 3072
+
+
 def bench_batch(args):
     """Batched pattern: 4096 graphs (mixed families, n log-uniform in
-    [64, 2^16]) solved by ONE captured launch sequence, against the plain
-    per-graph solve of the same graphs, each launched separately."""
+    [64, 2^16]) against the plain per-graph solve of the same graphs, each
+    launched separately.  The batched path splits the batch: graphs of at
+    most SMALL_SPLIT vertices go, packed, to the fused one-workgroup-per-pack
+    kernels, the rest to the general launch sequence; each part is one
+    captured HIP graph on its own stream, so the two overlap.  The general
+    sequence over the whole batch is timed beside it."""
     import numpy as np
     import torch
 
     from paper_2301_01356_amd import gen, solve
-    from paper_2301_01356_amd.batch import BatchedSolver
+    from paper_2301_01356_amd.batch import BatchedSolver, SplitBatchedSolver
     from paper_2301_01356_amd.tune import cache_key, gpu_arch, skew_class
 
     t0 = time.perf_counter()
@@ -309,8 +319,45 @@ def bench_batch(args):
             solver.graph.replay()
         e1.record(s)
     e1.synchronize()
-    ms_batch = e0.elapsed_time(e1) / args.steps
-    log(f"[bench] batched (graph replay): {ms_batch:.3f} ms per batch of {G}")
+    ms_general = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] batched, general sequence only (graph replay): {ms_general:.3f} ms per batch of {G}")
+    # the split path: fused kernels for the small graphs beside the general
+    # sequence for the rest, two streams
+    small_caps, big_caps = SplitBatchedSolver.capacities(graphs, SMALL_SPLIT)
+    split = SplitBatchedSolver(small_caps, big_caps, small_max=SMALL_SPLIT, pack_vertices=SMALL_PACK,
+                               device=dev, flags=flags | INPUT_FLAGS)
+    split.stage(graphs)
+    split.launch()
+    split.synchronize()
+    n_small = sum(1 for g in graphs if g.n <= SMALL_SPLIT)
+
+    def time_parts(parts, steps):
+        cur = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ends = [torch.cuda.Event() for _ in parts]
+        e0.record(cur)
+        for p in parts:
+            p.stream.wait_event(e0)
+        for _ in range(steps):
+            for p in parts:
+                with torch.cuda.stream(p.stream):
+                    p.graph.replay()
+        for p, e in zip(parts, ends):
+            e.record(p.stream)
+            cur.wait_event(e)
+        e1.record(cur)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    split.replay()  # captures both graphs on first use
+    split.synchronize()
+    time_parts([split.small, split.big], max(1, args.warmup))
+    ms_batch = time_parts([split.small, split.big], args.steps)
+    ms_small = time_parts([split.small], args.steps)
+    ms_big = time_parts([split.big], args.steps)
+    log(f"[bench] batched, split (graph replays on two streams): {ms_batch:.3f} ms per batch of {G} "
+        f"({n_small} graphs of <= {SMALL_SPLIT} vertices on the fused kernels: {ms_small:.3f} ms alone; "
+        f"the other {G - n_small} on the general sequence: {ms_big:.3f} ms alone)")
     from paper_2301_01356_amd import _native as N
     from paper_2301_01356_amd import solve_traced
 
@@ -357,11 +404,16 @@ def bench_batch(args):
         per.append(e0.elapsed_time(e1))
     ms_per_graph_total = float(np.median(per))
     log(f"[bench] per-graph plain solves: {ms_per_graph_total:.1f} ms for {G} graphs")
-    # results agree (batched == per-graph) on every graph
-    solver.launch()
-    br = solver.results()
+    # results agree (batched == per-graph) on every graph, for the split
+    # path and the general sequence alone
+    split.launch()
+    br = split.results()
     same = all(np.array_equal(b.edge_label, out.edge_label.cpu().numpy()) and b.num_bcc == int(out.num_bcc.item())
                for b, out in zip(br, outs))
+    solver.launch()
+    br = solver.results()
+    same = same and all(np.array_equal(b.edge_label, out.edge_label.cpu().numpy())
+                        and b.num_bcc == int(out.num_bcc.item()) for b, out in zip(br, outs))
     return {
         "metric": "batched vs per-graph speedup (1 GPU)",
         "value": ms_per_graph_total / ms_batch,
@@ -378,6 +430,10 @@ def bench_batch(args):
         "config": {"workload": "batch4096_mixed_64..65536", "graphs": G, "vertices": u.n, "arcs": u.num_arcs,
                    "graphs_per_s": G / (ms_batch * 1e-3), "edges_per_s": u.num_arcs / (ms_batch * 1e-3),
                    "per_graph_total_ms": ms_per_graph_total, "hip_graph": True, "tuned": cfg,
+                   "general_sequence_only_ms": ms_general,
+                   "split": {"small_max_vertices": SMALL_SPLIT, "pack_vertices": SMALL_PACK,
+                             "small_graphs": n_small, "small_part_alone_ms": ms_small,
+                             "big_part_alone_ms": ms_big},
                    "batched_equals_per_graph": bool(same)},
         "roofline": None,
         "cpu_baseline": None,

@@ -209,6 +209,39 @@ FASTBCC_API fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32
                                      void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
 
 /*
+ * Batched solve of SMALL graphs by persistent fused kernels (paper:
+ * Algorithm 1 -- First-CC, Rooting, Tagging, Last-CC and the head
+ * assignment -- with the connected components of a disconnected input
+ * solved in parallel): one workgroup solves a whole pack of consecutive
+ * graphs as one disjoint union, every per-vertex array of every phase in
+ * its LDS, and loops over the packs; one launch per size class (packs of up
+ * to 256, 1024 and FASTBCC_SMALL_MAX_VERTICES vertices).  Same graph layout,
+ * results (graph-local labels, AP flags, per-graph counts) and asynchrony as
+ * fastbcc_solve_batched, but no workspace: nothing but the outputs is
+ * written, and the call may be captured into a HIP graph.
+ *   - pack_begin: int32[num_packs + 1] on the device, pack p = graphs
+ *     [pack_begin[p], pack_begin[p + 1]), from 0 to num_graphs,
+ *     nondecreasing; null = one graph per pack (num_packs ignored).  Packing
+ *     many tiny graphs together pays the pipeline's fixed per-pack cost once.
+ *   - A pack with more than FASTBCC_SMALL_MAX_VERTICES vertices or graphs (or
+ *     whose vertex or arc range does not fit the arrays) is not solved: its
+ *     graphs' out_num_bcc is -1 and their labels and AP flags are not
+ *     written.
+ *   - Arcs whose target lies outside their graph are ignored (label -1), as
+ *     are self-loops (label -1).
+ *   - flags: FASTBCC_FLAG_SORTED_ROWS and FASTBCC_FLAG_NO_SELF_LOOPS are
+ *     accepted and not needed; any other bit is FASTBCC_ERR_INVALID_ARGUMENT.
+ *   - out_is_ap may be null; out_edge_label may be null only when
+ *     num_arcs == 0.
+ */
+#define FASTBCC_SMALL_MAX_VERTICES 3072
+FASTBCC_API fastbcc_status fastbcc_solve_small(int32_t num_graphs, const int32_t* graph_vbegin, int32_t num_packs,
+                                               const int32_t* pack_begin, int64_t n_total, int64_t num_arcs,
+                                               const int32_t* offsets, const int32_t* adj, int32_t* out_edge_label,
+                                               uint8_t* out_is_ap, int64_t* out_num_bcc, uint32_t flags,
+                                               void* stream);
+
+/*
  * BC-labeling read-out (paper: Section "Space-Efficient BCC Representation"
  * and the component heads of Algorithm 1).  Call after a solve on the same
  * workspace with the same n, num_arcs and graphs (enqueue on the solve's

@@ -13,10 +13,11 @@ from .api import (  # noqa: F401
     solve,
     solve_batched,
     solve_noalloc,
+    solve_small,
     solve_traced,
     vertex_labels,
     workspace_size,
 )
 
-__all__ = ["BccResult", "alloc_workspace", "batch_rebase", "bc_labeling", "check_batched", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_traced", "vertex_labels",
+__all__ = ["BccResult", "alloc_workspace", "batch_rebase", "bc_labeling", "check_batched", "read_device_status", "solve", "solve_batched", "solve_noalloc", "solve_small", "solve_traced", "vertex_labels",
            "workspace_size"]

@@ -21,6 +21,7 @@ ERR_HIP = 4
 ERR_INVALID_GRAPH = 5
 ERR_SCRATCH_TOO_SMALL = 6
 NOALLOC_SCRATCH_BYTES = 64 << 20  # FASTBCC_NOALLOC_SCRATCH_BYTES
+SMALL_MAX_VERTICES = 3072  # FASTBCC_SMALL_MAX_VERTICES
 
 FLAG_VALIDATE = 0x1
 FLAG_SORTED_ROWS = 0x2
@@ -63,6 +64,7 @@ EXPORTED = (
     "fastbcc_bc_labeling",
     "fastbcc_check_batched",
     "fastbcc_batch_rebase",
+    "fastbcc_solve_small",
 )
 
 
@@ -128,6 +130,8 @@ def lib():
     h.fastbcc_batch_rebase.argtypes = [i32, vp, vp, i64, i64, vp, vp, vp]
     h.fastbcc_check_batched.restype = st
     h.fastbcc_check_batched.argtypes = [i32, vp, i64, i64, vp, vp, u32, vp, vp]
+    h.fastbcc_solve_small.restype = st
+    h.fastbcc_solve_small.argtypes = [i32, vp, i32, vp, i64, i64, vp, vp, vp, vp, vp, u32, vp]
     h.fastbcc_vertex_labels.restype = st
     h.fastbcc_vertex_labels.argtypes = [i64, i64, i32, vp, vp, sz, vp, vp, vp]
     _lib = h

@@ -213,6 +213,65 @@ def solve_batched(
     return out
 
 
+def solve_small(
+    vbegin: torch.Tensor,
+    offsets: torch.Tensor,
+    adj: torch.Tensor,
+    *,
+    packs: Optional[torch.Tensor] = None,
+    out: Optional[BccResult] = None,
+    flags: int = 0,
+    stream=None,
+) -> BccResult:
+    """As ``solve_batched`` for small graphs, by the fused kernels (one
+    workgroup per pack of consecutive graphs, all state in LDS, no
+    workspace).  ``packs``: int32 pack starts (graph indices, from 0 to G),
+    or None for one graph per pack.  A pack above ``SMALL_MAX_VERTICES``
+    vertices or graphs gets num_bcc = -1 for its graphs and no labels."""
+    _check_tensor(offsets, "offsets", (torch.int32,))
+    dev = offsets.device
+    _check_tensor(vbegin, "vbegin", (torch.int32,), device=dev)
+    _check_tensor(adj, "adj", (torch.int32,), device=dev)
+    G = vbegin.numel() - 1
+    if G < 1:
+        raise ValueError("vbegin needs at least 2 entries")
+    P = 0
+    if packs is not None:
+        _check_tensor(packs, "packs", (torch.int32,), device=dev)
+        P = packs.numel() - 1
+        if P < 1:
+            raise ValueError("packs needs at least 2 entries")
+    n = offsets.numel() - 1
+    if n < 0:
+        raise ValueError("offsets needs n + 1 >= 1 entries")
+    A = adj.numel()
+    if out is None:
+        out = BccResult(
+            torch.empty(A, dtype=torch.int32, device=dev),
+            torch.empty(n, dtype=torch.uint8, device=dev),
+            torch.empty(G, dtype=torch.int64, device=dev),
+        )
+    _check_result(out, n, A, G, dev)
+    with torch.cuda.device(dev):
+        st = N.lib().fastbcc_solve_small(
+            G,
+            vbegin.data_ptr(),
+            P,
+            packs.data_ptr() if packs is not None else None,
+            n,
+            A,
+            offsets.data_ptr(),
+            _dev_ptr(adj) if A else None,
+            _dev_ptr(out.edge_label) if A else None,
+            _dev_ptr(out.is_ap) if n else None,
+            out.num_bcc.data_ptr(),
+            flags,
+            _stream_handle(stream),
+        )
+    N.check(st, "fastbcc_solve_small")
+    return out
+
+
 def solve_traced(
     offsets: torch.Tensor,
     adj: torch.Tensor,
@@ -294,6 +353,24 @@ def vertex_labels(workspace: torch.Tensor, n: int, num_arcs: int, vbegin: Option
                                            _stream_handle(stream))
     N.check(st, "fastbcc_vertex_labels")
     return home, head
+
+
+def greedy_packs(sizes, capacity: int = N.SMALL_MAX_VERTICES) -> list:
+    """Pack starts for ``solve_small``: consecutive graphs are added to a
+    pack while its vertex count stays within ``capacity`` (a graph above it
+    forms a pack of its own) and its graph count within the fused kernels'
+    limit."""
+    starts, total, count = [0], 0, 0
+    for i, v in enumerate(sizes):
+        v = int(v)
+        if count and (total + v > capacity or count >= N.SMALL_MAX_VERTICES):
+            starts.append(i)
+            total = count = 0
+        total += v
+        count += 1
+    if count:
+        starts.append(len(sizes))
+    return starts
 
 
 def batch_rebase(offsets: torch.Tensor, adj: torch.Tensor, vbegin: torch.Tensor, abegin: torch.Tensor,

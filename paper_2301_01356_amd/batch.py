@@ -36,7 +36,7 @@ import numpy as np
 import torch
 
 from . import _native as N
-from .api import BccResult, alloc_workspace, batch_rebase, check_batched, solve_batched
+from .api import BccResult, alloc_workspace, batch_rebase, check_batched, greedy_packs, solve_batched, solve_small
 
 
 @dataclass
@@ -140,14 +140,22 @@ def device_digests(label: torch.Tensor, is_ap: torch.Tensor, abound: torch.Tenso
 
 
 class BatchedSolver:
-    """Device-resident batch buffers, exact or fixed-shape (HIP-graph replay)."""
+    """Device-resident batch buffers, exact or fixed-shape (HIP-graph replay).
+
+    ``small=True`` solves with the fused small-graph kernels
+    (``fastbcc_solve_small``) instead of the general batched path: graphs of
+    at most ``N.SMALL_MAX_VERTICES`` vertices, packed greedily into runs of
+    at most ``pack_vertices`` vertices, no workspace."""
 
     def __init__(self, max_vertices: int, max_arcs: int, max_graphs: int, device="cuda:0", flags: int = 0,
                  use_graph: bool = True, stream: Optional[torch.cuda.Stream] = None, exact: bool = False,
-                 digests: bool = False, check: bool = False):
+                 digests: bool = False, check: bool = False, small: bool = False,
+                 pack_vertices: int = N.SMALL_MAX_VERTICES):
         self.cap_v, self.cap_a, self.cap_g = int(max_vertices), int(max_arcs), int(max_graphs)
         self.device = torch.device(device)
         self.flags = flags
+        self.small = small
+        self.pack_vertices = int(pack_vertices)
         self.exact = exact
         self.use_graph = use_graph and not exact
         self.digests = digests
@@ -162,7 +170,12 @@ class BatchedSolver:
             torch.empty(self.cap_v, dtype=torch.uint8, device=dev),
             torch.empty(G1, dtype=torch.int64, device=dev),
         )
-        self.ws = alloc_workspace(self.cap_v, self.cap_a, G1, dev)
+        self.ws = None if small else alloc_workspace(self.cap_v, self.cap_a, G1, dev)
+        # pack starts (small mode): at most one pack per graph; unused packs
+        # are empty, so a captured launch always covers cap_g + 1 packs
+        self.h_packs = torch.zeros(G1 + 1, dtype=torch.int32, pin_memory=True)
+        self.d_packs = torch.zeros(G1 + 1, dtype=torch.int32, device=dev)
+        self.num_packs = 0
         # pinned staging for host<->device copies
         self.h_vbegin = torch.empty(G1 + 1, dtype=torch.int32, pin_memory=True)
         self.h_bounds = torch.empty(2 * (G1 + 1), dtype=torch.int64, pin_memory=True)
@@ -188,8 +201,8 @@ class BatchedSolver:
         self.stream.synchronize()
 
     @staticmethod
-    def bytes_needed(max_vertices: int, max_arcs: int, max_graphs: int) -> int:
-        ws = N.workspace_size(max_vertices, max_arcs, max_graphs + 1)
+    def bytes_needed(max_vertices: int, max_arcs: int, max_graphs: int, small: bool = False) -> int:
+        ws = 0 if small else N.workspace_size(max_vertices, max_arcs, max_graphs + 1)
         return ws + 2 * 4 * max_arcs + 5 * max_vertices + 8 * (max_graphs + 2) + 4 * (max_graphs + 2)
 
     # ------------------------------------------------------------ staging
@@ -210,6 +223,16 @@ class BatchedSolver:
         spare = 0 if self.exact else (2 if a0 < self.cap_a else 1)
         if v0 > self.cap_v - spare or a0 > self.cap_a:
             raise ValueError("batch exceeds the vertex/arc capacity")
+        if self.small:
+            too_big = [s1 - s0 for (s0, s1, _, _) in spans if s1 - s0 > N.SMALL_MAX_VERTICES]
+            if too_big:
+                raise ValueError(f"a graph of {too_big[0]} vertices exceeds the fused kernels' limit "
+                                 f"{N.SMALL_MAX_VERTICES}")
+            packs = greedy_packs([s1 - s0 for (s0, s1, _, _) in spans], self.pack_vertices)
+            hp = self.h_packs.numpy()
+            hp[: len(packs)] = packs
+            hp[len(packs) :] = G
+            self.num_packs = len(packs) - 1
         for g, (s0, s1, b0, b1) in zip(graphs, spans):
             if isinstance(g, PinnedGraph):
                 copies.append((s0, s1, b0, b1, g.t_off, g.t_adj))
@@ -242,6 +265,8 @@ class BatchedSolver:
         G, v0, a0 = len(self.spans), self.used_v, self.used_a
         with torch.cuda.stream(s):
             self.d_vbegin.copy_(self.h_vbegin, non_blocking=True)
+            if self.small:
+                self.d_packs.copy_(self.h_packs, non_blocking=True)
             # staged graphs sit contiguously in the staging buffers: copy each
             # run of them at once, pinned-source graphs one by one
             run = None
@@ -286,6 +311,20 @@ class BatchedSolver:
 
     # ------------------------------------------------------------ solving
     def _launch(self):
+        if self.small:
+            # promise bits only: the fused kernels take no tuning fields
+            fl = self.flags & (N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS)
+            if self.exact:
+                G, v, a = len(self.spans), self.used_v, self.used_a
+                if G == 0 or self.num_packs == 0:
+                    return
+                out = BccResult(self.out.edge_label[:a], self.out.is_ap[:v], self.out.num_bcc[:G])
+                solve_small(self.d_vbegin[: G + 1], self.d_off[: v + 1], self.d_adj[:a],
+                            packs=self.d_packs[: self.num_packs + 1], out=out, flags=fl, stream=self.stream)
+            else:
+                solve_small(self.d_vbegin, self.d_off, self.d_adj, packs=self.d_packs, out=self.out, flags=fl,
+                            stream=self.stream)
+            return
         if self.exact:
             G, v, a = len(self.spans), self.used_v, self.used_a
             if G == 0:
@@ -369,6 +408,86 @@ class BatchedSolver:
             out.append(GraphResult(gl, ga, int(nb[i]), int(dig[i]) if self.digests else None,
                                    int(self.h_status[i]) if self.check else 0))
         return out
+
+    def solve(self, graphs: Sequence) -> List[GraphResult]:
+        self.stage(graphs)
+        self.launch()
+        return self.results()
+
+
+class SplitBatchedSolver:
+    """A batch split by graph size: graphs of at most ``small_max``
+    vertices go, packed, to the fused small-graph kernels, the others to the
+    general batched path.  The two parts have their own buffers and streams,
+    so their launches (or HIP-graph replays) overlap on the device; results
+    come back in the order the graphs were staged."""
+
+    def __init__(self, small_caps, big_caps, small_max: int = N.SMALL_MAX_VERTICES,
+                 pack_vertices: int = N.SMALL_MAX_VERTICES, device="cuda:0", flags: int = 0, use_graph: bool = True):
+        if not 0 <= small_max <= N.SMALL_MAX_VERTICES:
+            raise ValueError(f"small_max must lie in [0, {N.SMALL_MAX_VERTICES}]")
+        self.small_max = int(small_max)
+        self.small = BatchedSolver(*small_caps, device=device, use_graph=use_graph, small=True,
+                                   pack_vertices=pack_vertices)
+        self.big = BatchedSolver(*big_caps, device=device, flags=flags, use_graph=use_graph)
+        self.order: List[tuple] = []
+
+    @staticmethod
+    def capacities(graphs: Sequence, small_max: int = N.SMALL_MAX_VERTICES):
+        """(vertices, arcs, graphs) capacities of the small and the big part
+        for exactly these graphs (the big part's padding needs two spare
+        vertices)."""
+        sv = sa = sg = bv = ba = bg = 0
+        for g in graphs:
+            n, A = int(g.n), int(g.offsets[-1])
+            if n <= small_max:
+                sv, sa, sg = sv + n, sa + A, sg + 1
+            else:
+                bv, ba, bg = bv + n, ba + A, bg + 1
+        return (sv + 2, max(sa, 1), max(sg, 1)), (bv + 2, max(ba, 1), max(bg, 1))
+
+    @property
+    def flags(self) -> int:
+        return self.big.flags
+
+    @flags.setter
+    def flags(self, value: int) -> None:
+        self.big.flags = value
+        self.small.flags = value
+
+    def stage(self, graphs: Sequence) -> None:
+        small, big, order = [], [], []
+        for g in graphs:
+            if int(g.n) <= self.small_max:
+                order.append((0, len(small)))
+                small.append(g)
+            else:
+                order.append((1, len(big)))
+                big.append(g)
+        self.small.stage(small)
+        self.big.stage(big)
+        self.order = order
+
+    def launch(self, keep_host: bool = True) -> None:
+        self.small.launch(keep_host)
+        self.big.launch(keep_host)
+
+    def replay(self) -> None:
+        """Replay both captured solves, each on its own stream (inputs as
+        last copied; nothing copied back)."""
+        for part in (self.small, self.big):
+            part._ensure_graph()
+        for part in (self.small, self.big):
+            with torch.cuda.stream(part.stream):
+                part.graph.replay()
+
+    def synchronize(self) -> None:
+        self.small.stream.synchronize()
+        self.big.stream.synchronize()
+
+    def results(self, copy: bool = True) -> List[GraphResult]:
+        parts = (self.small.results(copy), self.big.results(copy))
+        return [parts[p][i] for p, i in self.order]
 
     def solve(self, graphs: Sequence) -> List[GraphResult]:
         self.stage(graphs)

@@ -13,7 +13,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-HIP_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("fastbcc.hip",)]
+HIP_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("fastbcc.hip", "small.hip")]
 LIB = os.path.join(PKG, "libfastbcc.so")
 GEN_SRC = os.path.join(PKG, "gen", "graphgen.cpp")
 GEN_LIB = os.path.join(PKG, "gen", "libgraphgen.so")

@@ -80,6 +80,22 @@ def test_solve_argument_errors_are_synchronous():
     assert lib.fastbcc_read_device_status(None, None, ctypes.byref(st)) == N.ERR_INVALID_ARGUMENT
 
 
+def test_solve_small_argument_errors_are_synchronous():
+    """Refused before anything touches the GPU (pointers are never read)."""
+    f = N.lib().fastbcc_solve_small
+    # graphs, vbegin, packs, pack_begin, n, arcs, offsets, adj, label, ap, nbcc, flags, stream
+    assert f(0, 256, 0, None, 10, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_INVALID_ARGUMENT
+    assert f(1, None, 0, None, 10, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_INVALID_ARGUMENT
+    assert f(1, 256, 0, None, 10, 10, 256, 256, 256, None, None, 0, None) == N.ERR_INVALID_ARGUMENT
+    assert f(1, 256, 0, 256, 10, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_INVALID_ARGUMENT  # packs < 1
+    assert f(1, 256, 0, None, 10, 10, 256, None, 256, None, 256, 0, None) == N.ERR_INVALID_ARGUMENT  # no adj
+    assert f(1, 256, 0, None, 10, 10, 256, 256, 256, None, 256, N.FLAG_VALIDATE, None) == N.ERR_INVALID_ARGUMENT
+    assert f(1, 256, 0, None, 10, 10, 256, 256, 256, None, 256, 1 << N.TUNE_RULER_SHIFT, None) \
+        == N.ERR_INVALID_ARGUMENT  # tuning fields belong to the general path
+    assert f(1, 256, 0, None, 1 << 30, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_TOO_LARGE
+    assert f(1, 256, 0, None, -1, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_INVALID_ARGUMENT
+
+
 @pytest.mark.parametrize("code", range(7))
 def test_status_strings(code):
     s = N.lib().fastbcc_status_string(code).decode()

@@ -65,3 +65,34 @@ def test_pack_rejects_overflow():
     pack([g], 11, 18, 4)  # no leftover arcs: one spare vertex
     with pytest.raises(ValueError):
         pack([g] * 5, 1000, 1000, 4)
+
+
+def test_greedy_packs_bounds_every_pack():
+    from paper_2301_01356_amd import _native as N
+    from paper_2301_01356_amd.api import greedy_packs
+
+    rng = np.random.default_rng(5)
+    sizes = list(rng.integers(0, 900, size=500)) + [3000, 0, 0, 5] + [0] * 4000
+    for cap in (256, 1024, 3072):
+        p = greedy_packs(sizes, cap)
+        assert p[0] == 0 and p[-1] == len(sizes) and all(a < b for a, b in zip(p, p[1:]))
+        for a, b in zip(p, p[1:]):
+            tot = sum(sizes[a:b])
+            assert b - a <= N.SMALL_MAX_VERTICES
+            assert tot <= cap or b - a == 1, "only a single graph may exceed the capacity"
+            if b < len(sizes) and b - a < N.SMALL_MAX_VERTICES:
+                assert tot + sizes[b] > cap, "greedy: the next graph did not fit"
+    assert greedy_packs([], 10) == [0]
+
+
+def test_split_capacities():
+    from paper_2301_01356_amd import gen
+    from paper_2301_01356_amd.batch import SplitBatchedSolver
+
+    graphs = [gen.mixed(7, i, 16, 6000, 4.0, 8.0) for i in range(40)]
+    (sv, sa, sg), (bv, ba, bg) = SplitBatchedSolver.capacities(graphs, 3072)
+    small = [g for g in graphs if g.n <= 3072]
+    big = [g for g in graphs if g.n > 3072]
+    assert sg == max(len(small), 1) and bg == max(len(big), 1)
+    assert sv == sum(g.n for g in small) + 2 and bv == sum(g.n for g in big) + 2
+    assert sa == max(sum(g.num_arcs for g in small), 1) and ba == max(sum(g.num_arcs for g in big), 1)

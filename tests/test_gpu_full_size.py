@@ -118,7 +118,8 @@ def test_paper_tori_exact(name, tuned):
 
 def test_batch4096_full_size_exact():
     """The 4096-graph batch in the benchmarked configuration (shipped flags,
-    input promises), under the general contract and with the defaults."""
+    input promises; the general sequence alone and the split path the
+    benchmark times), under the general contract and with the defaults."""
     f = shipped_flags("batch4096")
     note("batch of 4096: generate")
     u = gen.batch()
@@ -134,6 +135,26 @@ def test_batch4096_full_size_exact():
         assert read_device_status(ws) == 0, f"a device-side invariant check fired ({what})"
         outs.append((what, r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()))
         del r
+    del ws
+    torch.cuda.empty_cache()
+    # the benchmarked split: graphs of <= 3072 vertices packed onto the fused
+    # kernels, the rest on the general sequence, each part a replayed HIP graph
+    from paper_2301_01356_amd.batch import SplitBatchedSolver
+
+    graphs = []
+    for i in range(G):
+        v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
+        a0, a1 = int(u.offsets[v0]), int(u.offsets[v1])
+        graphs.append(gen.Csr(v1 - v0, u.offsets[v0 : v1 + 1] - a0, u.adj[a0:a1] - v0))
+    note("batch of 4096: split path (fused small graphs + general sequence)")
+    small_caps, big_caps = SplitBatchedSolver.capacities(graphs, N.SMALL_MAX_VERTICES)
+    split = SplitBatchedSolver(small_caps, big_caps, device=DEV, flags=f | PROMISES)
+    split.stage(graphs)
+    split.launch()
+    split.synchronize()
+    split.replay()
+    split.synchronize()
+    sres = split.results()
     note("batch of 4096: oracle per graph")
     for i in range(G):
         v0, v1 = int(u.vbegin[i]), int(u.vbegin[i + 1])
@@ -143,6 +164,9 @@ def test_batch4096_full_size_exact():
             assert int(nb[i]) == onb, f"graph {i} ({what})"
             assert np.array_equal(ap[v0:v1], oap), f"graph {i} ({what})"
             assert np.array_equal(lab[a0:a1], olab), f"graph {i} ({what})"
+        assert sres[i].num_bcc == onb, f"graph {i} (split path)"
+        assert np.array_equal(sres[i].is_ap, oap), f"graph {i} (split path)"
+        assert np.array_equal(sres[i].edge_label, olab), f"graph {i} (split path)"
 
 
 def test_shipped_table_names_every_benchmark_workload():
