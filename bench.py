@@ -262,6 +262,53 @@ SMALL_SPLIT = 3072
 SMALL_PACK = 3072
 
 
+def bench_tiny_batch(args, dev):
+    """Many tiny graphs (16384, n log-uniform in [16, 1024], the batch's
+    families): the fused kernels over packs of up to SMALL_PACK vertices
+    against the general launch sequence over the same union, both on
+    device-resident inputs, results compared on every output."""
+    import numpy as np
+    import torch
+
+    from paper_2301_01356_amd import alloc_workspace, gen, solve_batched, solve_small
+    from paper_2301_01356_amd.api import greedy_packs
+
+    u = gen.batch(seed=9, count=16384, nmin=16, nmax=1024)
+    G = len(u.vbegin) - 1
+    vb = torch.from_numpy(u.vbegin).to(dev)
+    off = torch.from_numpy(u.offsets32()).to(dev)
+    adj = torch.from_numpy(u.adj).to(dev)
+    pk = torch.tensor(greedy_packs(np.diff(u.vbegin), SMALL_PACK), dtype=torch.int32, device=dev)
+    ws = alloc_workspace(u.n, u.num_arcs, G, dev)
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    steps = max(1, args.steps)
+    ms_general = timed(lambda: solve_batched(vb, off, adj, workspace=ws, flags=INPUT_FLAGS), steps)
+    ms_fused = timed(lambda: solve_small(vb, off, adj, packs=pk, flags=INPUT_FLAGS), steps)
+    r1 = solve_small(vb, off, adj, packs=pk, flags=INPUT_FLAGS)
+    r2 = solve_batched(vb, off, adj, workspace=ws, flags=INPUT_FLAGS)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(r1.edge_label, r2.edge_label) and torch.equal(r1.is_ap, r2.is_ap)
+                and torch.equal(r1.num_bcc, r2.num_bcc))
+    log(f"[bench] tiny graphs ({G}, {u.n} vertices, {u.num_arcs} arcs): general sequence {ms_general:.3f} ms, "
+        f"fused kernels over {pk.numel() - 1} packs {ms_fused:.3f} ms, equal={same}")
+    del ws, r1, r2
+    torch.cuda.empty_cache()
+    return {"graphs": G, "vertices": u.n, "arcs": u.num_arcs, "packs": pk.numel() - 1,
+            "general_sequence_ms": ms_general, "fused_ms": ms_fused, "speedup": ms_general / ms_fused,
+            "fused_equals_general": same}
+
+
 def bench_batch(args):
     """Batched pattern: 4096 graphs (mixed families, n log-uniform in
     [64, 2^16]) against the plain per-graph solve of the same graphs, each
@@ -404,6 +451,7 @@ def bench_batch(args):
         per.append(e0.elapsed_time(e1))
     ms_per_graph_total = float(np.median(per))
     log(f"[bench] per-graph plain solves: {ms_per_graph_total:.1f} ms for {G} graphs")
+    tiny = bench_tiny_batch(args, dev)
     # results agree (batched == per-graph) on every graph, for the split
     # path and the general sequence alone
     split.launch()
@@ -434,7 +482,8 @@ def bench_batch(args):
                    "split": {"small_max_vertices": SMALL_SPLIT, "pack_vertices": SMALL_PACK,
                              "small_graphs": n_small, "small_part_alone_ms": ms_small,
                              "big_part_alone_ms": ms_big},
-                   "batched_equals_per_graph": bool(same)},
+                   "batched_equals_per_graph": bool(same),
+                   "tiny_graphs": tiny},
         "roofline": None,
         "cpu_baseline": None,
     }
