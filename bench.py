@@ -112,18 +112,18 @@ def random_accesses(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "80f962138b6cce9f",
+    "src_sha": "46c377d1348edf74",
     "workload": "rmat25",
     "flags": 0x2B32506,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378463.5, "write_kib": 4090677.4},
-    "k_tag_sample": {"fetch_kib": 2377793.6, "write_kib": 1445420.6},
-    "k_cc_sample": {"fetch_kib": 2316651.3, "write_kib": 732185.6},
-    "k_lr_walk": {"fetch_kib": 1411174.5, "write_kib": 1063916.0},
-    "k_rmq_query": {"fetch_kib": 871275.9, "write_kib": 67796.0},
-    "k_tree_link": {"fetch_kib": 1257097.9, "write_kib": 830754.3},
-    "k_mirror_find": {"fetch_kib": 2068584.6, "write_kib": 312027.7},
-    "k_lcc_tree": {"fetch_kib": 862530.1, "write_kib": 297130.0},
+    "k_bcc_rows": {"fetch_kib": 378497.4, "write_kib": 4090686.4},
+    "k_tag_sample": {"fetch_kib": 2380423.0, "write_kib": 1445401.5},
+    "k_cc_sample": {"fetch_kib": 2314497.8, "write_kib": 733740.6},
+    "k_lr_walk": {"fetch_kib": 1411392.1, "write_kib": 1063985.7},
+    "k_rmq_query": {"fetch_kib": 871178.6, "write_kib": 67817.6},
+    "k_tree_link": {"fetch_kib": 1257078.2, "write_kib": 830754.3},
+    "k_mirror_find": {"fetch_kib": 2068313.5, "write_kib": 312027.7},
+    "k_lcc_tree": {"fetch_kib": 862850.1, "write_kib": 296773.9},
 }
 
 

@@ -456,15 +456,21 @@ class SplitBatchedSolver:
         self.small.flags = value
 
     def stage(self, graphs: Sequence) -> None:
-        small, big, order = [], [], []
-        for g in graphs:
+        """Split the graphs; the small ones are staged in decreasing size, so
+        greedy packing fills nearly every pack to the largest class (a pack
+        left small would get a launch of a smaller class to itself)."""
+        small_idx, big, order = [], [], []
+        for i, g in enumerate(graphs):
             if int(g.n) <= self.small_max:
-                order.append((0, len(small)))
-                small.append(g)
+                order.append(None)
+                small_idx.append(i)
             else:
                 order.append((1, len(big)))
                 big.append(g)
-        self.small.stage(small)
+        small_idx.sort(key=lambda i: -int(graphs[i].n))
+        for k, i in enumerate(small_idx):
+            order[i] = (0, k)
+        self.small.stage([graphs[i] for i in small_idx])
         self.big.stage(big)
         self.order = order
 
