@@ -633,6 +633,43 @@ def bench_tori(args):
     }
 
 
+def pinned_link_rates(dev, mib=64, reps=10):
+    """Pinned host <-> device copy rates of this machine (torch copies on two
+    streams): host to device alone, device to host alone, and both at once
+    (total).  Requests of a server cross this link twice."""
+    import torch
+
+    count = mib << 18
+    h1 = torch.empty(count, dtype=torch.int32, pin_memory=True)
+    h2 = torch.empty(count, dtype=torch.int32, pin_memory=True)
+    d1 = torch.empty(count, dtype=torch.int32, device=dev)
+    d2 = torch.empty(count, dtype=torch.int32, device=dev)
+    s1, s2 = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+
+    def h2d():
+        with torch.cuda.stream(s1):
+            d1.copy_(h1, non_blocking=True)
+
+    def d2h():
+        with torch.cuda.stream(s2):
+            h2.copy_(d2, non_blocking=True)
+
+    def rate(fns):
+        for f in fns:
+            f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            for f in fns:
+                f()
+        torch.cuda.synchronize()
+        return reps * len(fns) * count * 4 / (time.perf_counter() - t) / 1e9
+
+    out = {"h2d_GBps": rate([h2d]), "d2h_GBps": rate([d2h]), "both_total_GBps": rate([h2d, d2h])}
+    del h1, h2, d1, d2
+    return out
+
+
 def bench_serve(args):
     """Serving: Poisson arrivals at a frozen rate of mixed-family requests
     (n log-uniform in [2^10, 2^22], mean degree 4-32), for at least a minute;
@@ -693,13 +730,38 @@ def bench_serve(args):
     run(warm, slots)
     run(warm[:50], [serial_slot], max_batch=1)
     reqs, _ = stream_of(n_cap, np.zeros(n_cap), 50)
-    comps, st, wall = run(reqs, slots)
+
+    def set_digests(on):  # the verification fingerprints are GPU work that serving does not do
+        for sl in slots:
+            sl.solver.digests = on
+        serial_slot.digests = on
+
+    set_digests(False)
+    comps_t, st, wall = run(reqs, slots)
     cap = n_cap / wall
     log(f"[bench] served capacity {cap:.1f} graphs/s ({n_cap} requests queued at t=0, {st['batches']} batches)")
-    comps_c1, _, wall_c1 = run(reqs, [serial_slot], max_batch=1)
+    comps_c1t, _, wall_c1 = run(reqs, [serial_slot], max_batch=1)
     cap_serial = n_cap / wall_c1
     log(f"[bench] serial capacity {cap_serial:.1f} graphs/s")
-    same_cap = all(a.ok and b.ok and a.digest == b.digest for a, b in zip(comps, comps_c1))
+    link = pinned_link_rates(dev)
+    # bytes a request moves: its CSR in (row starts and arcs), its labels,
+    # AP flags and count out
+    in_bytes = float(np.mean([4 * r.graph.num_arcs + 4 * (r.graph.n + 1) for r in reqs]))
+    out_bytes = float(np.mean([4 * r.graph.num_arcs + r.graph.n + 20 for r in reqs]))
+    req_bytes = in_bytes + out_bytes
+    link_bound = min(link["h2d_GBps"] * 1e9 / in_bytes, link["d2h_GBps"] * 1e9 / out_bytes,
+                     link["both_total_GBps"] * 1e9 / req_bytes)
+    log(f"[bench] pinned link: H2D {link['h2d_GBps']:.1f} GB/s, D2H {link['d2h_GBps']:.1f} GB/s, both at once "
+        f"{link['both_total_GBps']:.1f} GB/s total; {req_bytes / 1e6:.1f} MB per request -> at most "
+        f"{link_bound:.0f} graphs/s over the link (served: {100 * cap / link_bound:.0f}% of it)")
+    set_digests(True)
+    # the same two runs again with fingerprints, untimed, to check them equal
+    comps, _, _ = run(reqs, slots)
+    comps_c1, _, _ = run(reqs, [serial_slot], max_batch=1)
+    same_cap = all(a.ok and b.ok and a.digest == b.digest and a.num_bcc == b.num_bcc
+                   for a, b in zip(comps, comps_c1))
+    same_cap = same_cap and all(a.ok and b.ok and a.num_bcc == c.num_bcc == b.num_bcc
+                                for a, b, c in zip(comps_t, comps_c1t, comps))
     if qps is None:
         qps = 0.7 * cap
     count = max(int(np.ceil(qps * args.serve_seconds)), 1)
@@ -749,6 +811,8 @@ def bench_serve(args):
                    "qps_source": "frozen" if (args.qps or SERVE_QPS) else "0.7 x capacity measured in this run",
                    "arrival_span_s": float(arr[-1]), "flags": flags, "input_contract": "general",
                    "capacity_graphs_per_s": cap, "serial_capacity_graphs_per_s": cap_serial,
+                   "pinned_link": link, "bytes_per_request": req_bytes,
+                   "link_bound_graphs_per_s": link_bound, "served_fraction_of_link_bound": cap / link_bound,
                    "capacity_requests": n_cap, "served_vs_serial_capacity": cap / cap_serial,
                    "slots": args.slots, "hbm_budget_bytes_initial": budget,
                    "hbm_budget_bytes_min": st["min_budget"], "budget_reads": st["budget_reads"],
