@@ -479,13 +479,17 @@ class SplitBatchedSolver:
         self.big.launch(keep_host)
 
     def replay(self) -> None:
-        """Replay both captured solves, each on its own stream (inputs as
-        last copied; nothing copied back)."""
+        """Solve both parts again, each on its own stream, from their captured
+        HIP graphs when they have them (inputs as last copied; nothing copied
+        back)."""
         for part in (self.small, self.big):
             part._ensure_graph()
         for part in (self.small, self.big):
             with torch.cuda.stream(part.stream):
-                part.graph.replay()
+                if part.graph is not None:
+                    part.graph.replay()
+                else:  # built without HIP graphs: the same launches, eagerly
+                    part._launch()
 
     def synchronize(self) -> None:
         self.small.stream.synchronize()
