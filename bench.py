@@ -851,8 +851,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design notes describe how the solve would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library solves a graph on one GPU and has no "
+              "multi-GPU path (the design notes describe how the solve would shard).", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration_mib:
