@@ -232,7 +232,7 @@ FASTBCC_API fastbcc_status fastbcc_solve_batched(int32_t num_graphs, const int32
  *   - flags: FASTBCC_FLAG_SORTED_ROWS and FASTBCC_FLAG_NO_SELF_LOOPS are
  *     accepted and not needed; any other bit is FASTBCC_ERR_INVALID_ARGUMENT.
  *   - out_is_ap may be null; out_edge_label may be null only when
- *     num_arcs == 0.
+ *     num_arcs == 0.  num_arcs >= 2^31 - 64 is FASTBCC_ERR_TOO_LARGE.
  */
 #define FASTBCC_SMALL_MAX_VERTICES 3072
 FASTBCC_API fastbcc_status fastbcc_solve_small(int32_t num_graphs, const int32_t* graph_vbegin, int32_t num_packs,

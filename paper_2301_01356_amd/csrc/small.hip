@@ -262,12 +262,12 @@ __global__ void __launch_bounds__(T) k_small_bcc(const int* __restrict__ vbegin,
       }
       return lo;
     };
-    const int per = (A + T - 1) / T;
-    const int ab = min(tid * per, A), ae = min(ab + per, A);
+    const int64_t per = ((int64_t)A + T - 1) / T;  // 64-bit: tid * per may pass 2^31 before the clamp
+    const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
     auto for_arcs = [&](auto&& body) {
       if (ab >= ae) return;
       int v = row_of(ab);
-      for (int c0 = ab; c0 < ae; c0 += ARC_CHUNK) {
+      for (int c0 = ab; c0 < ae; c0 += ARC_CHUNK) {  // c0 + ARC_CHUNK < 2^31: the entry point bounds the arcs
         int tg[ARC_CHUNK];
 #pragma unroll
         for (int k = 0; k < ARC_CHUNK; ++k) tg[k] = c0 + k < ae ? adj[a0 + c0 + k] - v0 : -1;
@@ -735,7 +735,8 @@ FASTBCC_API fastbcc_status fastbcc_solve_small(int32_t num_graphs, const int32_t
     return FASTBCC_ERR_INVALID_ARGUMENT;
   if (pack_begin == nullptr) num_packs = num_graphs;
   else if (num_packs < 1) return FASTBCC_ERR_INVALID_ARGUMENT;
-  if (n_total >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31)) return FASTBCC_ERR_TOO_LARGE;
+  // arcs stay 64 below 2^31 so that a thread's chunk index never wraps
+  if (n_total >= (int64_t(1) << 30) || num_arcs >= (int64_t(1) << 31) - 64) return FASTBCC_ERR_TOO_LARGE;
   if (num_arcs > 0 && (adj == nullptr || out_edge_label == nullptr)) return FASTBCC_ERR_INVALID_ARGUMENT;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return FASTBCC_ERR_HIP;

@@ -93,6 +93,7 @@ def test_solve_small_argument_errors_are_synchronous():
     assert f(1, 256, 0, None, 10, 10, 256, 256, 256, None, 256, 1 << N.TUNE_RULER_SHIFT, None) \
         == N.ERR_INVALID_ARGUMENT  # tuning fields belong to the general path
     assert f(1, 256, 0, None, 1 << 30, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_TOO_LARGE
+    assert f(1, 256, 0, None, 10, (1 << 31) - 64, 256, 256, 256, None, 256, 0, None) == N.ERR_TOO_LARGE
     assert f(1, 256, 0, None, -1, 10, 256, 256, 256, None, 256, 0, None) == N.ERR_INVALID_ARGUMENT
 
 
