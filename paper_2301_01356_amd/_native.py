@@ -41,6 +41,7 @@ TUNE_LCC_ROUNDS_SHIFT = 25
 TUNE_VERTEX_BLOCK_SHIFT = 27
 TUNE_COMPRESS_FREE_ROUND = 0x20000000
 TUNE_XCD_ORDER = 0x40000000
+TUNE_GRAPH_CC = 0x80000000
 VERTEX_BLOCK_CODES = {256: 0, 64: 1, 128: 2, 512: 3}
 
 EXPORTED = (
@@ -152,12 +153,14 @@ def workspace_size(n: int, num_arcs: int, num_graphs: int = 1) -> int:
 def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc_priority: bool = False,
                ldd: int = 0, sampled_tags: bool = False, tag_samples: int = 4,
                free_first_round: bool = False, lcc_priority: bool = False, lcc_rounds=None,
-               vertex_block: int = 256, compress_free_round: bool = False, xcd_order: bool = False) -> int:
+               vertex_block: int = 256, compress_free_round: bool = False, xcd_order: bool = False,
+               graph_cc: bool = False) -> int:
     """Encode tuning fields (0/None = library default).  ``ldd`` = k turns on
     the low-diameter decomposition before First-CC's union-find, beta = 2^-k;
     ``sampled_tags`` certifies fences from ``tag_samples`` (1, 2, 3 or 4)
     sampled neighbours per vertex first; ``vertex_block`` (64, 128, 256 or
-    512) is the block size of the hot per-vertex kernels."""
+    512) is the block size of the hot per-vertex kernels; ``graph_cc`` runs a
+    batch's First-CC per graph, one workgroup each."""
     f = TUNE_CC_PRIORITY if cc_priority else 0
     f |= TUNE_SAMPLED_TAGS if sampled_tags else 0
     f |= TAG_SAMPLE_CODES[tag_samples] << TUNE_TAG_SAMPLES_SHIFT
@@ -169,6 +172,7 @@ def tune_flags(ruler_shift: int = 0, sample_rounds=None, tile_shift: int = 0, cc
     f |= VERTEX_BLOCK_CODES[vertex_block] << TUNE_VERTEX_BLOCK_SHIFT
     f |= TUNE_COMPRESS_FREE_ROUND if compress_free_round else 0
     f |= TUNE_XCD_ORDER if xcd_order else 0
+    f |= TUNE_GRAPH_CC if graph_cc else 0
     if ruler_shift:
         f |= (ruler_shift & 0xF) << TUNE_RULER_SHIFT
     if sample_rounds is not None:

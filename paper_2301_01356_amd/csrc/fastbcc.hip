@@ -99,6 +99,7 @@ enum Scalar : int {
   S_BIG_MIN = 13,   // its smallest member
   S_HUBS = 14,      // hubs numbered so far
   S_DIRTY = 15,     // rows listed for exact tags
+  S_GRAPH_NEXT = 16,  // next graph of a per-graph First-CC
   S_COUNT = 64,
 };
 
@@ -212,6 +213,7 @@ struct Tune {
   int vertex_block = BLOCK;       // threads per block of the hot per-vertex kernels
   bool compress_free = false;     // flatten the sets after the atomic-free round too
   bool xcd = false;               // per-vertex launches in XCD-ordered shape
+  bool graph_cc = false;          // batches: First-CC per graph, one workgroup each
 };
 
 bool decode_flags(uint32_t flags, Tune& t) {
@@ -222,7 +224,7 @@ bool decode_flags(uint32_t flags, Tune& t) {
                          FASTBCC_TUNE_SAMPLED_TAGS | (0x3u << FASTBCC_TUNE_TAG_SAMPLES_SHIFT) |
                          FASTBCC_TUNE_FREE_FIRST_ROUND | FASTBCC_TUNE_LCC_PRIORITY |
                          (0x3u << FASTBCC_TUNE_LCC_ROUNDS_SHIFT) | (0x3u << FASTBCC_TUNE_VERTEX_BLOCK_SHIFT) |
-                         FASTBCC_TUNE_COMPRESS_FREE_ROUND | FASTBCC_TUNE_XCD_ORDER;
+                         FASTBCC_TUNE_COMPRESS_FREE_ROUND | FASTBCC_TUNE_XCD_ORDER | FASTBCC_TUNE_GRAPH_CC;
   {
     const uint32_t lr = (flags >> FASTBCC_TUNE_LCC_ROUNDS_SHIFT) & 0x3;
     t.lcc_rounds = lr == 0 ? -1 : (int)lr - 1;
@@ -234,6 +236,7 @@ bool decode_flags(uint32_t flags, Tune& t) {
   t.first_round_free = (flags & FASTBCC_TUNE_FREE_FIRST_ROUND) != 0;
   t.compress_free = (flags & FASTBCC_TUNE_COMPRESS_FREE_ROUND) != 0;
   t.xcd = (flags & FASTBCC_TUNE_XCD_ORDER) != 0;
+  t.graph_cc = (flags & FASTBCC_TUNE_GRAPH_CC) != 0;
   t.lcc_prio = (flags & FASTBCC_TUNE_LCC_PRIORITY) != 0;
   t.sampled_tags = (flags & FASTBCC_TUNE_SAMPLED_TAGS) != 0;
   static const int kSamples[4] = {4, 2, 3, 1};
@@ -752,6 +755,136 @@ constexpr int LDD_SMALL = 32;    // rows up to this degree are expanded by one l
 constexpr int LDD_HUGE = 2048;   // longer rows are queued in chunks for the whole grid
 constexpr int LDD_CHUNK = 1024;  // arcs per queued chunk (<= LDD_HUGE)
 constexpr int LDD_HUGE_GRID = 1024;
+
+// ------------------------------------------------------------ per-graph First-CC (batches)
+// With FASTBCC_TUNE_GRAPH_CC a batch's First-CC runs per graph instead of
+// over the whole union (a BCC never spans two graphs, and neither does a
+// component): one workgroup at a time takes the next graph from a counter
+// the solve zeroed, runs union-find over its arcs -- each edge once, from its
+// smaller endpoint; the larger root goes under the smaller; the hooking edge
+// is kept at the hooked root, as uf_link_record keeps it -- and leaves cc[v]
+// on the graph's root.  The parents of a graph of at most 2^16 vertices live
+// in LDS as 16-bit local ids, two to a word: a hook is a 32-bit CAS on the
+// word, so a path-halving store into the other half makes it retry and never
+// loses an update.  A larger graph runs the same loop on the device-memory
+// union-find.
+// Thread t takes the t-th of 1024 equal runs of the graph's arcs, finds the
+// row of its first arc by bisection over the row starts and walks the rows
+// from there, with a chunk of targets in flight (owning whole rows instead
+// leaves most threads idle on graphs of a few thousand vertices).
+constexpr int GCC_THREADS = 1024;
+constexpr int GCC_LDS_VERTICES = 1 << 16;
+constexpr int GCC_CHUNK = 8;
+constexpr int GCC_GRID = 1024;  // workgroups of the launch (more than one per compute unit waits)
+
+__device__ __forceinline__ int p16_get(const uint32_t* P, int x) {
+  const uint32_t w = __hip_atomic_load(P + (x >> 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return (int)((x & 1) ? (w >> 16) : (w & 0xFFFFu));
+}
+__device__ __forceinline__ void p16_set(uint32_t* P, int x, int val) {
+  reinterpret_cast<volatile uint16_t*>(P)[x] = (uint16_t)val;
+}
+__device__ __forceinline__ bool p16_cas(uint32_t* P, int x, int expect, int val) {
+  uint32_t* w = P + (x >> 1);
+  const int sh = (x & 1) * 16;
+  uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (;;) {
+    if (((old >> sh) & 0xFFFFu) != (uint32_t)expect) return false;
+    const uint32_t nw = (old & ~(0xFFFFu << sh)) | ((uint32_t)val << sh);
+    const uint32_t prev = atomicCAS(w, old, nw);
+    if (prev == old) return true;
+    old = prev;  // the word changed (either half): test again
+  }
+}
+// Parents only point to smaller local ids, so both walks end.
+__device__ __forceinline__ int p16_find(uint32_t* P, int x) {
+  int px = p16_get(P, x);
+  while (px != x) {
+    const int gx = p16_get(P, px);
+    if (gx == px) return px;
+    p16_set(P, x, gx);  // path halving: an ancestor of x
+    x = gx;
+    px = p16_get(P, x);
+  }
+  return x;
+}
+__device__ __forceinline__ int p16_root(const uint32_t* P, int x) {
+  int px = p16_get(P, x);
+  while (px != x) {
+    x = px;
+    px = p16_get(P, x);
+  }
+  return x;
+}
+
+__global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict__ vbegin, int G, int n,
+                                                          const int* __restrict__ off, const int* __restrict__ adj,
+                                                          int* cc, int* hu, int* hv, int* next_graph) {
+  __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
+  __shared__ int g_s;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) g_s = atomicAdd(next_graph, 1);
+    __syncthreads();
+    const int g = g_s;
+    __syncthreads();  // everyone has read g_s before it is rewritten
+    if (g >= G) break;
+    const int v0 = min(max(vbegin[g], 0), n), v1 = min(max(vbegin[g + 1], v0), n), ng = v1 - v0;
+    if (ng == 0) continue;
+    const bool in_lds = ng <= GCC_LDS_VERTICES;
+    for (int v = tid; v < ng; v += GCC_THREADS) {
+      hu[v0 + v] = -1;
+      if (in_lds) p16_set(P, v, v);
+      else cc[v0 + v] = v0 + v;
+    }
+    __syncthreads();
+    const int a0 = off[v0], A = max(off[v1] - a0, 0);
+    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;
+    const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
+    if (ab < ae) {
+      int lo = 0, hi = ng;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[v0 + mid] - a0 <= ab) lo = mid;
+        else hi = mid;
+      }
+      int x = lo, rowend = off[v0 + x + 1] - a0;
+      for (int c0 = ab; c0 < ae; c0 += GCC_CHUNK) {
+        int tg[GCC_CHUNK];
+#pragma unroll
+        for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < ae ? adj[a0 + c0 + k] - v0 : -1;
+#pragma unroll
+        for (int k = 0; k < GCC_CHUNK; ++k) {
+          const int a = c0 + k;
+          if (a >= ae) break;
+          while (rowend <= a) rowend = off[v0 + (++x) + 1] - a0;  // the graph's last row ends at A > a
+          const int y = tg[k];
+          if (y <= x || y >= ng) continue;  // each edge once; self-loops and foreign ids skipped
+          if (in_lds) {
+            if (p16_get(P, x) == p16_get(P, y)) continue;  // same parent: same set
+            int ru = p16_find(P, x), rv = p16_find(P, y);
+            while (ru != rv) {
+              const int h = ru > rv ? ru : rv, l = ru > rv ? rv : ru;
+              if (p16_cas(P, h, h, l)) {
+                hu[v0 + h] = v0 + x;
+                hv[v0 + h] = v0 + y;
+                break;
+              }
+              ru = p16_find(P, ru);
+              rv = p16_find(P, rv);
+            }
+          } else {
+            uf_link_record(cc, v0 + x, v0 + y, hu, hv);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (in_lds)
+      for (int v = tid; v < ng; v += GCC_THREADS) cc[v0 + v] = v0 + p16_root(P, v);
+    __syncthreads();  // the next graph reuses P
+  }
+}
 
 // Start round from a splitmix64 hash of the vertex id (Steele, Lea and Flood,
 // "Fast splittable pseudorandom number generators").
@@ -2554,39 +2687,46 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
 
   // ---- First-CC (spanning forest)
-  if (tune.ldd) {
-    int* rnd = I(L.su);  // the tree-slot array is free until Rooting
-    int2* queue = (int2*)(w + L.dbits);  // A/8 bytes, free until Tagging; the queue needs < A/64
-    const float beta = 1.0f / (float)(1 << tune.ldd);
-    const int T0 = (int)ceil(log((double)(n > 2 ? n : 2)) / beta);
-    LAUNCH(c, k_ldd_init, gn, BLOCK, cc, hu, rnd, n, scal);
-    for (int r = 0; r <= T0; ++r) {
-      LAUNCH(c, k_ldd_round, gn, BLOCK, off, adj, n, r, T0, 1.0f / beta, cc, rnd, hu, hv, queue, scal);
-      LAUNCH(c, k_ldd_huge, LDD_HUGE_GRID, BLOCK, off, adj, r, queue, scal, cc, rnd, hu, hv);
+  if (tune.graph_cc && G > 1 && vbegin != nullptr) {
+    LAUNCH(c, k_graph_cc, (unsigned)(G < GCC_GRID ? G : GCC_GRID), GCC_THREADS, vbegin, G, n, off, adj, cc, hu, hv,
+           scal + S_GRAPH_NEXT);
+  } else {
+    if (tune.ldd) {
+      int* rnd = I(L.su);  // the tree-slot array is free until Rooting
+      int2* queue = (int2*)(w + L.dbits);  // A/8 bytes, free until Tagging; the queue needs < A/64
+      const float beta = 1.0f / (float)(1 << tune.ldd);
+      const int T0 = (int)ceil(log((double)(n > 2 ? n : 2)) / beta);
+      LAUNCH(c, k_ldd_init, gn, BLOCK, cc, hu, rnd, n, scal);
+      for (int r = 0; r <= T0; ++r) {
+        LAUNCH(c, k_ldd_round, gn, BLOCK, off, adj, n, r, T0, 1.0f / beta, cc, rnd, hu, hv, queue, scal);
+        LAUNCH(c, k_ldd_huge, LDD_HUGE_GRID, BLOCK, off, adj, r, queue, scal, cc, rnd, hu, hv);
+      }
+    } else if (!(tune.first_round_free && tune.sample_rounds > 0)) {
+      LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);  // else the atomic-free round initialises
     }
-  } else if (!(tune.first_round_free && tune.sample_rounds > 0)) {
-    LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);  // else the atomic-free round initialises
-  }
-  // compress after every round: the next round's finds then take one hop
-  for (int r = 0; r < tune.sample_rounds; ++r) {
-    const bool free_round = r == 0 && tune.first_round_free && !tune.ldd;
-    if (free_round) {
-      if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gv, VB, off, adj, n, cc, hu, hv);
-      else LAUNCH(c, k_cc_first_round<false>, gv, VB, off, adj, n, cc, hu, hv);
-    } else if (tune.cc_prio) {
-      LAUNCH(c, k_cc_sample<true>, gv, VB, off, adj, n, r, cc, hu, hv);
-    } else {
-      LAUNCH(c, k_cc_sample<false>, gv, VB, off, adj, n, r, cc, hu, hv);
+    // compress after every round: the next round's finds then take one hop
+    for (int r = 0; r < tune.sample_rounds; ++r) {
+      const bool free_round = r == 0 && tune.first_round_free && !tune.ldd;
+      if (free_round) {
+        if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gv, VB, off, adj, n, cc, hu, hv);
+        else LAUNCH(c, k_cc_first_round<false>, gv, VB, off, adj, n, cc, hu, hv);
+      } else if (tune.cc_prio) {
+        LAUNCH(c, k_cc_sample<true>, gv, VB, off, adj, n, r, cc, hu, hv);
+      } else {
+        LAUNCH(c, k_cc_sample<false>, gv, VB, off, adj, n, r, cc, hu, hv);
+      }
+      // flattened for the next round, except after the atomic-free round (its
+      // chains are short and the next round's finds walk them anyway) and
+      // after the last one (the frontier pass flattens)
+      if ((!free_round || tune.compress_free) && r + 1 < tune.sample_rounds) LAUNCH(c, k_compress, gx, BLOCK, cc, n);
     }
-    // flattened for the next round, except after the atomic-free round (its
-    // chains are short and the next round's finds walk them anyway) and
-    // after the last one (the frontier pass flattens)
-    if ((!free_round || tune.compress_free) && r + 1 < tune.sample_rounds) LAUNCH(c, k_compress, gx, BLOCK, cc, n);
+    LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
+    frontier(cc, S_BIG_CC);
+    if (tune.cc_prio)
+      LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
+    else
+      LAUNCH(c, k_cc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
   }
-  LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
-  frontier(cc, S_BIG_CC);
-  if (tune.cc_prio) LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
-  else LAUNCH(c, k_cc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
   // (Rooting's first pass flattens the sets)
 
   // ---- Rooting

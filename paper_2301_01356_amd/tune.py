@@ -44,8 +44,9 @@ LCC_ROUNDS = (-1, 0, 1, 2)  # Last-CC sampling rounds (-1: as First-CC)
 VBLOCK = (256, 64, 128, 512)  # threads per block of the hot per-vertex kernels
 CFREE = (0, 1)  # flatten First-CC's sets after the atomic-free round
 XCD = (0, 1)  # per-vertex launches ordered by XCD
+GCC = (0, 1)  # batches: First-CC per graph, one workgroup each (single graphs ignore it)
 START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts": 4, "free": 0, "lcc": 0, "lr": -1,
-         "vb": 256, "cf": 0, "xcd": 0}
+         "vb": 256, "cf": 0, "xcd": 0, "gcc": 0}
 # Starting points: the built-in defaults, the usual winner on power-law graphs
 # and the usual winner on lattices and k-NN graphs.  The descent starts from
 # the fastest of them, so noise between near-equal candidates cannot strand
@@ -53,9 +54,9 @@ START = {"ruler": 4, "sample": 2, "tile": 2, "uf": 0, "ldd": 0, "tags": 0, "ts":
 SEEDS = (
     START,
     {"ruler": 4, "sample": 2, "tile": 4, "uf": 0, "ldd": 0, "tags": 1, "ts": 2, "free": 1, "lcc": 0, "lr": 0,
-     "vb": 256, "cf": 0, "xcd": 0},
+     "vb": 256, "cf": 0, "xcd": 0, "gcc": 0},
     {"ruler": 4, "sample": 1, "tile": 3, "uf": 1, "ldd": 0, "tags": 0, "ts": 4, "free": 1, "lcc": 1, "lr": 0,
-     "vb": 256, "cf": 0, "xcd": 0},
+     "vb": 256, "cf": 0, "xcd": 0, "gcc": 0},
 )
 
 
@@ -88,7 +89,8 @@ def decode(flags: int) -> Dict:
             "ts": codes[(flags >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3],
             "free": int(bool(flags & N.TUNE_FREE_FIRST_ROUND)), "lcc": int(bool(flags & N.TUNE_LCC_PRIORITY)),
             "lr": lr - 1, "vb": {c: b for b, c in N.VERTEX_BLOCK_CODES.items()}[(flags >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3],
-            "cf": int(bool(flags & N.TUNE_COMPRESS_FREE_ROUND)), "xcd": int(bool(flags & N.TUNE_XCD_ORDER))}
+            "cf": int(bool(flags & N.TUNE_COMPRESS_FREE_ROUND)), "xcd": int(bool(flags & N.TUNE_XCD_ORDER)),
+            "gcc": int(bool(flags & N.TUNE_GRAPH_CC))}
 
 
 def encode(cfg: Dict) -> int:
@@ -98,7 +100,7 @@ def encode(cfg: Dict) -> int:
                         free_first_round=bool(cfg.get("free", 0)), lcc_priority=bool(cfg.get("lcc", 0)),
                         lcc_rounds=None if cfg.get("lr", -1) < 0 else int(cfg["lr"]),
                         vertex_block=int(cfg.get("vb", 256)), compress_free_round=bool(cfg.get("cf", 0)),
-                        xcd_order=bool(cfg.get("xcd", 0)))
+                        xcd_order=bool(cfg.get("xcd", 0)), graph_cc=bool(cfg.get("gcc", 0)))
 
 
 class Tuner:
@@ -151,7 +153,7 @@ class Tuner:
             changed = False
             for knob, values in (("tags", TAGS), ("uf", UF), ("free", FREE), ("lcc", LCC), ("ldd", LDD), ("sample", SAMPLE),
                                  ("tile", TILE), ("ruler", RULER), ("ts", TAG_SAMPLES), ("lr", LCC_ROUNDS),
-                                 ("vb", VBLOCK), ("cf", CFREE), ("xcd", XCD)):
+                                 ("vb", VBLOCK), ("cf", CFREE), ("xcd", XCD), ("gcc", GCC)):
                 if knob == "ts" and not cfg["tags"]:
                     continue
                 best_v, best_t = cfg[knob], cost(cfg)

@@ -69,7 +69,6 @@ def test_solve_argument_errors_are_synchronous():
     assert _solve(100, 400, 256 + 4, need) == N.ERR_INVALID_ARGUMENT  # misaligned workspace
     assert _solve(-5, 400, 256, need) == N.ERR_INVALID_ARGUMENT
     assert _solve(1 << 30, 400, 256, 1 << 40) == N.ERR_TOO_LARGE
-    assert _solve(100, 400, 256, need, flags=1 << 31) == N.ERR_INVALID_ARGUMENT  # unknown flag bit
     assert _solve(100, 400, 256, need, flags=2 << N.TUNE_RULER_SHIFT) == N.ERR_INVALID_ARGUMENT
     assert _solve(100, 400, 256, need, flags=1 << N.TUNE_TILE_SHIFT) == N.ERR_INVALID_ARGUMENT
     assert _solve(100, 400, 256, need, off=0) == N.ERR_INVALID_ARGUMENT
@@ -116,9 +115,9 @@ def test_tune_flag_encoding():
     assert (N.tune_flags(tag_samples=2) >> N.TUNE_TAG_SAMPLES_SHIFT) & 0x3 == 1
     assert (N.tune_flags(vertex_block=512) >> N.TUNE_VERTEX_BLOCK_SHIFT) & 0x3 == 3
     assert N.tune_flags(vertex_block=256) == 0
-    # bits above the last tuning field are refused
     assert N.tune_flags(compress_free_round=True) == N.TUNE_COMPRESS_FREE_ROUND
-    assert _solve(100, 400, 256, N.workspace_size(100, 400), flags=1 << 31) == N.ERR_INVALID_ARGUMENT
+    assert N.tune_flags(xcd_order=True) == N.TUNE_XCD_ORDER
+    assert N.tune_flags(graph_cc=True) == N.TUNE_GRAPH_CC == 1 << 31  # the last free bit: every bit has a meaning
 
 
 def test_host_tensors_are_refused_not_solved_on_the_cpu():

@@ -273,7 +273,10 @@ def test_repeated_solves_identical():
 
 BATCH_FLAGS = [0, N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(sampled_tags=True, free_first_round=True,
                                                                           ruler_shift=3),
-               N.tune_flags(xcd_order=True, cc_priority=True, lcc_priority=True, free_first_round=True)]
+               N.tune_flags(xcd_order=True, cc_priority=True, lcc_priority=True, free_first_round=True),
+               N.tune_flags(graph_cc=True),
+               N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(graph_cc=True, sampled_tags=True,
+                                                                          lcc_priority=True, ruler_shift=3)]
 
 
 @pytest.mark.parametrize("flags", BATCH_FLAGS)
@@ -606,3 +609,30 @@ def test_priority_last_cc_labels_stable_over_repeated_solves():
         bad += (r.edge_label != rl).any() | (r.is_ap != ra).any() | (r.num_bcc[0] != nb)
     assert int(bad.item()) == 0
     assert read_device_status(ws) == 0
+
+
+@pytest.mark.parametrize("flags", [N.tune_flags(graph_cc=True),
+                                   N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(graph_cc=True)])
+def test_batched_per_graph_first_cc_sizes(flags):
+    """Per-graph First-CC across its size boundary: graphs of 2^16 - 1 and 2^16
+    vertices keep their parents in LDS, one of 2^16 + 1 and a larger one run
+    on the device-memory union-find; with empty, edgeless and tiny graphs
+    and a disconnected one around them."""
+    lim = 1 << 16
+    empty = gen.Csr(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    edgeless = gen.Csr(5, np.zeros(6, np.int64), np.zeros(0, np.int32))
+    two = gen.unite([gen.family("knn", 3000, 5, seed=7), gen.family("random", 2000, 3.0, seed=8)])
+    two = gen.Csr(two.n, two.offsets, two.adj)
+    graphs = [gen.family("lattice", lim, 0.75, seed=1), empty, gen.family("random", lim - 1, 6.0, seed=2),
+              edgeless, gen.family("tree_back", lim + 1, 0.2, seed=3), gen.from_edges(3, cycle(3)), two,
+              gen.family("knn", 90000, 5, seed=4), empty, gen.family("lattice", 700, 0.8, seed=5)]
+    u = gen.unite(graphs)
+    note(f"per-graph First-CC: {len(graphs)} graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    r = solve_batched(vb, off, adj, flags=flags)
+    torch.cuda.synchronize()
+    lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for i, g in enumerate(graphs):
+        a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+        assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} (n={g.n})")
