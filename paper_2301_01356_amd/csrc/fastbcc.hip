@@ -100,6 +100,7 @@ enum Scalar : int {
   S_HUBS = 14,      // hubs numbered so far
   S_DIRTY = 15,     // rows listed for exact tags
   S_GRAPH_NEXT = 16,  // next graph of a per-graph First-CC
+  S_GRAPH_NEXT_LCC = 17,  // next graph of a per-graph Last-CC
   S_COUNT = 64,
 };
 
@@ -821,7 +822,7 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
                                                           const int* __restrict__ off, const int* __restrict__ adj,
                                                           int* cc, int* hu, int* hv, int* next_graph) {
   __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
-  __shared__ int g_s;
+  __shared__ int g_s, big_s;
   const int tid = threadIdx.x;
   for (;;) {
     if (tid == 0) g_s = atomicAdd(next_graph, 1);
@@ -839,6 +840,54 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     }
     __syncthreads();
     const int a0 = off[v0], A = max(off[v1] - a0, 0);
+    // hook the sets of local x and y, keeping the hooking edge
+    auto link16 = [&](int x, int y) {
+      if (p16_get(P, x) == p16_get(P, y)) return;  // same parent: same set
+      int ru = p16_find(P, x), rv = p16_find(P, y);
+      while (ru != rv) {
+        const int h = ru > rv ? ru : rv, l = ru > rv ? rv : ru;
+        if (p16_cas(P, h, h, l)) {
+          hu[v0 + h] = v0 + x;
+          hv[v0 + h] = v0 + y;
+          return;
+        }
+        ru = p16_find(P, ru);
+        rv = p16_find(P, rv);
+      }
+    };
+    int big = -1;  // sets rooted with big (sampled largest set) skip their rows below
+    if (in_lds) {
+      // two sampling rounds: every vertex links to one hashed neighbour
+      for (int r = 0; r < 2; ++r) {
+        for (int v = tid; v < ng; v += GCC_THREADS) {
+          const int b = min(max(off[v0 + v] - a0, 0), A), e = min(max(off[v0 + v + 1] - a0, b), A);
+          if (e > b) {
+            const int y = adj[a0 + b + (int)sample_pos(v0 + v, r, e - b)] - v0;
+            if (y != v && y >= 0 && y < ng) link16(v, y);
+          }
+        }
+        __syncthreads();
+      }
+      // the set most of 64 evenly spread vertices fall in
+      if (tid < WAVE) {
+        const int r = p16_root(P, (int)((int64_t)tid * ng / WAVE));
+        int cnt = 0;
+        for (int j = 0; j < WAVE; ++j) cnt += __shfl(r, j, WAVE) == r ? 1 : 0;
+        int best_c = cnt, best_r = r;
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+          const int oc = __shfl_xor(best_c, o, WAVE), orr = __shfl_xor(best_r, o, WAVE);
+          if (oc > best_c || (oc == best_c && orr < best_r)) {
+            best_c = oc;
+            best_r = orr;
+          }
+        }
+        if (tid == 0) big_s = best_r;
+      }
+      __syncthreads();
+      big = big_s;
+    }
+    // the sweep: every arc of every row outside the big set (an edge between
+    // two rows that are both skipped lies inside the big set already)
     const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;
     const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
     if (ab < ae) {
@@ -848,35 +897,27 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
         if (off[v0 + mid] - a0 <= ab) lo = mid;
         else hi = mid;
       }
-      int x = lo, rowend = off[v0 + x + 1] - a0;
-      for (int c0 = ab; c0 < ae; c0 += GCC_CHUNK) {
-        int tg[GCC_CHUNK];
+      int x = lo, a = ab;
+      while (a < ae) {  // one row per step; the graph's last row ends at A >= ae
+        const int rend = min(max(off[v0 + x + 1] - a0, a), ae);
+        const bool skip = in_lds && rend > a && p16_find(P, x) == p16_find(P, big);
+        if (!skip) {
+          for (int c0 = a; c0 < rend; c0 += GCC_CHUNK) {
+            int tg[GCC_CHUNK];
 #pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < ae ? adj[a0 + c0 + k] - v0 : -1;
+            for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
 #pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k) {
-          const int a = c0 + k;
-          if (a >= ae) break;
-          while (rowend <= a) rowend = off[v0 + (++x) + 1] - a0;  // the graph's last row ends at A > a
-          const int y = tg[k];
-          if (y <= x || y >= ng) continue;  // each edge once; self-loops and foreign ids skipped
-          if (in_lds) {
-            if (p16_get(P, x) == p16_get(P, y)) continue;  // same parent: same set
-            int ru = p16_find(P, x), rv = p16_find(P, y);
-            while (ru != rv) {
-              const int h = ru > rv ? ru : rv, l = ru > rv ? rv : ru;
-              if (p16_cas(P, h, h, l)) {
-                hu[v0 + h] = v0 + x;
-                hv[v0 + h] = v0 + y;
-                break;
-              }
-              ru = p16_find(P, ru);
-              rv = p16_find(P, rv);
+            for (int k = 0; k < GCC_CHUNK; ++k) {
+              if (c0 + k >= rend) break;
+              const int y = tg[k];
+              if (y == x || y < 0 || y >= ng) continue;  // self-loops and foreign ids skipped
+              if (in_lds) link16(x, y);
+              else if (y > x) uf_link_record(cc, v0 + x, v0 + y, hu, hv);  // each edge once
             }
-          } else {
-            uf_link_record(cc, v0 + x, v0 + y, hu, hv);
           }
         }
+        a = rend;
+        ++x;
       }
     }
     __syncthreads();
@@ -1675,6 +1716,122 @@ __device__ __forceinline__ bool cross_edge(int x, int4 rx, int y, int4 ry) {
   const bool y_under_x = rx.x <= ry.x && ry.x <= rx.y;
   const bool x_under_y = ry.x <= rx.x && rx.x <= ry.y;
   return !y_under_x && !x_under_y;
+}
+
+// Last-CC per graph of a batch (FASTBCC_TUNE_GRAPH_CC): the union-find of
+// k_graph_cc on the skeleton instead of the graph -- plain tree edges first,
+// then cross edges (InSkeleton: neither endpoint an ancestor of the other) --
+// hooked by id, so each set's root is its smallest member, as the read-out
+// needs.  Two sampling rounds link each vertex to the neighbour at a hashed
+// position of its row when that edge is a cross edge; the sweep then reads
+// every arc of the rows outside the sampled largest set.  Graphs above the
+// LDS size run on the device-memory union-find (flattened afterwards).
+__global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict__ vbegin, int G, int n,
+                                                           const int* __restrict__ off, const int* __restrict__ adj,
+                                                           const int4* __restrict__ rec, int* lab, int* next_graph) {
+  __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
+  __shared__ int g_s, big_s;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) g_s = atomicAdd(next_graph, 1);
+    __syncthreads();
+    const int g = g_s;
+    __syncthreads();  // everyone has read g_s before it is rewritten
+    if (g >= G) break;
+    const int v0 = min(max(vbegin[g], 0), n), v1 = min(max(vbegin[g + 1], v0), n), ng = v1 - v0;
+    if (ng == 0) continue;
+    const bool in_lds = ng <= GCC_LDS_VERTICES;
+    for (int v = tid; v < ng; v += GCC_THREADS) {
+      if (in_lds) p16_set(P, v, v);
+      else lab[v0 + v] = v0 + v;
+    }
+    __syncthreads();
+    const int a0 = off[v0], A = max(off[v1] - a0, 0);
+    auto link = [&](int x, int y) {
+      if (!in_lds) {
+        uf_link(lab, v0 + x, v0 + y);
+        return;
+      }
+      if (p16_get(P, x) == p16_get(P, y)) return;  // same parent: same set
+      int ru = p16_find(P, x), rv = p16_find(P, y);
+      while (ru != rv) {
+        const int h = ru > rv ? ru : rv, l = ru > rv ? rv : ru;
+        if (p16_cas(P, h, h, l)) return;
+        ru = p16_find(P, ru);
+        rv = p16_find(P, rv);
+      }
+    };
+    // plain (non-fence) tree edges
+    for (int v = tid; v < ng; v += GCC_THREADS) {
+      const int4 r = rec[v0 + v];
+      if (r.z >= v0 && r.z < v1 && r.w == 0) link(v, r.z - v0);
+    }
+    int big = -1;
+    if (in_lds) {
+      for (int r = 0; r < 2; ++r) {
+        for (int v = tid; v < ng; v += GCC_THREADS) {
+          const int b = min(max(off[v0 + v] - a0, 0), A), e = min(max(off[v0 + v + 1] - a0, b), A);
+          if (e > b) {
+            const int y = adj[a0 + b + (int)sample_pos(v0 + v, r, e - b)] - v0;
+            if (y != v && y >= 0 && y < ng && cross_edge(v0 + v, rec[v0 + v], v0 + y, rec[v0 + y])) link(v, y);
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < WAVE) {
+        const int r = p16_root(P, (int)((int64_t)tid * ng / WAVE));
+        int cnt = 0;
+        for (int j = 0; j < WAVE; ++j) cnt += __shfl(r, j, WAVE) == r ? 1 : 0;
+        int best_c = cnt, best_r = r;
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+          const int oc = __shfl_xor(best_c, o, WAVE), orr = __shfl_xor(best_r, o, WAVE);
+          if (oc > best_c || (oc == best_c && orr < best_r)) {
+            best_c = oc;
+            best_r = orr;
+          }
+        }
+        if (tid == 0) big_s = best_r;
+      }
+      __syncthreads();
+      big = big_s;
+    }
+    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;
+    const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
+    if (ab < ae) {
+      int lo = 0, hi = ng;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[v0 + mid] - a0 <= ab) lo = mid;
+        else hi = mid;
+      }
+      int x = lo, a = ab;
+      while (a < ae) {  // one row per step; the graph's last row ends at A >= ae
+        const int rend = min(max(off[v0 + x + 1] - a0, a), ae);
+        const bool skip = in_lds && rend > a && p16_find(P, x) == p16_find(P, big);
+        if (!skip && rend > a) {
+          const int4 rx = rec[v0 + x];
+          for (int c0 = a; c0 < rend; c0 += GCC_CHUNK) {
+            int tg[GCC_CHUNK];
+#pragma unroll
+            for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
+#pragma unroll
+            for (int k = 0; k < GCC_CHUNK; ++k) {
+              if (c0 + k >= rend) break;
+              const int y = tg[k];
+              if (y == x || y < 0 || y >= ng || (!in_lds && y < x)) continue;  // each edge once in memory mode
+              if (cross_edge(v0 + x, rx, v0 + y, rec[v0 + y])) link(x, y);
+            }
+          }
+        }
+        a = rend;
+        ++x;
+      }
+    }
+    __syncthreads();
+    if (in_lds)
+      for (int v = tid; v < ng; v += GCC_THREADS) lab[v0 + v] = v0 + p16_root(P, v);
+    __syncthreads();  // the next graph reuses P
+  }
 }
 
 template <bool PRIO>
@@ -2832,34 +2989,43 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
 
   // ---- Last-CC on the implicit skeleton
   int* lab = I(L.lab);
-  if (tune.lcc_prio) {
-    LAUNCH(c, k_lcc_tree_free<true>, gv, VB, rec, n, lab);
-    LAUNCH(c, k_lcc_tree<true>, gv, VB, rec, n, lab);
+  if (tune.graph_cc && G > 1 && vbegin != nullptr) {
+    LAUNCH(c, k_graph_lcc, (unsigned)(G < GCC_GRID ? G : GCC_GRID), GCC_THREADS, vbegin, G, n, off, adj,
+           (const int4*)rec, lab, scal + S_GRAPH_NEXT_LCC);
+    LAUNCH(c, k_flatten, gx, BLOCK, lab, n);  // graphs above the LDS size leave chains
+    LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
   } else {
-    LAUNCH(c, k_lcc_tree_free<false>, gv, VB, rec, n, lab);
-    LAUNCH(c, k_lcc_tree<false>, gv, VB, rec, n, lab);
-  }
-  // flattened before each sampling round; the frontier pass flattens the last state
-  const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
-  for (int r = 0; r < lcc_rounds; ++r) {
+    if (tune.lcc_prio) {
+      LAUNCH(c, k_lcc_tree_free<true>, gv, VB, rec, n, lab);
+      LAUNCH(c, k_lcc_tree<true>, gv, VB, rec, n, lab);
+    } else {
+      LAUNCH(c, k_lcc_tree_free<false>, gv, VB, rec, n, lab);
+      LAUNCH(c, k_lcc_tree<false>, gv, VB, rec, n, lab);
+    }
+    // flattened before each sampling round; the frontier pass flattens the last state
+    const int lcc_rounds = tune.lcc_rounds < 0 ? tune.sample_rounds : tune.lcc_rounds;
+    for (int r = 0; r < lcc_rounds; ++r) {
+      LAUNCH(c, k_compress, gx, BLOCK, lab, n);
+      if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gv, VB, off, adj, rec, n, r, lab);
+      else LAUNCH(c, k_lcc_sample<false>, gv, VB, off, adj, rec, n, r, lab);
+    }
+    LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
+    frontier(lab, S_BIG_LAB);
+    if (tune.lcc_prio)
+      LAUNCH(c, k_lcc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
+    else
+      LAUNCH(c, k_lcc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
     LAUNCH(c, k_compress, gx, BLOCK, lab, n);
-    if (tune.lcc_prio) LAUNCH(c, k_lcc_sample<true>, gv, VB, off, adj, rec, n, r, lab);
-    else LAUNCH(c, k_lcc_sample<false>, gv, VB, off, adj, rec, n, r, lab);
-  }
-  LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
-  frontier(lab, S_BIG_LAB);
-  if (tune.lcc_prio) LAUNCH(c, k_lcc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
-  else LAUNCH(c, k_lcc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, rec, lab);
-  LAUNCH(c, k_compress, gx, BLOCK, lab, n);
-  LAUNCH(c, k_flatten, gx, BLOCK, lab, n);  // the relabelling and the read-out read lab[v] as the label
-  if (tune.lcc_prio) {
-    int* minv = I(L.minid);  // refilled by the read-out
-    fill_i32(c, minv, INT32_MAX, n);
-    int* part = I(L.bsum);  // cdiv(n, BLOCK) + 1 slots, used again by the BCC count
-    LAUNCH(c, k_big_min_part, gn, BLOCK, lab, n, scal, part);
-    LAUNCH(c, k_big_min, 1, 1024, lab, part, (int)gn, scal);
-    LAUNCH(c, k_label_min, gn, BLOCK, lab, n, scal, minv);
-    LAUNCH(c, k_relabel, gn, BLOCK, lab, n, scal, minv);
+    LAUNCH(c, k_flatten, gx, BLOCK, lab, n);  // the relabelling and the read-out read lab[v] as the label
+    if (tune.lcc_prio) {
+      int* minv = I(L.minid);  // refilled by the read-out
+      fill_i32(c, minv, INT32_MAX, n);
+      int* part = I(L.bsum);  // cdiv(n, BLOCK) + 1 slots, used again by the BCC count
+      LAUNCH(c, k_big_min_part, gn, BLOCK, lab, n, scal, part);
+      LAUNCH(c, k_big_min, 1, 1024, lab, part, (int)gn, scal);
+      LAUNCH(c, k_label_min, gn, BLOCK, lab, n, scal, minv);
+      LAUNCH(c, k_relabel, gn, BLOCK, lab, n, scal, minv);
+    }
   }
 
   // ---- heads, articulation points, canonical labels
