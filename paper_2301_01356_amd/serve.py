@@ -60,11 +60,14 @@ class Completion:
 
 
 def serving_flags() -> int:
-    """Flags of the serving slots: the tuning fields shipped for mixed batches
-    (the 4096-graph batch's pick), under the general input contract."""
+    """Flags of the serving slots: the tuning fields shipped for a serving
+    slot's batch (a few requests of up to 2^22 vertices each, under the
+    general input contract).  The 4096-graph batch's pick does not carry
+    over: its per-graph union-find passes suit many small graphs, not a few
+    large ones."""
     from . import tune
 
-    return tune.shipped_entries()["batch4096"][0]
+    return tune.shipped_entries()["serve8"][0]
 
 
 def request_bytes(n: int, arcs: int) -> int:

@@ -201,7 +201,7 @@ def gpu_arch() -> str:
 # ------------------------------------------------------------ shipped table
 # Benchmark workloads whose tuned configurations ship in ``tuned_gfx950.json``.
 # Every generated input has ascending, loop-free rows, and the solve is told so.
-SHIP_WORKLOADS = ("rmat25", "grid", "plain", "batch4096", "knn2", "knn5", "knn10", "knn15", "knn20", "sqr_torus",
+SHIP_WORKLOADS = ("rmat25", "grid", "plain", "batch4096", "serve8", "knn2", "knn5", "knn10", "knn15", "knn20", "sqr_torus",
                   "rec_torus")
 
 
@@ -246,6 +246,31 @@ def workload_runner(name: str, device="cuda:0"):
             return e0.elapsed_time(e1)
 
         return cache_key(gpu_arch(), u.n, u.num_arcs, G, skew_class(np.diff(u.offsets))), run_batch
+    if name == "serve8":
+        # a serving slot's batch: 8 requests drawn as the serving stream draws
+        # them (n log-uniform in [2^10, 2^22], mean degree 4-32), solved under
+        # the general input contract as the slots solve them
+        from .api import solve_batched
+
+        u = gen.unite([gen.mixed(5, i, 1 << 10, 1 << 22, 4.0, 32.0) for i in range(8)])
+        G = len(u.vbegin) - 1
+        vb = torch.from_numpy(u.vbegin).to(dev)
+        off = torch.from_numpy(u.offsets32()).to(dev)
+        adj = torch.from_numpy(u.adj).to(dev)
+        ws = alloc_workspace(u.n, u.num_arcs, G, dev)
+        out = BccResult(torch.empty(u.num_arcs, dtype=torch.int32, device=dev),
+                        torch.empty(u.n, dtype=torch.uint8, device=dev), torch.empty(G, dtype=torch.int64, device=dev))
+        st = torch.cuda.current_stream(dev)
+
+        def run_serve(flags):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            solve_batched(vb, off, adj, out=out, workspace=ws, flags=flags, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            return e0.elapsed_time(e1)
+
+        return cache_key(gpu_arch(), u.n, u.num_arcs, G, skew_class(np.diff(u.offsets))), run_serve
     g = {"rmat25": gen.rmat, "grid": gen.grid, "plain": gen.plain}.get(name, lambda: gen.config(name))()
     off = torch.from_numpy(g.offsets if name == "rmat25" else g.offsets32()).to(dev)
     adj = torch.from_numpy(g.adj).to(dev)
