@@ -769,13 +769,14 @@ constexpr int LDD_HUGE_GRID = 1024;
 // word, so a path-halving store into the other half makes it retry and never
 // loses an update.  A larger graph runs the same loop on the device-memory
 // union-find.
-// Thread t takes the t-th of 1024 equal runs of the graph's arcs, finds the
-// row of its first arc by bisection over the row starts and walks the rows
-// from there, with a chunk of targets in flight (owning whole rows instead
-// leaves most threads idle on graphs of a few thousand vertices).
+// Thread t takes the t-th of 1024 equal runs of the graph's arcs and walks
+// the rows from the one holding its first arc (which the row pass records in
+// LDS), with a chunk of targets in flight (owning whole rows instead leaves
+// most threads idle on graphs of a few thousand vertices).
 constexpr int GCC_THREADS = 1024;
 constexpr int GCC_LDS_VERTICES = 1 << 16;
 constexpr int GCC_CHUNK = 8;
+constexpr int GCC_SB = 4;  // vertices per thread with their loads in flight together in the row pass
 constexpr int GCC_GRID = 1024;  // workgroups of the launch (more than one per compute unit waits)
 
 __device__ __forceinline__ int p16_get(const uint32_t* P, int x) {
@@ -818,14 +819,66 @@ __device__ __forceinline__ int p16_root(const uint32_t* P, int x) {
   return x;
 }
 
+// The per-graph passes take the graphs largest first: a workgroup that takes
+// a big graph near the end keeps running while the rest of the GPU idles
+// (claimed in index order, a mixed batch of 4096 graphs of 64-65536 vertices
+// would end about 1.6x after its mean load per compute unit; largest first,
+// within 1.1x).  One workgroup sorts the graphs into size classes by their
+// work (arcs plus twice the vertices; two classes per power of two): it
+// counts the classes, scans them from the largest down and scatters each
+// graph's index into its class's range.  The order within a class is
+// whatever the LDS atomics give; no result depends on which workgroup solves
+// which graph, or when.
+constexpr int GORDER_CLASSES = 128;
+constexpr int GORDER_THREADS = 1024;
+
+__device__ __forceinline__ int graph_size_class(const int* __restrict__ vbegin, int n, const int* __restrict__ off,
+                                                int g) {
+  const int v0 = min(max(vbegin[g], 0), n), v1 = min(max(vbegin[g + 1], v0), n);
+  const int64_t work = (int64_t)max(off[v1] - off[v0], 0) + 2 * (int64_t)(v1 - v0);
+  if (work == 0) return GORDER_CLASSES - 1;
+  const int bl = 64 - __clzll((unsigned long long)work);  // 1..34: arcs and vertices are below 2^31
+  const int half = bl >= 2 ? (int)((work >> (bl - 2)) & 1) : 0;
+  return GORDER_CLASSES - 1 - (2 * bl + half);  // larger work, smaller class (>= 58)
+}
+
+__global__ void __launch_bounds__(GORDER_THREADS) k_graph_order(const int* __restrict__ vbegin, int G, int n,
+                                                                const int* __restrict__ off, int* __restrict__ order) {
+  __shared__ int cls[GORDER_CLASSES];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < GORDER_CLASSES; i += GORDER_THREADS) cls[i] = 0;
+  __syncthreads();
+  for (int g = tid; g < G; g += GORDER_THREADS) atomicAdd(&cls[graph_size_class(vbegin, n, off, g)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int i = 0; i < GORDER_CLASSES; ++i) {
+      const int k = cls[i];
+      cls[i] = s;
+      s += k;
+    }
+  }
+  __syncthreads();
+  for (int g = tid; g < G; g += GORDER_THREADS) order[atomicAdd(&cls[graph_size_class(vbegin, n, off, g)], 1)] = g;
+}
+
+// The next graph of a per-graph pass: the i-th claim takes order[i] (index
+// order without an order).
+__device__ __forceinline__ int claim_graph(int* next_graph, const int* __restrict__ order, int G) {
+  const int i = atomicAdd(next_graph, 1);
+  return (order != nullptr && i < G) ? order[i] : i;
+}
+
 __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict__ vbegin, int G, int n,
                                                           const int* __restrict__ off, const int* __restrict__ adj,
-                                                          int* cc, int* hu, int* hv, int* next_graph) {
+                                                          int* cc, int* hu, int* hv, int* next_graph,
+                                                          const int* __restrict__ order) {
   __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
+  __shared__ int first_row[GCC_THREADS];  // the row holding each thread's first sweep arc
   __shared__ int g_s, big_s;
   const int tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) g_s = atomicAdd(next_graph, 1);
+    if (tid == 0) g_s = claim_graph(next_graph, order, G);
     __syncthreads();
     const int g = g_s;
     __syncthreads();  // everyone has read g_s before it is rewritten
@@ -840,6 +893,7 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     }
     __syncthreads();
     const int a0 = off[v0], A = max(off[v1] - a0, 0);
+    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;  // arcs of a sweep run
     // hook the sets of local x and y, keeping the hooking edge
     auto link16 = [&](int x, int y) {
       if (p16_get(P, x) == p16_get(P, y)) return;  // same parent: same set
@@ -855,19 +909,47 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
         rv = p16_find(P, rv);
       }
     };
-    int big = -1;  // sets rooted with big (sampled largest set) skip their rows below
-    if (in_lds) {
-      // two sampling rounds: every vertex links to one hashed neighbour
-      for (int r = 0; r < 2; ++r) {
-        for (int v = tid; v < ng; v += GCC_THREADS) {
-          const int b = min(max(off[v0 + v] - a0, 0), A), e = min(max(off[v0 + v + 1] - a0, b), A);
-          if (e > b) {
-            const int y = adj[a0 + b + (int)sample_pos(v0 + v, r, e - b)] - v0;
-            if (y != v && y >= 0 && y < ng) link16(v, y);
+    // One pass over the rows: each row names itself the first row of the
+    // sweep runs that start inside it, and (parents in LDS) each vertex links
+    // to two hashed neighbours -- the two sampling rounds, taken together (no
+    // link order changes the sets).  GCC_SB vertices per thread at a time,
+    // all their loads in flight before the first link.
+    for (int base = 0; base < ng; base += GCC_THREADS * GCC_SB) {
+      int rb[GCC_SB], re[GCC_SB], ys[GCC_SB][2];
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid;
+        rb[j] = re[j] = 0;
+        if (v < ng) {
+          rb[j] = min(max(off[v0 + v] - a0, 0), A);
+          re[j] = min(max(off[v0 + v + 1] - a0, rb[j]), A);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
+        ys[j][0] = ys[j][1] = -1;
+        if (d > 0) {
+          for (int64_t t = (rb[j] + per - 1) / per; t * per < re[j] && t < GCC_THREADS; ++t) first_row[t] = v;
+          if (in_lds) {
+            ys[j][0] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0;
+            ys[j][1] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0;
           }
         }
-        __syncthreads();
       }
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int y = ys[j][r];
+          if (y != v && y >= 0 && y < ng) link16(v, y);  // -1 unless sampled
+        }
+      }
+    }
+    __syncthreads();
+    int big = -1;  // sets rooted with big (sampled largest set) skip their rows below
+    if (in_lds) {
       // the set most of 64 evenly spread vertices fall in
       if (tid < WAVE) {
         const int r = p16_root(P, (int)((int64_t)tid * ng / WAVE));
@@ -888,16 +970,9 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     }
     // the sweep: every arc of every row outside the big set (an edge between
     // two rows that are both skipped lies inside the big set already)
-    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;
     const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
     if (ab < ae) {
-      int lo = 0, hi = ng;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[v0 + mid] - a0 <= ab) lo = mid;
-        else hi = mid;
-      }
-      int x = lo, a = ab;
+      int x = min(max(first_row[tid], 0), ng - 1), a = ab;
       while (a < ae) {  // one row per step; the graph's last row ends at A >= ae
         const int rend = min(max(off[v0 + x + 1] - a0, a), ae);
         const bool skip = in_lds && rend > a && p16_find(P, x) == p16_find(P, big);
@@ -923,7 +998,7 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     __syncthreads();
     if (in_lds)
       for (int v = tid; v < ng; v += GCC_THREADS) cc[v0 + v] = v0 + p16_root(P, v);
-    __syncthreads();  // the next graph reuses P
+    __syncthreads();  // the next graph reuses P and first_row
   }
 }
 
@@ -1719,21 +1794,23 @@ __device__ __forceinline__ bool cross_edge(int x, int4 rx, int y, int4 ry) {
 }
 
 // Last-CC per graph of a batch (FASTBCC_TUNE_GRAPH_CC): the union-find of
-// k_graph_cc on the skeleton instead of the graph -- plain tree edges first,
-// then cross edges (InSkeleton: neither endpoint an ancestor of the other) --
+// k_graph_cc on the skeleton instead of the graph -- plain tree edges and
+// cross edges (InSkeleton: neither endpoint an ancestor of the other) --
 // hooked by id, so each set's root is its smallest member, as the read-out
-// needs.  Two sampling rounds link each vertex to the neighbour at a hashed
-// position of its row when that edge is a cross edge; the sweep then reads
-// every arc of the rows outside the sampled largest set.  Graphs above the
+// needs.  The row pass links each vertex's plain tree edge and, of the two
+// neighbours at hashed positions of its row, those across cross edges; the
+// sweep then reads every arc of the rows outside the sampled largest set.  Graphs above the
 // LDS size run on the device-memory union-find (flattened afterwards).
 __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict__ vbegin, int G, int n,
                                                            const int* __restrict__ off, const int* __restrict__ adj,
-                                                           const int4* __restrict__ rec, int* lab, int* next_graph) {
+                                                           const int4* __restrict__ rec, int* lab, int* next_graph,
+                                                           const int* __restrict__ order) {
   __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
+  __shared__ int first_row[GCC_THREADS];  // the row holding each thread's first sweep arc
   __shared__ int g_s, big_s;
   const int tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) g_s = atomicAdd(next_graph, 1);
+    if (tid == 0) g_s = claim_graph(next_graph, order, G);
     __syncthreads();
     const int g = g_s;
     __syncthreads();  // everyone has read g_s before it is rewritten
@@ -1747,6 +1824,7 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
     }
     __syncthreads();
     const int a0 = off[v0], A = max(off[v1] - a0, 0);
+    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;  // arcs of a sweep run
     auto link = [&](int x, int y) {
       if (!in_lds) {
         uf_link(lab, v0 + x, v0 + y);
@@ -1761,23 +1839,60 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
         rv = p16_find(P, rv);
       }
     };
-    // plain (non-fence) tree edges
-    for (int v = tid; v < ng; v += GCC_THREADS) {
-      const int4 r = rec[v0 + v];
-      if (r.z >= v0 && r.z < v1 && r.w == 0) link(v, r.z - v0);
-    }
-    int big = -1;
-    if (in_lds) {
-      for (int r = 0; r < 2; ++r) {
-        for (int v = tid; v < ng; v += GCC_THREADS) {
-          const int b = min(max(off[v0 + v] - a0, 0), A), e = min(max(off[v0 + v + 1] - a0, b), A);
-          if (e > b) {
-            const int y = adj[a0 + b + (int)sample_pos(v0 + v, r, e - b)] - v0;
-            if (y != v && y >= 0 && y < ng && cross_edge(v0 + v, rec[v0 + v], v0 + y, rec[v0 + y])) link(v, y);
+    // One pass over the rows, as in k_graph_cc: the sweep's first rows, each
+    // vertex's plain tree edge and (parents in LDS) its two sampled cross
+    // edges, GCC_SB vertices per thread with their loads in flight together.
+    for (int base = 0; base < ng; base += GCC_THREADS * GCC_SB) {
+      int rb[GCC_SB], re[GCC_SB], ys[GCC_SB][2];
+      int4 rv[GCC_SB];
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid;
+        rb[j] = re[j] = 0;
+        rv[j] = make_int4(0, -1, -1, 1);  // no tree edge
+        if (v < ng) {
+          rv[j] = rec[v0 + v];
+          rb[j] = min(max(off[v0 + v] - a0, 0), A);
+          re[j] = min(max(off[v0 + v + 1] - a0, rb[j]), A);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
+        ys[j][0] = ys[j][1] = -1;
+        if (d > 0) {
+          for (int64_t t = (rb[j] + per - 1) / per; t * per < re[j] && t < GCC_THREADS; ++t) first_row[t] = v;
+          if (in_lds) {
+            ys[j][0] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0;
+            ys[j][1] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0;
           }
         }
       }
-      __syncthreads();
+      int4 ry[GCC_SB][2];
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int y = ys[j][r];
+          const bool want = y != v && y >= 0 && y < ng;
+          ys[j][r] = want ? y : -1;
+          ry[j][r] = want ? rec[v0 + y] : make_int4(0, -1, -1, 0);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid;
+        const int4 r = rv[j];
+        if (r.z >= v0 && r.z < v1 && r.w == 0) link(v, r.z - v0);  // plain tree edge
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          if (ys[j][k] >= 0 && cross_edge(v0 + v, r, v0 + ys[j][k], ry[j][k])) link(v, ys[j][k]);
+      }
+    }
+    __syncthreads();
+    int big = -1;
+    if (in_lds) {
       if (tid < WAVE) {
         const int r = p16_root(P, (int)((int64_t)tid * ng / WAVE));
         int cnt = 0;
@@ -1795,16 +1910,9 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
       __syncthreads();
       big = big_s;
     }
-    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;
     const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
     if (ab < ae) {
-      int lo = 0, hi = ng;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[v0 + mid] - a0 <= ab) lo = mid;
-        else hi = mid;
-      }
-      int x = lo, a = ab;
+      int x = min(max(first_row[tid], 0), ng - 1), a = ab;
       while (a < ae) {  // one row per step; the graph's last row ends at A >= ae
         const int rend = min(max(off[v0 + x + 1] - a0, a), ae);
         const bool skip = in_lds && rend > a && p16_find(P, x) == p16_find(P, big);
@@ -1814,13 +1922,19 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
             int tg[GCC_CHUNK];
 #pragma unroll
             for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
+            // the chunk's target records are all in flight before the first link
+            int4 ry[GCC_CHUNK];
 #pragma unroll
             for (int k = 0; k < GCC_CHUNK; ++k) {
-              if (c0 + k >= rend) break;
               const int y = tg[k];
-              if (y == x || y < 0 || y >= ng || (!in_lds && y < x)) continue;  // each edge once in memory mode
-              if (cross_edge(v0 + x, rx, v0 + y, rec[v0 + y])) link(x, y);
+              // each edge once in memory mode
+              const bool want = y != x && y >= 0 && y < ng && (in_lds || y > x);
+              tg[k] = want ? y : -1;
+              ry[k] = want ? rec[v0 + y] : make_int4(0, -1, -1, 0);
             }
+#pragma unroll
+            for (int k = 0; k < GCC_CHUNK; ++k)
+              if (tg[k] >= 0 && cross_edge(v0 + x, rx, v0 + tg[k], ry[k])) link(x, tg[k]);
           }
         }
         a = rend;
@@ -1830,7 +1944,7 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
     __syncthreads();
     if (in_lds)
       for (int v = tid; v < ng; v += GCC_THREADS) lab[v0 + v] = v0 + p16_root(P, v);
-    __syncthreads();  // the next graph reuses P
+    __syncthreads();  // the next graph reuses P and first_row
   }
 }
 
@@ -2844,9 +2958,13 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
 
   // ---- First-CC (spanning forest)
+  // the per-graph passes' largest-first order (the read-out's root labels are
+  // free until then; a batch of more graphs than vertices keeps index order)
+  int* gorder = (tune.graph_cc && G > 1 && vbegin != nullptr && G <= n) ? I(L.rootlab) : nullptr;
+  if (gorder) LAUNCH(c, k_graph_order, 1, GORDER_THREADS, vbegin, G, n, off, gorder);
   if (tune.graph_cc && G > 1 && vbegin != nullptr) {
     LAUNCH(c, k_graph_cc, (unsigned)(G < GCC_GRID ? G : GCC_GRID), GCC_THREADS, vbegin, G, n, off, adj, cc, hu, hv,
-           scal + S_GRAPH_NEXT);
+           scal + S_GRAPH_NEXT, (const int*)gorder);
   } else {
     if (tune.ldd) {
       int* rnd = I(L.su);  // the tree-slot array is free until Rooting
@@ -2991,7 +3109,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int* lab = I(L.lab);
   if (tune.graph_cc && G > 1 && vbegin != nullptr) {
     LAUNCH(c, k_graph_lcc, (unsigned)(G < GCC_GRID ? G : GCC_GRID), GCC_THREADS, vbegin, G, n, off, adj,
-           (const int4*)rec, lab, scal + S_GRAPH_NEXT_LCC);
+           (const int4*)rec, lab, scal + S_GRAPH_NEXT_LCC, (const int*)gorder);
     LAUNCH(c, k_flatten, gx, BLOCK, lab, n);  // graphs above the LDS size leave chains
     LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, lab, n, scal + S_BIG_LAB);
   } else {

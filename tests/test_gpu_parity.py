@@ -636,3 +636,25 @@ def test_batched_per_graph_first_cc_sizes(flags):
     for i, g in enumerate(graphs):
         a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
         assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} (n={g.n})")
+
+
+@pytest.mark.parametrize("flags", [N.tune_flags(graph_cc=True),
+                                   N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.tune_flags(graph_cc=True)])
+def test_batched_per_graph_more_graphs_than_vertices(flags):
+    """The per-graph passes take the graphs largest first when the batch has
+    at most as many graphs as vertices, else in index order: a batch of
+    mostly empty graphs (more graphs than vertices) around a few small ones."""
+    empty = gen.Csr(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    small = [gen.from_edges(4, cycle(4)), gen.from_edges(3, path(3)), gen.family("random", 9, 2.0, seed=3)]
+    graphs = [empty] * 7 + [small[0]] + [empty] * 11 + [small[1], small[2]] + [empty] * 5
+    u = gen.unite(graphs)
+    assert len(graphs) > u.n
+    note(f"per-graph passes, {len(graphs)} graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    r = solve_batched(vb, off, adj, flags=flags)
+    torch.cuda.synchronize()
+    lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for i, g in enumerate(graphs):
+        a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+        assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} (n={g.n})")
