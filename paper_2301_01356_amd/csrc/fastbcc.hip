@@ -114,7 +114,7 @@ inline int ilog2_floor(int64_t x) {
 // ------------------------------------------------------------ workspace
 struct Layout {
   size_t total = 0;
-  size_t scalars, off32, cc, hu, hv, toff, su, sv, tadj, twin, rootidx, roots, next, ol, ol2, rnext2, rlen2, rlen,
+  size_t scalars, off32, cc, hook, toff, su, sv, tadj, twin, rootidx, roots, next, ol, ol2, rnext2, rlen2, rlen,
       rnext, rval0,
       rval1, rnx0, rnx1, pos, eflag, first, w1, w2, W, pre, suf, tab, rec, lab, head,
       rootlab, minid, canon, bsum, heads, foff, frank, frow, fstart, ftile, hubidx, shard, bigbits, dbits, tile_row, scan_tmp;
@@ -147,8 +147,7 @@ Layout make_layout(int64_t n, int64_t A) {
   L.scalars = take(c, S_COUNT * I);
   L.off32 = take(c, n1 * I);
   L.cc = take(c, n * I);
-  L.hu = take(c, n * I);
-  L.hv = take(c, n * I);
+  L.hook = take(c, n * sizeof(int2));  // First-CC's hooking edge per vertex (x < 0: none)
   L.toff = take(c, n1 * I);
   L.su = take(c, n * I);
   L.sv = take(c, n * I);
@@ -652,11 +651,11 @@ __global__ void k_validate_arcs(const int* __restrict__ off, const int* __restri
 }
 
 // ------------------------------------------------------------ First-CC
-__global__ void k_cc_init(int* __restrict__ cc, int* __restrict__ hu, int n) {
+__global__ void k_cc_init(int* __restrict__ cc, int2* __restrict__ hook, int n) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   cc[v] = v;
-  hu[v] = -1;
+  hook[v] = make_int2(-1, -1);
 }
 
 // Position of the neighbour a vertex samples in round r: a hash of (v, r)
@@ -673,21 +672,21 @@ __device__ __forceinline__ int64_t sample_pos(int v, int r, int64_t deg) {
 }
 
 template <bool PRIO>
-__device__ __forceinline__ void cc_link(int* cc, int u, int v, int* hu, int* hv) {
-  if (PRIO) uf_link_record_prio(cc, u, v, hu, hv);
-  else uf_link_record(cc, u, v, hu, hv);
+__device__ __forceinline__ void cc_link(int* cc, int u, int v, int2* hook) {
+  if (PRIO) uf_link_record_prio(cc, u, v, hook);
+  else uf_link_record(cc, u, v, hook);
 }
 
 // Sampling round r: every vertex links to one hashed neighbour.
 template <bool PRIO>
 __global__ void k_cc_sample(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int* cc,
-                            int* hu, int* hv) {
+                            int2* hook) {
   int v = vertex_index();
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
   if (e > b) {
     int w = adj[b + sample_pos(v, r, e - b)];
-    if (w != v) cc_link<PRIO>(cc, v, w, hu, hv);
+    if (w != v) cc_link<PRIO>(cc, v, w, hook);
   }
 }
 
@@ -704,7 +703,7 @@ __device__ __forceinline__ bool ranks_above(int w, int v) {
 
 template <bool PRIO>
 __global__ void k_cc_first_round(const int* __restrict__ off, const int* __restrict__ adj, int n, int* cc,
-                                 int* __restrict__ hu, int* __restrict__ hv) {
+                                 int2* __restrict__ hook) {
   int v = vertex_index();
   if (v >= n) return;
   const int64_t b = off[v], e = off[v + 1];
@@ -717,8 +716,7 @@ __global__ void k_cc_first_round(const int* __restrict__ off, const int* __restr
   }
   // this pass also initialises every set (cc[v] = v, no hook edge)
   cc[v] = w;
-  hu[v] = w == v ? -1 : v;
-  hv[v] = w;
+  hook[v] = make_int2(w == v ? -1 : v, w);
 }
 
 // Full sweep over the frontier: rows whose set is the sampled largest one
@@ -727,7 +725,7 @@ __global__ void k_cc_first_round(const int* __restrict__ off, const int* __restr
 template <bool PRIO>
 __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ frow, const int* __restrict__ fstart,
                            const int* __restrict__ adj, const int* __restrict__ frows, const int* __restrict__ ftile,
-                           int tw, int* cc, int* hu, int* hv) {
+                           int tw, int* cc, int2* hook) {
   const int R = *frows;
   const int64_t F = fstart[R];
   arc_tiles(fstart, R, F, ftile, tw, [&](int64_t k, int i, bool ok) {
@@ -735,7 +733,7 @@ __global__ void k_cc_sweep(const int* __restrict__ off, const int* __restrict__ 
     const int x = frow[i];
     const int64_t a = (int64_t)off[x] + (k - (int64_t)fstart[i]);
     const int w = adj[a];
-    if (w != x) cc_link<PRIO>(cc, x, w, hu, hv);
+    if (w != x) cc_link<PRIO>(cc, x, w, hook);
   });
 }
 
@@ -769,10 +767,10 @@ constexpr int LDD_HUGE_GRID = 1024;
 // word, so a path-halving store into the other half makes it retry and never
 // loses an update.  A larger graph runs the same loop on the device-memory
 // union-find.
-// Thread t takes the t-th of 1024 equal runs of the graph's arcs and walks
-// the rows from the one holding its first arc (which the row pass records in
-// LDS), with a chunk of targets in flight (owning whole rows instead leaves
-// most threads idle on graphs of a few thousand vertices).
+// Two sampling rounds link each vertex to the neighbours at two hashed
+// positions of its row; the sweep then gives thread t the rows t, t + 1024,
+// ..., tests each row's set in LDS and reads only the rows outside the
+// sampled largest set, a chunk of targets in flight.
 constexpr int GCC_THREADS = 1024;
 constexpr int GCC_LDS_VERTICES = 1 << 16;
 constexpr int GCC_CHUNK = 8;
@@ -871,10 +869,9 @@ __device__ __forceinline__ int claim_graph(int* next_graph, const int* __restric
 
 __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict__ vbegin, int G, int n,
                                                           const int* __restrict__ off, const int* __restrict__ adj,
-                                                          int* cc, int* hu, int* hv, int* next_graph,
+                                                          int* cc, int2* hook, int* next_graph,
                                                           const int* __restrict__ order) {
   __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
-  __shared__ int first_row[GCC_THREADS];  // the row holding each thread's first sweep arc
   __shared__ int g_s, big_s;
   const int tid = threadIdx.x;
   for (;;) {
@@ -887,13 +884,12 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     if (ng == 0) continue;
     const bool in_lds = ng <= GCC_LDS_VERTICES;
     for (int v = tid; v < ng; v += GCC_THREADS) {
-      hu[v0 + v] = -1;
+      hook[v0 + v] = make_int2(-1, -1);
       if (in_lds) p16_set(P, v, v);
       else cc[v0 + v] = v0 + v;
     }
     __syncthreads();
     const int a0 = off[v0], A = max(off[v1] - a0, 0);
-    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;  // arcs of a sweep run
     // hook the sets of local x and y, keeping the hooking edge
     auto link16 = [&](int x, int y) {
       if (p16_get(P, x) == p16_get(P, y)) return;  // same parent: same set
@@ -901,40 +897,35 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
       while (ru != rv) {
         const int h = ru > rv ? ru : rv, l = ru > rv ? rv : ru;
         if (p16_cas(P, h, h, l)) {
-          hu[v0 + h] = v0 + x;
-          hv[v0 + h] = v0 + y;
+          hook[v0 + h] = make_int2(v0 + x, v0 + y);
           return;
         }
         ru = p16_find(P, ru);
         rv = p16_find(P, rv);
       }
     };
-    // One pass over the rows: each row names itself the first row of the
-    // sweep runs that start inside it, and (parents in LDS) each vertex links
-    // to two hashed neighbours -- the two sampling rounds, taken together (no
-    // link order changes the sets).  GCC_SB vertices per thread at a time,
-    // all their loads in flight before the first link.
-    for (int base = 0; base < ng; base += GCC_THREADS * GCC_SB) {
-      int rb[GCC_SB], re[GCC_SB], ys[GCC_SB][2];
+    // The sampling rounds (parents in LDS): each vertex links to two hashed
+    // neighbours, both rounds taken together (no link order changes the
+    // sets), GCC_SB vertices per thread with all their loads in flight before
+    // the first link.
+    for (int base = 0; in_lds && base < ng; base += GCC_THREADS * GCC_SB) {
+      int ys[GCC_SB][2];
+      {
+        int rb[GCC_SB], re[GCC_SB];
 #pragma unroll
-      for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid;
-        rb[j] = re[j] = 0;
-        if (v < ng) {
-          rb[j] = min(max(off[v0 + v] - a0, 0), A);
-          re[j] = min(max(off[v0 + v + 1] - a0, rb[j]), A);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
-        ys[j][0] = ys[j][1] = -1;
-        if (d > 0) {
-          for (int64_t t = (rb[j] + per - 1) / per; t * per < re[j] && t < GCC_THREADS; ++t) first_row[t] = v;
-          if (in_lds) {
-            ys[j][0] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0;
-            ys[j][1] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0;
+        for (int j = 0; j < GCC_SB; ++j) {
+          const int v = base + j * GCC_THREADS + tid;
+          rb[j] = re[j] = 0;
+          if (v < ng) {
+            rb[j] = min(max(off[v0 + v] - a0, 0), A);
+            re[j] = min(max(off[v0 + v + 1] - a0, rb[j]), A);
           }
+        }
+#pragma unroll
+        for (int j = 0; j < GCC_SB; ++j) {
+          const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
+          ys[j][0] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0 : -1;
+          ys[j][1] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0 : -1;
         }
       }
 #pragma unroll
@@ -969,36 +960,30 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
       big = big_s;
     }
     // the sweep: every arc of every row outside the big set (an edge between
-    // two rows that are both skipped lies inside the big set already)
-    const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
-    if (ab < ae) {
-      int x = min(max(first_row[tid], 0), ng - 1), a = ab;
-      while (a < ae) {  // one row per step; the graph's last row ends at A >= ae
-        const int rend = min(max(off[v0 + x + 1] - a0, a), ae);
-        const bool skip = in_lds && rend > a && p16_find(P, x) == p16_find(P, big);
-        if (!skip) {
-          for (int c0 = a; c0 < rend; c0 += GCC_CHUNK) {
-            int tg[GCC_CHUNK];
+    // two rows that are both skipped lies inside the big set already); rows
+    // are tested in LDS, so the skipped ones (most, once sampling found the
+    // big set) cost no global load
+    for (int x = tid; x < ng; x += GCC_THREADS) {
+      if (in_lds && p16_find(P, x) == p16_find(P, big)) continue;
+      const int rb = min(max(off[v0 + x] - a0, 0), A), rend = min(max(off[v0 + x + 1] - a0, rb), A);
+      for (int c0 = rb; c0 < rend; c0 += GCC_CHUNK) {
+        int tg[GCC_CHUNK];
 #pragma unroll
-            for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
+        for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
 #pragma unroll
-            for (int k = 0; k < GCC_CHUNK; ++k) {
-              if (c0 + k >= rend) break;
-              const int y = tg[k];
-              if (y == x || y < 0 || y >= ng) continue;  // self-loops and foreign ids skipped
-              if (in_lds) link16(x, y);
-              else if (y > x) uf_link_record(cc, v0 + x, v0 + y, hu, hv);  // each edge once
-            }
-          }
+        for (int k = 0; k < GCC_CHUNK; ++k) {
+          if (c0 + k >= rend) break;
+          const int y = tg[k];
+          if (y == x || y < 0 || y >= ng) continue;  // self-loops and foreign ids skipped
+          if (in_lds) link16(x, y);
+          else if (y > x) uf_link_record(cc, v0 + x, v0 + y, hook);  // each edge once
         }
-        a = rend;
-        ++x;
       }
     }
     __syncthreads();
     if (in_lds)
       for (int v = tid; v < ng; v += GCC_THREADS) cc[v0 + v] = v0 + p16_root(P, v);
-    __syncthreads();  // the next graph reuses P and first_row
+    __syncthreads();  // the next graph reuses P
   }
 }
 
@@ -1015,19 +1000,18 @@ __device__ __forceinline__ int ldd_start(int v, int T0, float inv_beta) {
   return s < 0 ? 0 : s;
 }
 
-__global__ void k_ldd_init(int* __restrict__ cc, int* __restrict__ hu, int* __restrict__ rnd, int n, int* scal) {
+__global__ void k_ldd_init(int* __restrict__ cc, int2* __restrict__ hook, int* __restrict__ rnd, int n, int* scal) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v == 0) scal[S_LDD_HUGE] = scal[S_LDD_HUGE + 1] = 0;
   if (v >= n) return;
   cc[v] = -1;
-  hu[v] = -1;
+  hook[v] = make_int2(-1, -1);
   rnd[v] = -1;
 }
 
-__device__ __forceinline__ bool ldd_claim(int* cc, int* rnd, int* hu, int* hv, int u, int cu, int w, int r) {
+__device__ __forceinline__ bool ldd_claim(int* cc, int* rnd, int2* hook, int u, int cu, int w, int r) {
   if (ld_relaxed(cc + w) != -1 || atomicCAS(cc + w, -1, cu) != -1) return false;
-  hu[w] = u;
-  hv[w] = w;
+  hook[w] = make_int2(u, w);
   rnd[w] = r + 1;  // expands next round (unless expanded at once)
   return true;
 }
@@ -1041,7 +1025,7 @@ __device__ __forceinline__ bool ldd_claim(int* cc, int* rnd, int* hu, int* hv, i
 // arcs takes ceil(d / LDD_CHUNK) < 2d / LDD_CHUNK entries, so all rows together
 // need fewer than 2A / LDD_CHUNK.
 __global__ void k_ldd_round(const int* __restrict__ off, const int* __restrict__ adj, int n, int r, int T0,
-                            float inv_beta, int* cc, int* rnd, int* __restrict__ hu, int* __restrict__ hv,
+                            float inv_beta, int* cc, int* rnd, int2* __restrict__ hook,
                             int2* __restrict__ queue, int* scal) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v == 0) scal[S_LDD_HUGE + ((r + 1) & 1)] = 0;
@@ -1065,13 +1049,13 @@ __global__ void k_ldd_round(const int* __restrict__ off, const int* __restrict__
   if (active && e - b <= LDD_SMALL) {
     for (int a = b; a < e; ++a) {
       const int w = adj[a];
-      if (w == v || !ldd_claim(cc, rnd, hu, hv, v, cv, w, r)) continue;
+      if (w == v || !ldd_claim(cc, rnd, hook, v, cv, w, r)) continue;
       const int wb = off[w], we = off[w + 1];
       if (we - wb > LDD_SMALL) continue;
       rnd[w] = -2;  // expanded here
       for (int k = wb; k < we; ++k) {
         const int x = adj[k];
-        if (x != w) ldd_claim(cc, rnd, hu, hv, w, cv, x, r);
+        if (x != w) ldd_claim(cc, rnd, hook, w, cv, x, r);
       }
     }
   }
@@ -1083,15 +1067,15 @@ __global__ void k_ldd_round(const int* __restrict__ off, const int* __restrict__
     const int ub = __shfl(b, j, WAVE), ue = __shfl(e, j, WAVE);
     for (int a = ub + lane_id(); a < ue; a += WAVE) {
       const int w = adj[a];
-      if (w != u) ldd_claim(cc, rnd, hu, hv, u, cu, w, r);
+      if (w != u) ldd_claim(cc, rnd, hook, u, cu, w, r);
     }
   }
 }
 
 // The queued chunks of round r, one wave per chunk.
 __global__ void k_ldd_huge(const int* __restrict__ off, const int* __restrict__ adj, int r,
-                           const int2* __restrict__ queue, const int* scal, int* cc, int* rnd, int* __restrict__ hu,
-                           int* __restrict__ hv) {
+                           const int2* __restrict__ queue, const int* scal, int* cc, int* rnd,
+                           int2* __restrict__ hook) {
   const int count = scal[S_LDD_HUGE + (r & 1)];
   const int waves = gridDim.x * (blockDim.x / WAVE);
   for (int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; i < count; i += waves) {
@@ -1101,7 +1085,7 @@ __global__ void k_ldd_huge(const int* __restrict__ off, const int* __restrict__ 
     const int64_t end = (int64_t)q.y + LDD_CHUNK < e ? (int64_t)q.y + LDD_CHUNK : e;
     for (int64_t a = q.y + lane_id(); a < end; a += WAVE) {
       const int w = adj[a];
-      if (w != u) ldd_claim(cc, rnd, hu, hv, u, cu, w, r);
+      if (w != u) ldd_claim(cc, rnd, hook, u, cu, w, r);
     }
   }
 }
@@ -1120,24 +1104,26 @@ __device__ __forceinline__ bool is_hub(const int* __restrict__ off, int x) { ret
 // Per vertex, first pass of Rooting: edge flag for the dense numbering,
 // First-CC's sets flattened, the out-list head cleared, hubs numbered (in any
 // order: the number only picks the hub's counters).
-__global__ void k_edge_flags(const int* __restrict__ off, const int* __restrict__ hu, int n, int* cc,
+__global__ void k_edge_flags(const int* __restrict__ off, const int2* __restrict__ hook, int n, int* cc,
                              int* __restrict__ eid, int* __restrict__ headp, int* __restrict__ hubidx, int* scal) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= n) return;
-  eid[h] = hu[h] >= 0 ? 1 : 0;
+  eid[h] = hook[h].x >= 0 ? 1 : 0;
   const int r = uf_find(cc, h);
   if (ld_relaxed(cc + h) != r) st_relaxed(cc + h, r);
   headp[h] = -1;
   if (is_hub(off, h)) hubidx[h] = atomicAdd(scal + S_HUBS, 1);
 }
 
-__global__ void k_edge_compact(const int* __restrict__ hu, const int* __restrict__ hv, const int* __restrict__ eid,
-                               int n, int* __restrict__ eu, int* __restrict__ ev) {
+__global__ void k_edge_compact(const int2* __restrict__ hook, const int* __restrict__ eid, int n,
+                               int* __restrict__ eu, int* __restrict__ ev) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= n || hu[h] < 0) return;
+  if (h >= n) return;
+  const int2 r = hook[h];
+  if (r.x < 0) return;
   const int e = eid[h];
-  eu[e] = hu[h];
-  ev[e] = hv[h];
+  eu[e] = r.x;
+  ev[e] = r.y;
 }
 
 __device__ __forceinline__ int arc_src(const int* __restrict__ eu, const int* __restrict__ ev, int a) {
@@ -1806,7 +1792,6 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
                                                            const int4* __restrict__ rec, int* lab, int* next_graph,
                                                            const int* __restrict__ order) {
   __shared__ uint32_t P[GCC_LDS_VERTICES / 2];
-  __shared__ int first_row[GCC_THREADS];  // the row holding each thread's first sweep arc
   __shared__ int g_s, big_s;
   const int tid = threadIdx.x;
   for (;;) {
@@ -1824,7 +1809,6 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
     }
     __syncthreads();
     const int a0 = off[v0], A = max(off[v1] - a0, 0);
-    const int64_t per = ((int64_t)A + GCC_THREADS - 1) / GCC_THREADS;  // arcs of a sweep run
     auto link = [&](int x, int y) {
       if (!in_lds) {
         uf_link(lab, v0 + x, v0 + y);
@@ -1839,9 +1823,9 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
         rv = p16_find(P, rv);
       }
     };
-    // One pass over the rows, as in k_graph_cc: the sweep's first rows, each
-    // vertex's plain tree edge and (parents in LDS) its two sampled cross
-    // edges, GCC_SB vertices per thread with their loads in flight together.
+    // One pass over the rows: each vertex's plain tree edge and (parents in
+    // LDS) its two sampled cross edges, GCC_SB vertices per thread with their
+    // loads in flight together.
     for (int base = 0; base < ng; base += GCC_THREADS * GCC_SB) {
       int rb[GCC_SB], re[GCC_SB], ys[GCC_SB][2];
       int4 rv[GCC_SB];
@@ -1861,7 +1845,6 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
         const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
         ys[j][0] = ys[j][1] = -1;
         if (d > 0) {
-          for (int64_t t = (rb[j] + per - 1) / per; t * per < re[j] && t < GCC_THREADS; ++t) first_row[t] = v;
           if (in_lds) {
             ys[j][0] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0;
             ys[j][1] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0;
@@ -1910,41 +1893,34 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
       __syncthreads();
       big = big_s;
     }
-    const int ab = (int)min((int64_t)tid * per, (int64_t)A), ae = (int)min((int64_t)ab + per, (int64_t)A);
-    if (ab < ae) {
-      int x = min(max(first_row[tid], 0), ng - 1), a = ab;
-      while (a < ae) {  // one row per step; the graph's last row ends at A >= ae
-        const int rend = min(max(off[v0 + x + 1] - a0, a), ae);
-        const bool skip = in_lds && rend > a && p16_find(P, x) == p16_find(P, big);
-        if (!skip && rend > a) {
-          const int4 rx = rec[v0 + x];
-          for (int c0 = a; c0 < rend; c0 += GCC_CHUNK) {
-            int tg[GCC_CHUNK];
+    for (int x = tid; x < ng; x += GCC_THREADS) {
+      if (in_lds && p16_find(P, x) == p16_find(P, big)) continue;
+      const int rb = min(max(off[v0 + x] - a0, 0), A), rend = min(max(off[v0 + x + 1] - a0, rb), A);
+      if (rend == rb) continue;
+      const int4 rx = rec[v0 + x];
+      for (int c0 = rb; c0 < rend; c0 += GCC_CHUNK) {
+        int tg[GCC_CHUNK];
 #pragma unroll
-            for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
-            // the chunk's target records are all in flight before the first link
-            int4 ry[GCC_CHUNK];
+        for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
+        // the chunk's target records are all in flight before the first link
+        int4 ry[GCC_CHUNK];
 #pragma unroll
-            for (int k = 0; k < GCC_CHUNK; ++k) {
-              const int y = tg[k];
-              // each edge once in memory mode
-              const bool want = y != x && y >= 0 && y < ng && (in_lds || y > x);
-              tg[k] = want ? y : -1;
-              ry[k] = want ? rec[v0 + y] : make_int4(0, -1, -1, 0);
-            }
-#pragma unroll
-            for (int k = 0; k < GCC_CHUNK; ++k)
-              if (tg[k] >= 0 && cross_edge(v0 + x, rx, v0 + tg[k], ry[k])) link(x, tg[k]);
-          }
+        for (int k = 0; k < GCC_CHUNK; ++k) {
+          const int y = tg[k];
+          // each edge once in memory mode
+          const bool want = y != x && y >= 0 && y < ng && (in_lds || y > x);
+          tg[k] = want ? y : -1;
+          ry[k] = want ? rec[v0 + y] : make_int4(0, -1, -1, 0);
         }
-        a = rend;
-        ++x;
+#pragma unroll
+        for (int k = 0; k < GCC_CHUNK; ++k)
+          if (tg[k] >= 0 && cross_edge(v0 + x, rx, v0 + tg[k], ry[k])) link(x, tg[k]);
       }
     }
     __syncthreads();
     if (in_lds)
       for (int v = tid; v < ng; v += GCC_THREADS) lab[v0 + v] = v0 + p16_root(P, v);
-    __syncthreads();  // the next graph reuses P and first_row
+    __syncthreads();  // the next graph reuses P
   }
 }
 
@@ -2955,7 +2931,8 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   const int VB = tune.vertex_block;
   const dim3 gv = vertex_grid(n, VB, tune.xcd);
   const dim3 gx = vertex_grid(n, BLOCK, tune.xcd);  // compression and frontier passes
-  int *cc = I(L.cc), *hu = I(L.hu), *hv = I(L.hv);
+  int* cc = I(L.cc);
+  int2* hook = (int2*)(w + L.hook);
 
   // ---- First-CC (spanning forest)
   // the per-graph passes' largest-first order (the read-out's root labels are
@@ -2963,7 +2940,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int* gorder = (tune.graph_cc && G > 1 && vbegin != nullptr && G <= n) ? I(L.rootlab) : nullptr;
   if (gorder) LAUNCH(c, k_graph_order, 1, GORDER_THREADS, vbegin, G, n, off, gorder);
   if (tune.graph_cc && G > 1 && vbegin != nullptr) {
-    LAUNCH(c, k_graph_cc, (unsigned)(G < GCC_GRID ? G : GCC_GRID), GCC_THREADS, vbegin, G, n, off, adj, cc, hu, hv,
+    LAUNCH(c, k_graph_cc, (unsigned)(G < GCC_GRID ? G : GCC_GRID), GCC_THREADS, vbegin, G, n, off, adj, cc, hook,
            scal + S_GRAPH_NEXT, (const int*)gorder);
   } else {
     if (tune.ldd) {
@@ -2971,24 +2948,24 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
       int2* queue = (int2*)(w + L.dbits);  // A/8 bytes, free until Tagging; the queue needs < A/64
       const float beta = 1.0f / (float)(1 << tune.ldd);
       const int T0 = (int)ceil(log((double)(n > 2 ? n : 2)) / beta);
-      LAUNCH(c, k_ldd_init, gn, BLOCK, cc, hu, rnd, n, scal);
+      LAUNCH(c, k_ldd_init, gn, BLOCK, cc, hook, rnd, n, scal);
       for (int r = 0; r <= T0; ++r) {
-        LAUNCH(c, k_ldd_round, gn, BLOCK, off, adj, n, r, T0, 1.0f / beta, cc, rnd, hu, hv, queue, scal);
-        LAUNCH(c, k_ldd_huge, LDD_HUGE_GRID, BLOCK, off, adj, r, queue, scal, cc, rnd, hu, hv);
+        LAUNCH(c, k_ldd_round, gn, BLOCK, off, adj, n, r, T0, 1.0f / beta, cc, rnd, hook, queue, scal);
+        LAUNCH(c, k_ldd_huge, LDD_HUGE_GRID, BLOCK, off, adj, r, queue, scal, cc, rnd, hook);
       }
     } else if (!(tune.first_round_free && tune.sample_rounds > 0)) {
-      LAUNCH(c, k_cc_init, gn, BLOCK, cc, hu, n);  // else the atomic-free round initialises
+      LAUNCH(c, k_cc_init, gn, BLOCK, cc, hook, n);  // else the atomic-free round initialises
     }
     // compress after every round: the next round's finds then take one hop
     for (int r = 0; r < tune.sample_rounds; ++r) {
       const bool free_round = r == 0 && tune.first_round_free && !tune.ldd;
       if (free_round) {
-        if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gv, VB, off, adj, n, cc, hu, hv);
-        else LAUNCH(c, k_cc_first_round<false>, gv, VB, off, adj, n, cc, hu, hv);
+        if (tune.cc_prio) LAUNCH(c, k_cc_first_round<true>, gv, VB, off, adj, n, cc, hook);
+        else LAUNCH(c, k_cc_first_round<false>, gv, VB, off, adj, n, cc, hook);
       } else if (tune.cc_prio) {
-        LAUNCH(c, k_cc_sample<true>, gv, VB, off, adj, n, r, cc, hu, hv);
+        LAUNCH(c, k_cc_sample<true>, gv, VB, off, adj, n, r, cc, hook);
       } else {
-        LAUNCH(c, k_cc_sample<false>, gv, VB, off, adj, n, r, cc, hu, hv);
+        LAUNCH(c, k_cc_sample<false>, gv, VB, off, adj, n, r, cc, hook);
       }
       // flattened for the next round, except after the atomic-free round (its
       // chains are short and the next round's finds walk them anyway) and
@@ -2998,9 +2975,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_pick_mode, 1, MODE_SAMPLES, cc, n, scal + S_BIG_CC);
     frontier(cc, S_BIG_CC);
     if (tune.cc_prio)
-      LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
+      LAUNCH(c, k_cc_sweep<true>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hook);
     else
-      LAUNCH(c, k_cc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hu, hv);
+      LAUNCH(c, k_cc_sweep<false>, tile_grid, BLOCK, off, frow, fstart, adj, frows, ftile, tw, cc, hook);
   }
   // (Rooting's first pass flattens the sets)
 
@@ -3009,10 +2986,10 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *rootidx = I(L.rootidx), *roots = I(L.roots), *next = I(L.next), *tmp = I(L.scan_tmp);
   int *hubidx = I(L.hubidx), *shard = I(L.shard);
   fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
-  LAUNCH(c, k_edge_flags, gn, BLOCK, off, hu, n, cc, eid, headp, hubidx, scal);
+  LAUNCH(c, k_edge_flags, gn, BLOCK, off, hook, n, cc, eid, headp, hubidx, scal);
   LAUNCH(c, k_flatten, gx, BLOCK, cc, n);  // Rooting reads cc[v] as the component id
   scan_inplace(c, eid, n, nullptr, tmp, eid + n);
-  LAUNCH(c, k_edge_compact, gn, BLOCK, hu, hv, eid, n, eu, ev);
+  LAUNCH(c, k_edge_compact, gn, BLOCK, hook, eid, n, eu, ev);
   const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
   LAUNCH(c, k_tree_link, grid_for(arcs_max), BLOCK, off, hubidx, eid, n, eu, ev, headp, shard, nxt);
   int* lone = I(L.frank);  // free from here until Last-CC's frontier rewrites its row count (frank[n])

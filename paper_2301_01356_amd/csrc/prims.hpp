@@ -204,17 +204,17 @@ __device__ __forceinline__ void uf_link(int* p, int u, int v) {
   }
 }
 
-// As uf_link; a successful hook of root h stores the edge (u, v) at h.  At
-// the CAS, u's set (rooted at the hooked root) and v's set are disjoint, so
-// the recorded edges form a spanning forest.
-__device__ __forceinline__ void uf_link_record(int* p, int u, int v, int* hook_u, int* hook_v) {
+// As uf_link; a successful hook of root h stores the edge (u, v) at h (one
+// 8-byte store: the two ends share a line).  At the CAS, u's set (rooted at
+// the hooked root) and v's set are disjoint, so the recorded edges form a
+// spanning forest.
+__device__ __forceinline__ void uf_link_record(int* p, int u, int v, int2* hook) {
   if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
   int ru = uf_find(p, u), rv = uf_find(p, v);
   while (ru != rv) {
     int hi = ru > rv ? ru : rv, lo = ru > rv ? rv : ru;
     if (ld_relaxed(p + hi) == hi && atomicCAS(p + hi, hi, lo) == hi) {
-      hook_u[hi] = u;
-      hook_v[hi] = v;
+      hook[hi] = make_int2(u, v);
       return;
     }
     ru = uf_find(p, ru);
@@ -251,15 +251,14 @@ __device__ __forceinline__ void uf_link_prio(int* p, int u, int v) {
   }
 }
 
-__device__ __forceinline__ void uf_link_record_prio(int* p, int u, int v, int* hook_u, int* hook_v) {
+__device__ __forceinline__ void uf_link_record_prio(int* p, int u, int v, int2* hook) {
   if (ld_relaxed(p + u) == ld_relaxed(p + v)) return;
   int ru = uf_find(p, u), rv = uf_find(p, v);
   while (ru != rv) {
     const bool u_low = uf_prio(ru) < uf_prio(rv);
     const int lo = u_low ? ru : rv, hi = u_low ? rv : ru;
     if (ld_relaxed(p + lo) == lo && atomicCAS(p + lo, lo, hi) == lo) {
-      hook_u[lo] = u;
-      hook_v[lo] = v;
+      hook[lo] = make_int2(u, v);
       return;
     }
     ru = uf_find(p, ru);
