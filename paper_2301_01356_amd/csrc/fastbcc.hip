@@ -883,13 +883,51 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     const int v0 = min(max(vbegin[g], 0), n), v1 = min(max(vbegin[g + 1], v0), n), ng = v1 - v0;
     if (ng == 0) continue;
     const bool in_lds = ng <= GCC_LDS_VERTICES;
-    for (int v = tid; v < ng; v += GCC_THREADS) {
-      hook[v0 + v] = make_int2(-1, -1);
-      if (in_lds) p16_set(P, v, v);
-      else cc[v0 + v] = v0 + v;
+    const int a0 = off[v0], A = max(off[v1] - a0, 0);
+    // Every set starts here.  With parents in LDS this is also the first
+    // sampling round, without atomics: v points to the smaller of two sampled
+    // neighbours when that id is below v's (pointers to smaller ids are
+    // acyclic and keep each set's root its smallest member, as min-id hooking
+    // does), and the edge is kept at v as a hooked root's would be -- one
+    // coalesced store per vertex.  GCC_SB vertices per thread with their
+    // loads in flight together.
+    for (int base = 0; base < ng; base += GCC_THREADS * GCC_SB) {
+      int w[GCC_SB];
+      {
+        int rb[GCC_SB], re[GCC_SB];
+#pragma unroll
+        for (int j = 0; j < GCC_SB; ++j) {
+          const int v = base + j * GCC_THREADS + tid;
+          rb[j] = re[j] = 0;
+          if (in_lds && v < ng) {
+            rb[j] = min(max(off[v0 + v] - a0, 0), A);
+            re[j] = min(max(off[v0 + v + 1] - a0, rb[j]), A);
+          }
+        }
+        int w2[GCC_SB];
+#pragma unroll
+        for (int j = 0; j < GCC_SB; ++j) {
+          const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
+          w[j] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0 : v;
+          w2[j] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 16, d)] - v0 : v;
+        }
+#pragma unroll
+        for (int j = 0; j < GCC_SB; ++j) {
+          const int v = base + j * GCC_THREADS + tid;
+          const int c1 = w[j] >= 0 && w[j] < v ? w[j] : v, c2 = w2[j] >= 0 && w2[j] < v ? w2[j] : v;
+          w[j] = c1 < c2 ? c1 : c2;  // v unless a sampled neighbour of the graph has a smaller id
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < GCC_SB; ++j) {
+        const int v = base + j * GCC_THREADS + tid;
+        if (v >= ng) continue;
+        hook[v0 + v] = w[j] == v ? make_int2(-1, -1) : make_int2(v0 + v, v0 + w[j]);
+        if (in_lds) p16_set(P, v, w[j]);
+        else cc[v0 + v] = v0 + v;
+      }
     }
     __syncthreads();
-    const int a0 = off[v0], A = max(off[v1] - a0, 0);
     // hook the sets of local x and y, keeping the hooking edge
     auto link16 = [&](int x, int y) {
       if (p16_get(P, x) == p16_get(P, y)) return;  // same parent: same set
@@ -904,12 +942,10 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
         rv = p16_find(P, rv);
       }
     };
-    // The sampling rounds (parents in LDS): each vertex links to two hashed
-    // neighbours, both rounds taken together (no link order changes the
-    // sets), GCC_SB vertices per thread with all their loads in flight before
-    // the first link.
+    // The second sampling round (parents in LDS): each vertex links to one
+    // more hashed neighbour by union-find.
     for (int base = 0; in_lds && base < ng; base += GCC_THREADS * GCC_SB) {
-      int ys[GCC_SB][2];
+      int ys[GCC_SB];
       {
         int rb[GCC_SB], re[GCC_SB];
 #pragma unroll
@@ -924,18 +960,13 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
 #pragma unroll
         for (int j = 0; j < GCC_SB; ++j) {
           const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
-          ys[j][0] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0 : -1;
-          ys[j][1] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0 : -1;
+          ys[j] = d > 0 ? adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0 : -1;
         }
       }
 #pragma unroll
       for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid;
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          const int y = ys[j][r];
-          if (y != v && y >= 0 && y < ng) link16(v, y);  // -1 unless sampled
-        }
+        const int v = base + j * GCC_THREADS + tid, y = ys[j];
+        if (y != v && y >= 0 && y < ng) link16(v, y);  // -1 unless sampled
       }
     }
     __syncthreads();
@@ -1803,9 +1834,15 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
     const int v0 = min(max(vbegin[g], 0), n), v1 = min(max(vbegin[g + 1], v0), n), ng = v1 - v0;
     if (ng == 0) continue;
     const bool in_lds = ng <= GCC_LDS_VERTICES;
+    // Sets start from the plain tree edges to a parent of smaller id, without
+    // atomics (pointers to smaller ids are acyclic, and each pointer tree's
+    // root is its smallest member, as min-id hooking keeps it); the plain
+    // tree edges to a parent of larger id are linked after the barrier.
     for (int v = tid; v < ng; v += GCC_THREADS) {
-      if (in_lds) p16_set(P, v, v);
-      else lab[v0 + v] = v0 + v;
+      const int4 r = rec[v0 + v];
+      const bool up = r.z >= v0 && r.z < v0 + v && r.w == 0;
+      if (in_lds) p16_set(P, v, up ? r.z - v0 : v);
+      else lab[v0 + v] = up ? r.z : v0 + v;
     }
     __syncthreads();
     const int a0 = off[v0], A = max(off[v1] - a0, 0);
@@ -1823,55 +1860,9 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
         rv = p16_find(P, rv);
       }
     };
-    // One pass over the rows: each vertex's plain tree edge and (parents in
-    // LDS) its two sampled cross edges, GCC_SB vertices per thread with their
-    // loads in flight together.
-    for (int base = 0; base < ng; base += GCC_THREADS * GCC_SB) {
-      int rb[GCC_SB], re[GCC_SB], ys[GCC_SB][2];
-      int4 rv[GCC_SB];
-#pragma unroll
-      for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid;
-        rb[j] = re[j] = 0;
-        rv[j] = make_int4(0, -1, -1, 1);  // no tree edge
-        if (v < ng) {
-          rv[j] = rec[v0 + v];
-          rb[j] = min(max(off[v0 + v] - a0, 0), A);
-          re[j] = min(max(off[v0 + v + 1] - a0, rb[j]), A);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid, d = re[j] - rb[j];
-        ys[j][0] = ys[j][1] = -1;
-        if (d > 0) {
-          if (in_lds) {
-            ys[j][0] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 0, d)] - v0;
-            ys[j][1] = adj[a0 + rb[j] + (int)sample_pos(v0 + v, 1, d)] - v0;
-          }
-        }
-      }
-      int4 ry[GCC_SB][2];
-#pragma unroll
-      for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid;
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          const int y = ys[j][r];
-          const bool want = y != v && y >= 0 && y < ng;
-          ys[j][r] = want ? y : -1;
-          ry[j][r] = want ? rec[v0 + y] : make_int4(0, -1, -1, 0);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < GCC_SB; ++j) {
-        const int v = base + j * GCC_THREADS + tid;
-        const int4 r = rv[j];
-        if (r.z >= v0 && r.z < v1 && r.w == 0) link(v, r.z - v0);  // plain tree edge
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-          if (ys[j][k] >= 0 && cross_edge(v0 + v, r, v0 + ys[j][k], ry[j][k])) link(v, ys[j][k]);
-      }
+    for (int v = tid; v < ng; v += GCC_THREADS) {
+      const int4 r = rec[v0 + v];
+      if (r.z > v0 + v && r.z < v1 && r.w == 0) link(v, r.z - v0);
     }
     __syncthreads();
     int big = -1;
