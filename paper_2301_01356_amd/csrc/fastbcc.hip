@@ -767,10 +767,11 @@ constexpr int LDD_HUGE_GRID = 1024;
 // word, so a path-halving store into the other half makes it retry and never
 // loses an update.  A larger graph runs the same loop on the device-memory
 // union-find.
-// Two sampling rounds link each vertex to the neighbours at two hashed
-// positions of its row; the sweep then gives thread t the rows t, t + 1024,
-// ..., tests each row's set in LDS and reads only the rows outside the
-// sampled largest set, a chunk of targets in flight.
+// Two sampling rounds (an atomic-free one over two hashed neighbours, then a
+// union-find one over a third) hook most vertices of a connected graph into
+// one set; the sweep then gives thread t the rows t, t + 1024, ..., tests
+// each row's set in LDS and reads only the rows outside the sampled largest
+// set, a chunk of targets in flight.
 constexpr int GCC_THREADS = 1024;
 constexpr int GCC_LDS_VERTICES = 1 << 16;
 constexpr int GCC_CHUNK = 8;
