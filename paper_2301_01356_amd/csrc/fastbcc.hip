@@ -771,10 +771,9 @@ constexpr int LDD_HUGE_GRID = 1024;
 // union-find one over a third) hook most vertices of a connected graph into
 // one set; the sweep then gives thread t the rows t, t + 1024, ..., tests
 // each row's set in LDS and reads only the rows outside the sampled largest
-// set, a chunk of targets in flight.
+// set, their arcs spread over the wave's lanes.
 constexpr int GCC_THREADS = 1024;
 constexpr int GCC_LDS_VERTICES = 1 << 16;
-constexpr int GCC_CHUNK = 8;
 constexpr int GCC_SB = 4;  // vertices per thread with their loads in flight together in the row pass
 constexpr int GCC_GRID = 1024;  // workgroups of the launch (more than one per compute unit waits)
 
@@ -859,6 +858,33 @@ __global__ void __launch_bounds__(GORDER_THREADS) k_graph_order(const int* __res
   }
   __syncthreads();
   for (int g = tid; g < G; g += GORDER_THREADS) order[atomicAdd(&cls[graph_size_class(vbegin, n, off, g)], 1)] = g;
+}
+
+// The sweep's arcs spread over a wave: each lane holds at most one row to
+// read, [rb, re) (empty if none); the wave walks the concatenation of its
+// lanes' rows 64 arcs at a time, each lane finding the row of its arc by a
+// binary search over the wave's prefix sums of the row lengths (kept rows are
+// few and short, so one row per lane would leave most lanes idle).
+// body(owner lane, arc or -1) runs on all 64 lanes together, so it may shuffle.
+template <typename Body>
+__device__ __forceinline__ void wave_row_arcs(int rb, int re, Body&& body) {
+  const int lane = lane_id(), d = re - rb;
+  int incl = d;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl_up(incl, o, WAVE);
+    if (lane >= o) incl += t;
+  }
+  const int excl = incl - d, total = __shfl(incl, WAVE - 1, WAVE);
+  for (int c = 0; c < total; c += WAVE) {
+    const int k = c + lane;
+    int lo = 0;  // the last lane whose rows start at or before arc k: its row holds k
+#pragma unroll
+    for (int step = WAVE / 2; step > 0; step >>= 1)
+      if (__shfl(excl, lo + step, WAVE) <= k) lo += step;
+    const int a = __shfl(rb, lo, WAVE) + (k - __shfl(excl, lo, WAVE));
+    body(lo, k < total ? a : -1);
+  }
 }
 
 // The next graph of a per-graph pass: the i-th claim takes order[i] (index
@@ -995,22 +1021,21 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_cc(const int* __restrict_
     // two rows that are both skipped lies inside the big set already); rows
     // are tested in LDS, so the skipped ones (most, once sampling found the
     // big set) cost no global load
-    for (int x = tid; x < ng; x += GCC_THREADS) {
-      if (in_lds && p16_find(P, x) == p16_find(P, big)) continue;
-      const int rb = min(max(off[v0 + x] - a0, 0), A), rend = min(max(off[v0 + x + 1] - a0, rb), A);
-      for (int c0 = rb; c0 < rend; c0 += GCC_CHUNK) {
-        int tg[GCC_CHUNK];
-#pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
-#pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k) {
-          if (c0 + k >= rend) break;
-          const int y = tg[k];
-          if (y == x || y < 0 || y >= ng) continue;  // self-loops and foreign ids skipped
-          if (in_lds) link16(x, y);
-          else if (y > x) uf_link_record(cc, v0 + x, v0 + y, hook);  // each edge once
-        }
+    for (int xb = 0; xb < ng; xb += GCC_THREADS) {  // the same trip count on every wave
+      const int xo = xb + tid;
+      int rb = 0, re = 0;
+      if (xo < ng && !(in_lds && p16_find(P, xo) == p16_find(P, big))) {
+        rb = min(max(off[v0 + xo] - a0, 0), A);
+        re = min(max(off[v0 + xo + 1] - a0, rb), A);
       }
+      wave_row_arcs(rb, re, [&](int owner, int a) {
+        const int x = __shfl(xo, owner, WAVE);
+        if (a < 0) return;
+        const int y = adj[a0 + a] - v0;
+        if (y == x || y < 0 || y >= ng) return;  // self-loops and foreign ids skipped
+        if (in_lds) link16(x, y);
+        else if (y > x) uf_link_record(cc, v0 + x, v0 + y, hook);  // each edge once
+      });
     }
     __syncthreads();
     if (in_lds)
@@ -1885,29 +1910,25 @@ __global__ void __launch_bounds__(GCC_THREADS) k_graph_lcc(const int* __restrict
       __syncthreads();
       big = big_s;
     }
-    for (int x = tid; x < ng; x += GCC_THREADS) {
-      if (in_lds && p16_find(P, x) == p16_find(P, big)) continue;
-      const int rb = min(max(off[v0 + x] - a0, 0), A), rend = min(max(off[v0 + x + 1] - a0, rb), A);
-      if (rend == rb) continue;
-      const int4 rx = rec[v0 + x];
-      for (int c0 = rb; c0 < rend; c0 += GCC_CHUNK) {
-        int tg[GCC_CHUNK];
-#pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k) tg[k] = c0 + k < rend ? adj[a0 + c0 + k] - v0 : -1;
-        // the chunk's target records are all in flight before the first link
-        int4 ry[GCC_CHUNK];
-#pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k) {
-          const int y = tg[k];
-          // each edge once in memory mode
-          const bool want = y != x && y >= 0 && y < ng && (in_lds || y > x);
-          tg[k] = want ? y : -1;
-          ry[k] = want ? rec[v0 + y] : make_int4(0, -1, -1, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < GCC_CHUNK; ++k)
-          if (tg[k] >= 0 && cross_edge(v0 + x, rx, v0 + tg[k], ry[k])) link(x, tg[k]);
+    for (int xb = 0; xb < ng; xb += GCC_THREADS) {  // the same trip count on every wave
+      const int xo = xb + tid;
+      int rb = 0, re = 0;
+      int4 ro = make_int4(0, -1, -1, 0);
+      if (xo < ng && !(in_lds && p16_find(P, xo) == p16_find(P, big))) {
+        rb = min(max(off[v0 + xo] - a0, 0), A);
+        re = min(max(off[v0 + xo + 1] - a0, rb), A);
+        if (re > rb) ro = rec[v0 + xo];
       }
+      wave_row_arcs(rb, re, [&](int owner, int a) {
+        const int x = __shfl(xo, owner, WAVE);
+        const int4 rx = make_int4(__shfl(ro.x, owner, WAVE), __shfl(ro.y, owner, WAVE), __shfl(ro.z, owner, WAVE),
+                                  __shfl(ro.w, owner, WAVE));
+        if (a < 0) return;
+        const int y = adj[a0 + a] - v0;
+        // each edge once in memory mode
+        if (y == x || y < 0 || y >= ng || (!in_lds && y < x)) return;
+        if (cross_edge(v0 + x, rx, v0 + y, rec[v0 + y])) link(x, y);
+      });
     }
     __syncthreads();
     if (in_lds)
