@@ -129,10 +129,12 @@ class Tuner:
         cfg = self.cache.get(key)
         return encode(cfg) if cfg else None
 
-    def tune(self, key: str, time_ms: Callable[[int], float], reps: int = 5, force: bool = False) -> int:
+    def tune(self, key: str, time_ms: Callable[[int], float], reps: int = 5, force: bool = False,
+             progress: Optional[Callable[[str], None]] = None) -> int:
         """Coordinate descent over the knobs from the fastest seed, then a
         run-off between the fastest configurations seen; ``time_ms(flags)``
-        runs one solve and returns its duration.  Returns the best flags."""
+        runs one solve and returns its duration; ``progress`` (if given) gets
+        a line per knob visited.  Returns the best flags."""
         if not force and key in self.cache:
             return encode(self.cache[key])
         if not force and key in self.shipped:
@@ -165,6 +167,8 @@ class Tuner:
                 if best_v != cfg[knob]:
                     cfg[knob] = best_v
                     changed = True
+                if progress:
+                    progress(f"{key}: {knob} = {cfg[knob]} ({best_t:.3f} ms)")
             if not changed:
                 break
         # run-off: the descent's pick and the next fastest configurations,
@@ -304,7 +308,7 @@ def ship(names, path: str = SHIPPED, out: Optional[str] = None) -> Dict[str, Dic
     for name in names:
         key, run = workload_runner(name)
         t = Tuner(cache_path=None, shipped=None)
-        flags = t.tune(key, run, force=True)
+        flags = t.tune(key, run, force=True, progress=lambda line: print(line, flush=True))
         for k in [k for k, e in table.items() if name in e.get("workloads", ())]:
             table[k]["workloads"] = [w for w in table[k]["workloads"] if w != name]
             if not table[k]["workloads"]:
