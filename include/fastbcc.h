@@ -116,9 +116,11 @@ typedef enum fastbcc_status {
  *              2 = 128, 3 = 512
  *   bit  29    flatten First-CC's sets after its atomic-free first round too
  *              (the next sampling round's finds then take one hop)
- *   bit  30    XCD-ordered per-vertex launches: each of the GPU's 8 XCDs (each
- *              with its own L2) takes one contiguous run of vertices, which
- *              keeps graph-local accesses (a batch's graphs, lattices) in one L2
+ *   bit  30    XCD-ordered per-vertex launches (and the Euler tour's per-node
+ *              and per-ruler ones): each of the GPU's 8 XCDs (each with its
+ *              own L2) takes one contiguous run of vertices or tour nodes,
+ *              which keeps graph-local accesses (a batch's graphs, lattices)
+ *              in one L2
  *   bit  31    batches only (fastbcc_solve_batched): First-CC and Last-CC
  *              per graph, one workgroup per graph running union-find over the
  *              graph's arcs (or its skeleton), parents in LDS for graphs of up

@@ -264,7 +264,8 @@ bool decode_flags(uint32_t flags, Tune& t) {
 // own L2.  A per-vertex launch of shape (8, per) puts the logical blocks
 // k*per .. k*per + per - 1 (one contiguous run of vertices) on XCD k, so a
 // kernel whose accesses stay near its own vertex (the graphs of a batch,
-// lattices) keeps them in one L2.  The index below is the logical one for
+// lattices) keeps them in one L2.  The Euler tour's per-node and per-ruler
+// launches take the same shape: its nodes are numbered graph by graph too.  The index below is the logical one for
 // both shapes: a plain launch (blocks, 1) gives the usual numbering.
 constexpr int NUM_XCD = 8;
 __device__ __forceinline__ int vertex_index() {
@@ -1158,23 +1159,34 @@ __global__ void k_ldd_huge(const int* __restrict__ off, const int* __restrict__ 
 // picked by edge number, chained shard after shard.
 __device__ __forceinline__ bool is_hub(const int* __restrict__ off, int x) { return off[x + 1] - off[x] >= HUB_DEG; }
 
+// Hub test of the tour kernels: one bit per vertex (a 64-bit word per 64
+// vertices), which stays in cache where the row starts would not.
+__device__ __forceinline__ bool hub_bit(const unsigned long long* __restrict__ hubbits, int x) {
+  return (hubbits[x >> 6] >> (x & 63)) & 1ull;
+}
+
 // Per vertex, first pass of Rooting: edge flag for the dense numbering,
 // First-CC's sets flattened, the out-list head cleared, hubs numbered (in any
-// order: the number only picks the hub's counters).
+// order: the number only picks the hub's counters) and their bits set (a
+// wave covers 64 consecutive vertices from a multiple of 64: one word).
 __global__ void k_edge_flags(const int* __restrict__ off, const int2* __restrict__ hook, int n, int* cc,
-                             int* __restrict__ eid, int* __restrict__ headp, int* __restrict__ hubidx, int* scal) {
-  int h = blockIdx.x * blockDim.x + threadIdx.x;
+                             int* __restrict__ eid, int* __restrict__ headp, int* __restrict__ hubidx, int* scal,
+                             unsigned long long* __restrict__ hubbits) {
+  const int h = vertex_index();
+  const bool hub = h < n && is_hub(off, h);
+  const unsigned long long bits = __ballot(hub);
+  if (lane_id() == 0 && h < n) hubbits[h >> 6] = bits;
   if (h >= n) return;
   eid[h] = hook[h].x >= 0 ? 1 : 0;
   const int r = uf_find(cc, h);
   if (ld_relaxed(cc + h) != r) st_relaxed(cc + h, r);
   headp[h] = -1;
-  if (is_hub(off, h)) hubidx[h] = atomicAdd(scal + S_HUBS, 1);
+  if (hub) hubidx[h] = atomicAdd(scal + S_HUBS, 1);
 }
 
 __global__ void k_edge_compact(const int2* __restrict__ hook, const int* __restrict__ eid, int n,
                                int* __restrict__ eu, int* __restrict__ ev) {
-  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  int h = vertex_index();
   if (h >= n) return;
   const int2 r = hook[h];
   if (r.x < 0) return;
@@ -1187,13 +1199,14 @@ __device__ __forceinline__ int arc_src(const int* __restrict__ eu, const int* __
   return (a & 1) ? ev[a >> 1] : eu[a >> 1];
 }
 
-__global__ void k_tree_link(const int* __restrict__ off, const int* __restrict__ hubidx, const int* __restrict__ eid,
-                            int n, const int* __restrict__ eu, const int* __restrict__ ev, int* headp, int* shard,
-                            int* __restrict__ nxt) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_tree_link(const unsigned long long* __restrict__ hubbits, const int* __restrict__ hubidx,
+                            const int* __restrict__ eid, int n, const int* __restrict__ eu, const int* __restrict__ ev,
+                            int* headp, int* shard, int* __restrict__ nxt) {
+  const int a = vertex_index();
   if (a >= 2 * eid[n]) return;
   const int s = arc_src(eu, ev, a);
-  int* slot = is_hub(off, s) ? shard + (size_t)hubidx[s] * HUB_SHARDS + ((a >> 1) & (HUB_SHARDS - 1)) : headp + s;
+  int* slot = hub_bit(hubbits, s) ? shard + (size_t)hubidx[s] * HUB_SHARDS + ((a >> 1) & (HUB_SHARDS - 1))
+                                  : headp + s;
   nxt[a] = atomicExch(slot, a);
 }
 
@@ -1207,7 +1220,7 @@ __global__ void k_tree_link(const int* __restrict__ off, const int* __restrict__
 __global__ void k_hub_lists(const int* __restrict__ off, const int* __restrict__ hubidx,
                             const int* __restrict__ cc, int n, int* headp, int* shard, int* __restrict__ rootidx,
                             int* __restrict__ lone, int* __restrict__ rdeg) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   rdeg[v] = -1;
   int hv = headp[v];
@@ -1239,7 +1252,7 @@ __global__ void k_root_list(const int* __restrict__ cc, const int* __restrict__ 
                             const int* __restrict__ rootidx, const int* __restrict__ rdeg,
                             const int* __restrict__ rsel, const int* __restrict__ scal, int n,
                             int* __restrict__ roots) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   if (cc[v] != v || headp[v] < 0) return;
   roots[rootidx[v]] = rdeg[v] >= 0 ? rsel[v] : v;
@@ -1276,14 +1289,14 @@ __device__ __forceinline__ int node_count(const int* __restrict__ rootidx, const
   return rootidx[n] + 2 * eid[n];
 }
 
-__global__ void k_euler_next(const int* __restrict__ off, const int* __restrict__ hubidx,
+__global__ void k_euler_next(const unsigned long long* __restrict__ hubbits, const int* __restrict__ hubidx,
                              const int* __restrict__ eid, const int* __restrict__ eu, const int* __restrict__ ev,
                              const int* __restrict__ headp, const int* __restrict__ shard,
                              const int* __restrict__ nxt, const int* __restrict__ cc,
                              const int* __restrict__ rootidx, const int* __restrict__ roots, int n,
                              int* __restrict__ next) {
   const int C = rootidx[n], NL = node_count(rootidx, eid, n);
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = vertex_index();
   if (i >= NL) return;
   if (i < C) {
     next[i] = C + headp[roots[i]];
@@ -1298,7 +1311,7 @@ __global__ void k_euler_next(const int* __restrict__ off, const int* __restrict_
   const int v = arc_src(eu, ev, t);
   int head;
   bool wrap;
-  if (is_hub(off, v)) {
+  if (hub_bit(hubbits, v)) {
     const int q = shard[(size_t)hubidx[v] * HUB_SHARDS + ((t >> 1) & (HUB_SHARDS - 1))];
     wrap = q < 0;
     head = wrap ? -2 - q : q;
@@ -1326,7 +1339,7 @@ __global__ void k_lr_walk(const int* __restrict__ next, const int* __restrict__ 
                           int* __restrict__ rnext, int* __restrict__ rlen) {
   const int NL = node_count(rootidx, eid, n);
   const int R = (NL + (1 << shift) - 1) >> shift;
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = vertex_index();
   if (r >= R) return;
   const int mask = (1 << shift) - 1;
   int i = r << shift, cnt = 0, nr = -1;
@@ -1416,7 +1429,7 @@ __global__ void k_lr_pos(const int* __restrict__ rootidx, const int* __restrict_
                          int* status) {
   const int NL = node_count(rootidx, eid, n);
   const int R = (NL + (1 << shift) - 1) >> shift;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = vertex_index();
   if (i >= NL) return;
   int2 o = ol[i];
   if (o.x < 0 || o.x >= R) {  // a node no ruler walked over: the tour is broken
@@ -1430,7 +1443,7 @@ __global__ void k_lr_pos(const int* __restrict__ rootidx, const int* __restrict_
 __global__ void k_enter_flags(const int* __restrict__ rootidx, const int* __restrict__ eid, int n,
                               const int* __restrict__ pos, int* __restrict__ eflag, int* status) {
   const int C = rootidx[n], NL = node_count(rootidx, eid, n);
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = vertex_index();
   if (i >= NL) return;
   int f = 1;
   if (i >= C) f = pos[i] < pos[C + ((i - C) ^ 1)] ? 1 : 0;  // the down arc comes first
@@ -1449,7 +1462,7 @@ __global__ void k_tags(const int* __restrict__ rootidx, const int* __restrict__ 
                        const int* __restrict__ lone, int n, const int* __restrict__ pos,
                        const int* __restrict__ escan, int* __restrict__ first, int4* __restrict__ rec, int* status) {
   const int C = rootidx[n], NL = node_count(rootidx, eid, n);
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = vertex_index();
   if (i >= NL) return;
   int v, f, l, p;
   if (i < C) {
@@ -2999,30 +3012,35 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   int *rootidx = I(L.rootidx), *roots = I(L.roots), *next = I(L.next), *tmp = I(L.scan_tmp);
   int *hubidx = I(L.hubidx), *shard = I(L.shard);
   fill_i32(c, shard, -1, L.hubs * HUB_SHARDS);
-  LAUNCH(c, k_edge_flags, gn, BLOCK, off, hook, n, cc, eid, headp, hubidx, scal);
+  unsigned long long* hubbits = (unsigned long long*)(w + L.bigbits);  // free until the read-out
+  LAUNCH(c, k_edge_flags, gx, BLOCK, off, hook, n, cc, eid, headp, hubidx, scal, hubbits);
   LAUNCH(c, k_flatten, gx, BLOCK, cc, n);  // Rooting reads cc[v] as the component id
   scan_inplace(c, eid, n, nullptr, tmp, eid + n);
-  LAUNCH(c, k_edge_compact, gn, BLOCK, hook, eid, n, eu, ev);
+  LAUNCH(c, k_edge_compact, gx, BLOCK, hook, eid, n, eu, ev);
   const int64_t arcs_max = 2 * (int64_t)n;  // 2T <= 2n - 2
-  LAUNCH(c, k_tree_link, grid_for(arcs_max), BLOCK, off, hubidx, eid, n, eu, ev, headp, shard, nxt);
+  // plain order: its atomics gain nothing from one XCD's L2 and lose issue
+  // rate when one graph's all land there
+  LAUNCH(c, k_tree_link, grid_for(arcs_max), BLOCK, (const unsigned long long*)hubbits, hubidx, eid, n, eu, ev, headp,
+         shard, nxt);
   int* lone = I(L.frank);  // free from here until Last-CC's frontier rewrites its row count (frank[n])
   int *rdeg = I(L.pos), *rsel = I(L.eflag);  // free until list ranking
-  LAUNCH(c, k_hub_lists, gn, BLOCK, off, hubidx, cc, n, headp, shard, rootidx, lone, rdeg);
+  LAUNCH(c, k_hub_lists, gx, BLOCK, off, hubidx, cc, n, headp, shard, rootidx, lone, rdeg);
   scan_inplace(c, rootidx, n, nullptr, tmp, rootidx + n);
   scan_inplace(c, lone, n, nullptr, tmp, lone + n);
   LAUNCH(c, k_root_degree, grid_for(ROOT_SAMPLES, ROOT_BLOCK), ROOT_BLOCK, off, cc, n, rdeg);
   LAUNCH(c, k_root_select, grid_for(ROOT_SAMPLES), BLOCK, off, cc, n, rdeg, rsel);
-  LAUNCH(c, k_root_list, gn, BLOCK, cc, headp, rootidx, rdeg, rsel, scal, n, roots);
+  LAUNCH(c, k_root_list, gx, BLOCK, cc, headp, rootidx, rdeg, rsel, scal, n, roots);
   const int64_t nodes_max = 2 * (int64_t)n;  // C + 2T <= 2n - 1
-  const unsigned gnode = grid_for(nodes_max);
-  LAUNCH(c, k_euler_next, gnode, BLOCK, off, hubidx, eid, eu, ev, headp, shard, nxt, cc, rootidx, roots, n, next);
+  const dim3 gnode = vertex_grid(nodes_max, BLOCK, tune.xcd);
+  LAUNCH(c, k_euler_next, gnode, BLOCK, (const unsigned long long*)hubbits, hubidx, eid, eu, ev, headp, shard, nxt, cc,
+         rootidx, roots, n, next);
 
   // list ranking: ruling set + pointer jumping over rulers
   const int sh = tune.ruler_shift;
   const int64_t rmax = cdiv(nodes_max, int64_t(1) << sh);
   int2* ol = (int2*)(w + L.ol);
   int *rlen = I(L.rlen), *rnext = I(L.rnext);
-  LAUNCH(c, k_lr_walk, grid_for(rmax), BLOCK, next, rootidx, eid, n, sh, ol, rnext, rlen);
+  LAUNCH(c, k_lr_walk, vertex_grid(rmax, BLOCK, tune.xcd), BLOCK, next, rootidx, eid, n, sh, ol, rnext, rlen);
   int* bufv[2] = {I(L.rval0), I(L.rval1)};
   int* bufn[2] = {I(L.rnx0), I(L.rnx1)};
   auto jump = [&](const int* vin, const int* nin, int shift, int64_t count) {  // suffix sums
