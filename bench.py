@@ -112,18 +112,18 @@ def random_accesses(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "46c377d1348edf74",
+    "src_sha": "3b2bf07c079764bd",
     "workload": "rmat25",
     "flags": 0x2B32506,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378497.4, "write_kib": 4090686.4},
-    "k_tag_sample": {"fetch_kib": 2380423.0, "write_kib": 1445401.5},
-    "k_cc_sample": {"fetch_kib": 2314497.8, "write_kib": 733740.6},
-    "k_lr_walk": {"fetch_kib": 1411392.1, "write_kib": 1063985.7},
-    "k_rmq_query": {"fetch_kib": 871178.6, "write_kib": 67817.6},
-    "k_tree_link": {"fetch_kib": 1257078.2, "write_kib": 830754.3},
-    "k_mirror_find": {"fetch_kib": 2068313.5, "write_kib": 312027.7},
-    "k_lcc_tree": {"fetch_kib": 862850.1, "write_kib": 296773.9},
+    "k_bcc_rows": {"fetch_kib": 378485.8, "write_kib": 4090678.7},
+    "k_tag_sample": {"fetch_kib": 2381264.7, "write_kib": 1445325.7},
+    "k_cc_sample": {"fetch_kib": 2296317.7, "write_kib": 635973.3},
+    "k_lr_walk": {"fetch_kib": 1409439.6, "write_kib": 1063863.8},
+    "k_rmq_query": {"fetch_kib": 871215.9, "write_kib": 67797.6},
+    "k_tree_link": {"fetch_kib": 579204.3, "write_kib": 830753.4},
+    "k_mirror_find": {"fetch_kib": 2068323.6, "write_kib": 312027.7},
+    "k_lcc_tree": {"fetch_kib": 863204.7, "write_kib": 296596.4},
 }
 
 
