@@ -658,3 +658,39 @@ def test_batched_per_graph_more_graphs_than_vertices(flags):
     for i, g in enumerate(graphs):
         a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
         assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} (n={g.n})")
+
+
+@pytest.mark.parametrize("flags", [N.tune_flags(graph_cc=True), N.tune_flags(graph_cc=True, xcd_order=True)])
+def test_batched_per_graph_long_rows_outside_the_largest_set(flags):
+    """The per-graph sweeps spread the rows outside each graph's largest set
+    over a wave's lanes: hubs of thousands of arcs outside it (a star beside a
+    larger lattice, a star whose hub has the largest id, a star inside a graph
+    above the LDS size), repeated edges and self-loops (general contract)."""
+    rng = np.random.default_rng(23)
+
+    def star_beside(base_n, leaves, hub_last):
+        lat = gen.family("lattice", base_n, 0.9, seed=int(rng.integers(1 << 30)))
+        ed = []
+        for v in range(lat.n):
+            for a in range(int(lat.offsets[v]), int(lat.offsets[v + 1])):
+                if v < int(lat.adj[a]):
+                    ed.append((v, int(lat.adj[a])))
+        hub = lat.n + leaves if hub_last else lat.n
+        first_leaf = lat.n if hub_last else lat.n + 1
+        ed += [(hub, first_leaf + i) for i in range(leaves)]
+        ed += [(first_leaf + i, first_leaf + i + 1) for i in range(0, leaves - 1, 7)]  # a few leaf-leaf chords
+        return gen.multigraph_csr(lat.n + leaves + 1, ed)
+
+    loopy = gen.multigraph_csr(6, [(0, 1), (0, 1), (1, 2), (2, 0), (2, 2), (3, 4), (4, 5), (5, 3), (5, 5), (2, 3)])
+    graphs = [star_beside(4000, 3000, False), loopy, star_beside(2500, 5000, True),
+              star_beside(70000, 4000, False), gen.from_edges(3, cycle(3))]
+    u = gen.unite(graphs)
+    note(f"per-graph long rows: {len(graphs)} graphs n={u.n} arcs={u.num_arcs} flags={flags:#x}")
+    vb = torch.from_numpy(u.vbegin).to(DEV)
+    off, adj = to_dev(u)
+    r = solve_batched(vb, off, adj, flags=flags)
+    torch.cuda.synchronize()
+    lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
+    for i, g in enumerate(graphs):
+        a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
+        assert_parity(g, (lab[a0:a1], ap[u.vbegin[i] : u.vbegin[i + 1]], int(nb[i])), f"graph {i} (n={g.n})")
