@@ -1273,7 +1273,7 @@ __device__ __forceinline__ bool lone_tags(const int* __restrict__ lone, int n, i
 // Exact tags: w1/w2 start empty for the sweep's atomics.
 __global__ void k_tag_init(const int* __restrict__ lone, int n, int* __restrict__ first, int4* __restrict__ rec,
                            int* __restrict__ w1, int* __restrict__ w2) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   lone_tags(lone, n, v, first, rec);
   w1[v] = INT32_MAX;
@@ -1549,7 +1549,7 @@ __global__ void k_tag_sweep(const int* __restrict__ off, const int* __restrict__
 // both tags at once and the preorder map costs no second line.
 __global__ void k_rmq_scatter(const int* __restrict__ first, const int* __restrict__ w1, const int* __restrict__ w2,
                               int n, int4* __restrict__ W, int* status) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   int f = first[v];
   if (f < 0 || f >= n) {  // preorder numbers must be a permutation of [0, n)
@@ -2046,7 +2046,7 @@ __global__ void k_relabel(int* lab, int n, const int* __restrict__ scal, const i
 // ------------------------------------------------------------ read-out
 __global__ void k_readout_init(int n, int* __restrict__ head, uint8_t* __restrict__ heads, int* __restrict__ rootlab,
                                int* __restrict__ minid, uint8_t* __restrict__ ap) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = vertex_index();
   if (v >= n) return;
   head[v] = -1;
   heads[v] = 0;
@@ -2383,7 +2383,7 @@ __global__ void k_canon_first(const int* __restrict__ off, const int* __restrict
 // Records for the final pass: z becomes canon(l) (canon is -1 where l labels
 // no BCC).
 __global__ void k_vertex_canon(const int* __restrict__ canon, int n, int4* __restrict__ vlh) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = vertex_index();
   if (v >= n) return;
   vlh[v].z = canon[vlh[v].x];
 }
@@ -2546,7 +2546,7 @@ __global__ void k_bcc_rows(const int* __restrict__ off, const int* __restrict__ 
 // The arcs h->y of the mirror search get y's BCC.
 __global__ void k_mirror_write(int n, const int4* __restrict__ vlh, const int* __restrict__ mpos,
                                const int* __restrict__ mcnt, int* __restrict__ out) {
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = vertex_index();
   if (y >= n) return;
   const int a0 = mpos[y];
   if (a0 < 0) return;
@@ -3087,9 +3087,9 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
       LAUNCH(c, k_rmq_level, grid_for(L.nb), BLOCK, tab, L.nb, j, j + 1 < L.levels);
   };
   if (!tune.sampled_tags) {
-    LAUNCH(c, k_tag_init, gn, BLOCK, lone, n, first, rec, w1, w2);
+    LAUNCH(c, k_tag_init, gx, BLOCK, lone, n, first, rec, w1, w2);
     LAUNCH(c, k_tag_sweep, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, first, rec, w1, w2, dbits);
-    LAUNCH(c, k_rmq_scatter, gn, BLOCK, first, w1, w2, n, W, scal + S_STATUS);
+    LAUNCH(c, k_rmq_scatter, gx, BLOCK, first, w1, w2, n, W, scal + S_STATUS);
     rmq_tables(nullptr);
     LAUNCH(c, k_rmq_query, gv, VB, n, L.nb, W, pre, suf, tab, rec, (int)QUERY_EXACT, true, (int*)nullptr,
            scal + S_STATUS);
@@ -3157,7 +3157,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
   // ---- heads, articulation points, canonical labels
   int *head = I(L.head), *rootlab = I(L.rootlab), *minid = I(L.minid), *canon = I(L.canon), *bsum = I(L.bsum);
   uint8_t* heads = (uint8_t*)(w + L.heads);
-  LAUNCH(c, k_readout_init, gn, BLOCK, n, head, heads, rootlab, minid, out_ap);
+  LAUNCH(c, k_readout_init, gx, BLOCK, n, head, heads, rootlab, minid, out_ap);
   LAUNCH(c, k_bcc_heads, gn, BLOCK, rec, lab, n, head, heads, rootlab, out_ap, out_nbcc ? bsum : nullptr);
   if (out_nbcc) {
     if (G <= 1) {
@@ -3181,7 +3181,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     LAUNCH(c, k_mirror_find, gv, VB, off, adj, n, vlh, scal, minid, mpos, mcnt);
     fill_i32(c, canon, -1, n);
     LAUNCH(c, k_canon_first, gv, VB, off, adj, n, rec, lab, vlh, heads, bigbits, scal, minid, vbegin, G, canon);
-    LAUNCH(c, k_vertex_canon, gn, BLOCK, canon, n, vlh);
+    LAUNCH(c, k_vertex_canon, gx, BLOCK, canon, n, vlh);
     if (no_loops) {
       const int stride = tw >= ROWS_TILE_WINDOWS ? 1 : ROWS_TILE_WINDOWS / tw;
       const unsigned rows_grid = (unsigned)cdiv(cdiv(ntiles, stride) * WAVE, BLOCK);
@@ -3191,7 +3191,7 @@ fastbcc_status solve_core(const Layout& L, Ctx& c, int n, int64_t A, const int* 
     } else {
       LAUNCH(c, k_bcc_final, tile_grid, BLOCK, off, adj, n, A, tile_row, tw, vlh, bigbits, scal, out_label);
     }
-    LAUNCH(c, k_mirror_write, gn, BLOCK, n, vlh, mpos, mcnt, out_label);
+    LAUNCH(c, k_mirror_write, gx, BLOCK, n, vlh, mpos, mcnt, out_label);
     return c.ok ? FASTBCC_OK : FASTBCC_ERR_HIP;
   }
   if (!tune.sampled_tags)
