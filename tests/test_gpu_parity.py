@@ -559,12 +559,15 @@ def test_hub_graphs_batched(flags):
         assert_parity(gi, (lab[a0:a1], ap[v0:v1], int(nb[i])), f"batched hub graph {i}")
 
 
-@pytest.mark.parametrize("sizes", [(200, 56, 256), (256, 256), (100, 156, 300, 212), (512,), (30, 226)])
-def test_batched_counts_when_the_batch_ends_on_a_block_boundary(sizes):
+@pytest.mark.parametrize("flags", [0, N.tune_flags(xcd_order=True), N.tune_flags(xcd_order=True, graph_cc=True)])
+@pytest.mark.parametrize("sizes", [(200, 56, 256), (256, 256), (100, 156, 300, 212), (512,), (30, 226),
+                                   (256,) * 9 + (100,)])
+def test_batched_counts_when_the_batch_ends_on_a_block_boundary(sizes, flags):
     """Per-graph BCC counts read the scanned per-block counts up to the end
     of the last graph; when the vertex total is a multiple of the block size
     (256) that is the scan's total slot.  The workspace starts full of
-    garbage so that a slot the solve did not write cannot pass by luck."""
+    garbage so that a slot the solve did not write cannot pass by luck; the
+    same with XCD-ordered launches and with the per-graph passes."""
     rng = np.random.default_rng(sum(sizes))
     graphs = []
     for n in sizes:
@@ -572,14 +575,14 @@ def test_batched_counts_when_the_batch_ends_on_a_block_boundary(sizes):
         edges += [(int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(n // 3)]
         graphs.append(gen.from_edges(n, [(a, b) for a, b in edges if a != b]))
     u = gen.unite(graphs)
-    assert u.n % 256 == 0 or len(sizes) == 2
+    assert u.n % 256 == 0 or len(sizes) == 2 or sizes[-1] == 100
     vb = torch.from_numpy(u.vbegin).to(DEV)
     off, adj = to_dev(u)
     ws = alloc_workspace(u.n, u.num_arcs, len(graphs), DEV)
     for fill in (0x7F, 0x00, 0xFF):
         ws.fill_(fill)
-        note(f"batch ending on a block boundary: sizes {sizes}, n={u.n}, workspace fill {fill:#x}")
-        r = solve_batched(vb, off, adj, workspace=ws)
+        note(f"batch ending on a block boundary: sizes {sizes}, n={u.n}, workspace fill {fill:#x}, flags {flags:#x}")
+        r = solve_batched(vb, off, adj, workspace=ws, flags=flags)
         lab, ap, nb = r.edge_label.cpu().numpy(), r.is_ap.cpu().numpy(), r.num_bcc.cpu().numpy()
         for i, g in enumerate(graphs):
             a0, a1 = u.offsets[u.vbegin[i]], u.offsets[u.vbegin[i + 1]]
