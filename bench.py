@@ -112,18 +112,18 @@ def random_accesses(kernel, n, A, deg=None, flags=0):
 # device copy gives the same counters (known bytes / counter).  Valid only for
 # the kernel sources and the flags they were taken with; otherwise traffic = null.
 COUNTERS = {
-    "src_sha": "3b2bf07c079764bd",
+    "src_sha": "4bba8af2921599d8",
     "workload": "rmat25",
     "flags": 0x2B32506,
     "copy_factor": {"fetch": 2.0, "write": 1.0},
-    "k_bcc_rows": {"fetch_kib": 378485.8, "write_kib": 4090678.7},
-    "k_tag_sample": {"fetch_kib": 2381264.7, "write_kib": 1445325.7},
-    "k_cc_sample": {"fetch_kib": 2296317.7, "write_kib": 635973.3},
-    "k_lr_walk": {"fetch_kib": 1409439.6, "write_kib": 1063863.8},
-    "k_rmq_query": {"fetch_kib": 871215.9, "write_kib": 67797.6},
-    "k_tree_link": {"fetch_kib": 579204.3, "write_kib": 830753.4},
-    "k_mirror_find": {"fetch_kib": 2068323.6, "write_kib": 312027.7},
-    "k_lcc_tree": {"fetch_kib": 863204.7, "write_kib": 296596.4},
+    "k_bcc_rows": {"fetch_kib": 378484.7, "write_kib": 4090690.0},
+    "k_tag_sample": {"fetch_kib": 2381041.1, "write_kib": 1445290.3},
+    "k_cc_sample": {"fetch_kib": 2296379.6, "write_kib": 636608.3},
+    "k_lr_walk": {"fetch_kib": 1410318.8, "write_kib": 1064381.6},
+    "k_rmq_query": {"fetch_kib": 871129.3, "write_kib": 67782.6},
+    "k_tree_link": {"fetch_kib": 578806.1, "write_kib": 830754.0},
+    "k_mirror_find": {"fetch_kib": 2068277.0, "write_kib": 312027.7},
+    "k_lcc_tree": {"fetch_kib": 862361.0, "write_kib": 297084.8},
 }
 
 
