@@ -83,3 +83,17 @@ def test_latency_summary():
     srv, _ = server()
     s = latency_summary(srv.run(reqs))
     assert 0 < s["p50_ms"] <= s["p99_ms"] and s["graphs_per_s"] > 0
+
+
+def test_serving_flags_are_the_serving_slot_pick():
+    """Serving slots run their own shipped pick (a batch of a few large
+    requests), not the 4096-graph batch's, whose per-graph passes give each
+    graph one workgroup; and under the general input contract (no promises)."""
+    from paper_2301_01356_amd import _native as N
+    from paper_2301_01356_amd import tune
+    from paper_2301_01356_amd.serve import serving_flags
+
+    entries = tune.shipped_entries()
+    assert serving_flags() == entries["serve8"][0]
+    assert entries["serve8"][1]["tuned_on"] == "serve8"
+    assert serving_flags() & (N.FLAG_SORTED_ROWS | N.FLAG_NO_SELF_LOOPS | N.FLAG_VALIDATE) == 0
