@@ -1,6 +1,6 @@
 """Autotuner for the solve's tuning fields.
 
-The C ABI exposes twelve speed-only knobs in its flags word (they never change
+The C ABI exposes speed-only knobs in its flags word (they never change
 results; a GPU test checks that): the list-ranking ruler spacing, the number
 of union-find sampling rounds before the full connectivity sweep (0 turns
 sampling off), the First-CC union-find variant (hook by id or by hashed
@@ -10,7 +10,8 @@ sampled-and-certified tags (and how many samples), an atomic-free first
 sampling round, Last-CC's hooking rule and sampling rounds, the arc-tile
 size (64-arc windows per wave, i.e. work per wave), the block size of the
 hot per-vertex kernels, whether First-CC's sets are flattened after the
-atomic-free round, and whether per-vertex launches are ordered by XCD.  The tuner times candidates by
+atomic-free round, whether per-vertex and tour launches are ordered by XCD,
+and (batches only) whether First-CC and Last-CC run graph by graph.  The tuner times candidates by
 coordinate descent on the real input, from the fastest of a few seed
 configurations, settles near-ties by a run-off, and keeps the winner per
 (GPU arch, size bucket, degree-skew class) in a JSON cache.
