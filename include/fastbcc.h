@@ -124,9 +124,10 @@ typedef enum fastbcc_status {
  *   bit  31    batches only (fastbcc_solve_batched): First-CC and Last-CC
  *              per graph, one workgroup per graph running union-find over the
  *              graph's arcs (or its skeleton), parents in LDS for graphs of up
- *              to 2^16 vertices (larger ones in device memory, slowly); for
- *              batches of many graphs, never for few huge ones; ignored by
- *              single-graph solves */
+ *              to 2^16 vertices (larger ones in device memory, slowly),
+ *              graphs taken largest first when there are no more graphs than
+ *              vertices; for batches of many graphs, never for few huge ones;
+ *              ignored by single-graph solves */
 #define FASTBCC_TUNE_RULER_SHIFT 8
 #define FASTBCC_TUNE_SAMPLE_SHIFT 12
 #define FASTBCC_TUNE_TILE_SHIFT 14
